@@ -1,0 +1,25 @@
+"""MI355X (gfx950) library for the Vecchia / VIF approximate negative
+log-likelihood of non-separable space-time Gaussian processes (arXiv 2602.03609).
+
+The compute path is the HIP library libvif.so (C ABI in include/vif.h); this
+package holds its build script and a thin ctypes binding with the same names.
+"""
+from ._lib import (  # noqa: F401
+    VifError,
+    VIF_KERNEL_GNEITING,
+    VIF_KERNEL_GNEITING_MATERN,
+    VIF_KERNEL_MATERN_ANISO,
+    VIF_OP_FACTOR,
+    VIF_OP_NEIGHBORS,
+    VIF_OP_NLL,
+    VIF_PREC_BF16X3,
+    VIF_PREC_FP32,
+    VIF_PREC_FP64,
+    load,
+    release_workspaces,
+    vif_factor,
+    vif_neighbors,
+    vif_nll,
+    vif_nll_terms,
+    vif_workspace_bytes,
+)

@@ -1,0 +1,231 @@
+"""ctypes binding of libvif.so (the C ABI in include/vif.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI. Tensors must be CUDA (HIP) tensors on one device;
+PyTorch provides the device memory and the stream. There is no CPU fallback:
+if the library or a GPU is missing, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libvif.so")
+
+VIF_OK, VIF_E_ARG, VIF_E_NOT_PD, VIF_E_DEVICE, VIF_E_WORKSPACE, VIF_E_UNSUPPORTED = range(6)
+VIF_KERNEL_GNEITING, VIF_KERNEL_GNEITING_MATERN, VIF_KERNEL_MATERN_ANISO = 1, 2, 3
+VIF_PREC_FP64, VIF_PREC_FP32, VIF_PREC_BF16X3 = 0, 1, 2
+VIF_OP_NEIGHBORS, VIF_OP_FACTOR, VIF_OP_NLL = 0, 1, 2
+PREC_NAMES = {"fp64": VIF_PREC_FP64, "fp32": VIF_PREC_FP32, "bf16x3": VIF_PREC_BF16X3}
+
+EXPORTS = ("vif_workspace_bytes", "vif_neighbors", "vif_factor", "vif_nll", "vif_nll_terms",
+           "vif_last_error")
+
+
+class VifError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"vif error {status}: {message}")
+        self.status = status
+        self.message = message
+
+
+class Kernel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32)] + [
+        (f, ctypes.c_double) for f in ("sigma2", "nugget", "a", "c", "alpha", "beta", "gamma", "tau",
+                                       "nu", "delta", "range_s", "range_t", "jitter")]
+
+
+class Points(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("sx", ctypes.c_void_p), ("sy", ctypes.c_void_p),
+                ("t", ctypes.c_void_p)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load(path=LIB_PATH):
+    """Load libvif.so and declare the C signatures. Raises if it is not built."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is not built; run `python -m paper_2602_03609_amd.build`")
+        lib = ctypes.CDLL(path)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        pP, pK = ctypes.POINTER(Points), ctypes.POINTER(Kernel)
+        pd = ctypes.POINTER(ctypes.c_double)
+        lib.vif_workspace_bytes.argtypes = [i64, i32, i32, i32, i32]
+        lib.vif_workspace_bytes.restype = sz
+        lib.vif_neighbors.argtypes = [pP, pK, i32, vp, vp, sz, vp]
+        lib.vif_neighbors.restype = i32
+        lib.vif_factor.argtypes = [pP, pK, i32, vp, pP, i32, vp, vp, vp, sz, vp]
+        lib.vif_factor.restype = i32
+        lib.vif_nll.argtypes = [pP, vp, pK, i32, vp, pP, i32, pd, vp, sz, vp]
+        lib.vif_nll.restype = i32
+        lib.vif_nll_terms.argtypes = [pP, vp, pK, i32, vp, pP, i32, pd, pd, vp, sz, vp]
+        lib.vif_nll_terms.restype = i32
+        lib.vif_last_error.argtypes = []
+        lib.vif_last_error.restype = ctypes.c_char_p
+        _lib = lib
+        return lib
+
+
+def _check(st):
+    if st != VIF_OK:
+        msg = load().vif_last_error().decode(errors="replace")
+        raise VifError(st, msg)
+
+
+def make_kernel(kern):
+    """vif_kernel from a dict with keys kind, sigma2, nugget, ... (missing keys = 0)."""
+    k = Kernel()
+    k.kind = int(kern["kind"])
+    for f, _ in Kernel._fields_[1:]:
+        setattr(k, f, float(kern.get(f, 0.0)))
+    return k
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(x, dtype, name):
+    torch = _torch()
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if x.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {x.dtype}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return x.data_ptr()
+
+
+def make_points(sx, sy, t, name="points"):
+    torch = _torch()
+    n = sx.shape[0]
+    if sy.shape[0] != n or t.shape[0] != n:
+        raise ValueError(f"{name}: sx, sy, t must have the same length")
+    p = Points()
+    p.n = n
+    p.sx = _dev_ptr(sx, torch.float64, name + ".sx")
+    p.sy = _dev_ptr(sy, torch.float64, name + ".sy")
+    p.t = _dev_ptr(t, torch.float64, name + ".t")
+    return p
+
+
+_ws_cache = {}
+
+
+def workspace(n, m, k, prec, op, device):
+    """Cached caller-owned workspace (a uint8 CUDA tensor) for one operation shape."""
+    torch = _torch()
+    nbytes = vif_workspace_bytes(n, m, k, prec, op)
+    if nbytes == 0:
+        raise VifError(VIF_E_ARG, "invalid workspace request")
+    key = (str(device), op, prec)
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        _ws_cache.pop(key, None)
+        buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
+def release_workspaces():
+    _ws_cache.clear()
+
+
+def _stream(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _prec(prec):
+    return PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
+
+
+def vif_workspace_bytes(n, m, k, prec, op):
+    return int(load().vif_workspace_bytes(int(n), int(m), int(k), _prec(prec), int(op)))
+
+
+def vif_neighbors(sx, sy, t, kern, m, nbr=None, stream=None):
+    """Exact correlation-based neighbors; returns int32 [n, m] (-1 padded)."""
+    torch = _torch()
+    lib = load()
+    n = sx.shape[0]
+    if nbr is None:
+        nbr = torch.empty((n, m), dtype=torch.int32, device=sx.device)
+    p = make_points(sx, sy, t)
+    K = make_kernel(kern)
+    ws = workspace(n, m, 0, 0, VIF_OP_NEIGHBORS, sx.device)
+    _check(lib.vif_neighbors(ctypes.byref(p), ctypes.byref(K), int(m),
+                             _dev_ptr(nbr, torch.int32, "nbr") if m > 0 else None,
+                             ws.data_ptr(), ws.numel(), _stream(stream)))
+    return nbr
+
+
+def _ind(ind):
+    if ind is None:
+        return None, 0
+    zx, zy, zt = ind
+    return make_points(zx, zy, zt, "ind"), int(zx.shape[0])
+
+
+def vif_factor(sx, sy, t, kern, m, nbr, ind=None, prec="fp64", stream=None):
+    """Per-point factor; returns (B [n, m] = -A_i, D [n]) as float64 tensors."""
+    torch = _torch()
+    lib = load()
+    n = sx.shape[0]
+    p = make_points(sx, sy, t)
+    K = make_kernel(kern)
+    ip, k = _ind(ind)
+    B = torch.empty((n, m), dtype=torch.float64, device=sx.device)
+    D = torch.empty(n, dtype=torch.float64, device=sx.device)
+    ws = workspace(n, m, k, _prec(prec), VIF_OP_FACTOR, sx.device)
+    _check(lib.vif_factor(ctypes.byref(p), ctypes.byref(K), int(m),
+                          _dev_ptr(nbr, torch.int32, "nbr") if m > 0 else None,
+                          ctypes.byref(ip) if ip is not None else None, _prec(prec),
+                          B.data_ptr() if m > 0 else None, D.data_ptr(), ws.data_ptr(), ws.numel(),
+                          _stream(stream)))
+    return B, D
+
+
+def vif_nll_terms(sx, sy, t, y, kern, m, nbr, ind=None, prec="fp64", stream=None):
+    """(nll, [sum log D, z'z, log det M, q'M^-1 q])."""
+    torch = _torch()
+    lib = load()
+    n = sx.shape[0]
+    p = make_points(sx, sy, t)
+    K = make_kernel(kern)
+    ip, k = _ind(ind)
+    ws = workspace(n, m, k, _prec(prec), VIF_OP_NLL, sx.device)
+    out = ctypes.c_double(0.0)
+    terms = (ctypes.c_double * 4)()
+    _check(lib.vif_nll_terms(ctypes.byref(p), _dev_ptr(y, torch.float64, "y"), ctypes.byref(K),
+                             int(m), _dev_ptr(nbr, torch.int32, "nbr") if m > 0 else None,
+                             ctypes.byref(ip) if ip is not None else None, _prec(prec),
+                             ctypes.byref(out), terms, ws.data_ptr(), ws.numel(), _stream(stream)))
+    return out.value, list(terms)
+
+
+def vif_nll(sx, sy, t, y, kern, m, nbr, ind=None, prec="fp64", stream=None):
+    """Negative log-likelihood (float)."""
+    torch = _torch()
+    lib = load()
+    n = sx.shape[0]
+    p = make_points(sx, sy, t)
+    K = make_kernel(kern)
+    ip, k = _ind(ind)
+    ws = workspace(n, m, k, _prec(prec), VIF_OP_NLL, sx.device)
+    out = ctypes.c_double(0.0)
+    _check(lib.vif_nll(ctypes.byref(p), _dev_ptr(y, torch.float64, "y"), ctypes.byref(K), int(m),
+                       _dev_ptr(nbr, torch.int32, "nbr") if m > 0 else None,
+                       ctypes.byref(ip) if ip is not None else None, _prec(prec),
+                       ctypes.byref(out), ws.data_ptr(), ws.numel(), _stream(stream)))
+    return out.value

@@ -1,0 +1,473 @@
+// Host side of the C ABI declared in include/vif.h: argument validation,
+// workspace layout, per-lag tables for the neighbor key, launch sequencing and
+// error reporting. No device memory is allocated here.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "vif.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int32_t ok() {
+  g_err.clear();
+  return VIF_OK;
+}
+
+#define HIPCHK(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(VIF_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int kpad_of(int k) { return k > 0 ? ((k + 1 + 63) / 64) * 64 : 0; }
+
+struct Layout {
+  size_t flags = 0, out = 0, part = 0, sums = 0, logD = 0, z = 0, Sk = 0, P = 0, U = 0, W = 0,
+         syrk = 0, M = 0, q = 0, dscr = 0, slab = 0, tab1 = 0, tab2 = 0, bnd = 0, total = 0;
+  int kpad = 0, splits = 0;
+};
+
+// Flags block: [0] fail_points, [1] fail_sigma_k, [2] fail_M, [3] bad_nbr (uint64 each),
+// [4] time flags (uint32).
+constexpr size_t kFlagBytes = 256;
+
+Layout make_layout(int64_t n, int m, int k, int prec, int op) {
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off += align256(bytes);
+    return at;
+  };
+  const size_t es = prec == VIF_PREC_FP64 ? 8 : 4;
+  L.flags = take(kFlagBytes);
+  if (op == VIF_OP_NEIGHBORS) {
+    L.slab = take(sizeof(int32_t) * (VIF_MAX_LAGS + 2));
+    L.tab1 = take(sizeof(double) * VIF_MAX_LAGS);
+    L.tab2 = take(sizeof(double) * VIF_MAX_LAGS);
+    L.bnd = take(sizeof(double) * VIF_MAX_LAGS);
+    L.total = off;
+    return L;
+  }
+  (void)m;
+  L.out = take(sizeof(double) * 8);
+  L.part = take(sizeof(double) * 256);
+  L.sums = take(sizeof(double) * 8);
+  if (op == VIF_OP_NLL) {
+    L.logD = take(sizeof(double) * (size_t)n);
+    if (k == 0) L.z = take(sizeof(double) * (size_t)n);
+  }
+  if (k > 0) {
+    L.kpad = kpad_of(k);
+    const size_t kk = (size_t)L.kpad * L.kpad;
+    L.Sk = take(sizeof(double) * kk);
+    L.P = take(sizeof(double) * kk);
+    L.dscr = take(sizeof(double) * 64 * 64);
+    L.U = take(es * (size_t)n * L.kpad);
+    if (op == VIF_OP_NLL) {
+      L.W = take(es * (size_t)n * L.kpad);
+      L.splits = vif::syrk_splits(n, L.kpad);
+      const int nt = L.kpad / 64;
+      L.syrk = take(sizeof(double) * (size_t)L.splits * (nt * (nt + 1) / 2) * 64 * 64);
+      L.M = take(sizeof(double) * kk);
+      L.q = take(sizeof(double) * L.kpad);
+    }
+  }
+  L.total = off;
+  return L;
+}
+
+bool finite(double x) { return isfinite(x); }
+
+int nu_code(double nu) {
+  if (nu == 0.5) return 0;
+  if (nu == 1.5) return 1;
+  if (nu == 2.5) return 2;
+  return -1;
+}
+
+int32_t check_kernel(const vif_kernel* K) {
+  if (!K) return fail(VIF_E_ARG, "kern is NULL");
+  if (!finite(K->sigma2) || !(K->sigma2 > 0)) return fail(VIF_E_ARG, "sigma2 must be finite and > 0");
+  if (!finite(K->nugget) || K->nugget < 0) return fail(VIF_E_ARG, "nugget must be finite and >= 0");
+  if (!finite(K->jitter) || K->jitter < 0) return fail(VIF_E_ARG, "jitter must be finite and >= 0");
+  switch (K->kind) {
+    case VIF_KERNEL_GNEITING:
+      if (!finite(K->a) || !(K->a > 0)) return fail(VIF_E_ARG, "a must be > 0");
+      if (!finite(K->c) || !(K->c > 0)) return fail(VIF_E_ARG, "c must be > 0");
+      if (!(K->alpha > 0 && K->alpha <= 1)) return fail(VIF_E_ARG, "alpha must be in (0,1]");
+      if (!(K->gamma > 0 && K->gamma <= 1)) return fail(VIF_E_ARG, "gamma must be in (0,1]");
+      if (!(K->beta >= 0 && K->beta <= 1)) return fail(VIF_E_ARG, "beta must be in [0,1]");
+      if (!finite(K->tau) || K->tau < 0) return fail(VIF_E_ARG, "tau must be >= 0");
+      return VIF_OK;
+    case VIF_KERNEL_GNEITING_MATERN:
+      if (!finite(K->a) || !(K->a > 0)) return fail(VIF_E_ARG, "a must be > 0");
+      if (!finite(K->c) || !(K->c > 0)) return fail(VIF_E_ARG, "c must be > 0");
+      if (!(K->alpha > 0 && K->alpha <= 1)) return fail(VIF_E_ARG, "alpha must be in (0,1]");
+      if (!(K->gamma >= 0 && K->gamma <= 1)) return fail(VIF_E_ARG, "gamma must be in [0,1]");
+      if (!finite(K->delta) || K->delta < 0) return fail(VIF_E_ARG, "delta must be >= 0");
+      if (nu_code(K->nu) < 0)
+        return fail(VIF_E_UNSUPPORTED, "nu must be 0.5, 1.5 or 2.5 (closed forms only)");
+      return VIF_OK;
+    case VIF_KERNEL_MATERN_ANISO:
+      if (!finite(K->range_s) || !(K->range_s > 0)) return fail(VIF_E_ARG, "range_s must be > 0");
+      if (!finite(K->range_t) || !(K->range_t > 0)) return fail(VIF_E_ARG, "range_t must be > 0");
+      if (nu_code(K->nu) < 0)
+        return fail(VIF_E_UNSUPPORTED, "nu must be 0.5, 1.5 or 2.5 (closed forms only)");
+      return VIF_OK;
+    default:
+      return fail(VIF_E_ARG, "unknown kernel kind %d", (int)K->kind);
+  }
+}
+
+vif::KernDev to_dev(const vif_kernel* K) {
+  vif::KernDev d{};
+  d.kind = K->kind;
+  d.nu_code = (K->kind == VIF_KERNEL_GNEITING) ? 0 : nu_code(K->nu);
+  d.gamma_half = (K->kind == VIF_KERNEL_GNEITING && K->gamma == 0.5) ? 1 : 0;
+  d.sigma2 = K->sigma2;
+  d.nugget = K->nugget;
+  d.a = K->a;
+  d.c = K->c;
+  d.two_alpha = 2.0 * K->alpha;
+  d.tau = K->tau;
+  d.bg = K->beta * K->gamma;
+  d.gamma = K->gamma;
+  d.half_gamma = K->gamma / 2.0;
+  d.dpg = K->delta + K->gamma;
+  if (K->kind == VIF_KERNEL_MATERN_ANISO) {
+    d.ir_s2 = 1.0 / (K->range_s * K->range_s);
+    d.ir_t2 = 1.0 / (K->range_t * K->range_t);
+  }
+  return d;
+}
+
+int32_t check_points(const vif_points* p, const char* what) {
+  if (!p) return fail(VIF_E_ARG, "%s is NULL", what);
+  if (p->n < 0 || p->n >= (int64_t)INT32_MAX) return fail(VIF_E_ARG, "%s->n out of range", what);
+  if (p->n > 0 && (!p->sx || !p->sy || !p->t)) return fail(VIF_E_ARG, "%s has NULL arrays", what);
+  return VIF_OK;
+}
+
+int32_t check_common(const vif_points* p, const vif_kernel* kern, int32_t m, void* ws,
+                     size_t ws_bytes, size_t need) {
+  int32_t st = check_points(p, "points");
+  if (st) return st;
+  if (p->n < 1) return fail(VIF_E_ARG, "n must be >= 1");
+  st = check_kernel(kern);
+  if (st) return st;
+  if (m < 0) return fail(VIF_E_ARG, "m must be >= 0");
+  if (m > VIF_MAX_M) return fail(VIF_E_UNSUPPORTED, "m = %d exceeds VIF_MAX_M = %d", m, VIF_MAX_M);
+  if (!ws) return fail(VIF_E_ARG, "workspace is NULL");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(VIF_E_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < need)
+    return fail(VIF_E_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  return VIF_OK;
+}
+
+struct Flags {
+  unsigned long long fail_pts, fail_sk, fail_m, bad_nbr;
+  uint32_t tflag, pad;
+};
+
+int32_t init_flags(char* ws, const Layout& L, hipStream_t s) {
+  HIPCHK(vif::launch_init_flags(ws + L.flags, s));
+  return VIF_OK;
+}
+
+int32_t read_flags(char* ws, const Layout& L, Flags* f, double* out, int nout, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(f, ws + L.flags, sizeof(Flags), hipMemcpyDeviceToHost, s));
+  if (nout > 0) HIPCHK(hipMemcpyAsync(out, ws + L.out, sizeof(double) * nout, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return VIF_OK;
+}
+
+int32_t report_flags(const Flags& f) {
+  if (f.bad_nbr != ~0ull)
+    return fail(VIF_E_ARG, "neighbor row %llu has an index that is not an earlier point, or -1 padding before a valid entry",
+                f.bad_nbr);
+  if (f.fail_sk != ~0ull)
+    return fail(VIF_E_NOT_PD, "Sigma_k (inducing-point covariance) is not positive definite at row %llu", f.fail_sk);
+  if (f.fail_pts != ~0ull)
+    return fail(VIF_E_NOT_PD, "conditioning block of point %llu is not positive definite", f.fail_pts);
+  if (f.fail_m != ~0ull)
+    return fail(VIF_E_NOT_PD, "Woodbury matrix M is not positive definite at row %llu", f.fail_m);
+  return VIF_OK;
+}
+
+// Sigma_k, its Cholesky factor and inverse, then U = C(X,Z) L_k^-T.
+int32_t run_lowrank(const vif_points* p, const vif_points* ind, const vif_kernel* kern, int prec,
+                    char* ws, const Layout& L, hipStream_t s) {
+  vif::LowRankArgs a{};
+  a.n = p->n;
+  a.k = (int)ind->n;
+  a.kpad = L.kpad;
+  a.K = to_dev(kern);
+  a.jitter = kern->jitter;
+  a.sx = p->sx; a.sy = p->sy; a.t = p->t;
+  a.zx = ind->sx; a.zy = ind->sy; a.zt = ind->t;
+  double* Sk = reinterpret_cast<double*>(ws + L.Sk);
+  double* P = reinterpret_cast<double*>(ws + L.P);
+  auto* fl = reinterpret_cast<unsigned long long*>(ws + L.flags);
+  HIPCHK(vif::launch_cov_kk(a, Sk, s));
+  HIPCHK(vif::launch_cholesky(L.kpad, Sk, reinterpret_cast<double*>(ws + L.dscr), fl + 1, s));
+  HIPCHK(vif::launch_trinv(L.kpad, Sk, P, s));
+  HIPCHK(vif::launch_lowrank_u(a, P, ws + L.U, prec, nullptr, s));
+  return VIF_OK;
+}
+
+int32_t check_ind(const vif_points* ind, int* k) {
+  *k = 0;
+  if (!ind) return VIF_OK;
+  int32_t st = check_points(ind, "ind");
+  if (st) return st;
+  if (ind->n > VIF_MAX_K) return fail(VIF_E_UNSUPPORTED, "k = %lld exceeds VIF_MAX_K = %d", (long long)ind->n, VIF_MAX_K);
+  *k = (int)ind->n;
+  return VIF_OK;
+}
+
+int32_t nll_impl(const vif_points* p, const double* y, const vif_kernel* kern, int32_t m,
+                 const int32_t* nbr, const vif_points* ind, int32_t prec, double* nll,
+                 double* terms, void* wsv, size_t ws_bytes, void* hip_stream) {
+  int k = 0;
+  int32_t st = check_ind(ind, &k);
+  if (st) return st;
+  if (prec < VIF_PREC_FP64 || prec > VIF_PREC_BF16X3) return fail(VIF_E_ARG, "unknown precision %d", prec);
+  if (!p) return fail(VIF_E_ARG, "points is NULL");
+  const Layout L = make_layout(p->n, m, k, prec, VIF_OP_NLL);
+  st = check_common(p, kern, m, wsv, ws_bytes, L.total);
+  if (st) return st;
+  if (!y) return fail(VIF_E_ARG, "y is NULL");
+  if (m > 0 && !nbr) return fail(VIF_E_ARG, "nbr is NULL");
+  if (!nll) return fail(VIF_E_ARG, "nll is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  char* ws = reinterpret_cast<char*>(wsv);
+  auto* fl = reinterpret_cast<unsigned long long*>(ws + L.flags);
+  double* sums = reinterpret_cast<double*>(ws + L.sums);
+  double* part = reinterpret_cast<double*>(ws + L.part);
+  double* out = reinterpret_cast<double*>(ws + L.out);
+  if ((st = init_flags(ws, L, s))) return st;
+
+  vif::FactorArgs fa{};
+  fa.n = p->n;
+  fa.m = m;
+  fa.k = k;
+  fa.ldu = L.kpad;
+  fa.K = to_dev(kern);
+  fa.sx = p->sx; fa.sy = p->sy; fa.t = p->t; fa.y = y;
+  fa.nbr = nbr;
+  fa.logD = reinterpret_cast<double*>(ws + L.logD);
+  fa.fail = fl;
+  fa.bad_nbr = fl + 3;
+  if (k > 0) {
+    if ((st = run_lowrank(p, ind, kern, prec, ws, L, s))) return st;
+    fa.U = ws + L.U;
+    fa.W = ws + L.W;
+    HIPCHK(vif::launch_point_factor(fa, 0, prec, s));
+    double* syrk = reinterpret_cast<double*>(ws + L.syrk);
+    double* M = reinterpret_cast<double*>(ws + L.M);
+    double* q = reinterpret_cast<double*>(ws + L.q);
+    HIPCHK(vif::launch_syrk(p->n, L.kpad, ws + L.W, prec, syrk, L.splits, s));
+    HIPCHK(vif::launch_syrk_reduce(k, L.kpad, syrk, L.splits, M, q, sums + 1, s));
+    HIPCHK(vif::launch_cholesky(L.kpad, M, reinterpret_cast<double*>(ws + L.dscr), fl + 2, s));
+    HIPCHK(vif::launch_sum(p->n, fa.logD, 0, part, sums + 0, s));
+    HIPCHK(vif::launch_finalize(p->n, k, L.kpad, M, q, sums + 0, sums + 1, out, s));
+  } else {
+    fa.z = reinterpret_cast<double*>(ws + L.z);
+    HIPCHK(vif::launch_point_factor(fa, 0, prec, s));
+    HIPCHK(vif::launch_sum(p->n, fa.logD, 0, part, sums + 0, s));
+    HIPCHK(vif::launch_sum(p->n, fa.z, 1, part, sums + 1, s));
+    HIPCHK(vif::launch_finalize(p->n, 0, 0, nullptr, nullptr, sums + 0, sums + 1, out, s));
+  }
+  Flags f;
+  double h[5];
+  if ((st = read_flags(ws, L, &f, h, 5, s))) return st;
+  if ((st = report_flags(f))) return st;
+  *nll = h[0];
+  if (terms) {
+    terms[0] = h[1];
+    terms[1] = h[2];
+    terms[2] = h[3];
+    terms[3] = h[4];
+  }
+  return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t vif_workspace_bytes(int64_t n, int32_t m, int32_t k, int32_t prec, int32_t op) {
+  if (n < 1 || m < 0 || m > VIF_MAX_M || k < 0 || k > VIF_MAX_K) return 0;
+  if (prec < VIF_PREC_FP64 || prec > VIF_PREC_BF16X3) return 0;
+  if (op < VIF_OP_NEIGHBORS || op > VIF_OP_NLL) return 0;
+  return make_layout(n, m, k, prec, op).total;
+}
+
+const char* vif_last_error(void) { return g_err.c_str(); }
+
+int32_t vif_neighbors(const vif_points* p, const vif_kernel* kern, int32_t m, int32_t* nbr,
+                      void* wsv, size_t ws_bytes, void* hip_stream) {
+  if (!p) return fail(VIF_E_ARG, "points is NULL");
+  const Layout L = make_layout(p->n, m, 0, VIF_PREC_FP64, VIF_OP_NEIGHBORS);
+  int32_t st = check_common(p, kern, m, wsv, ws_bytes, L.total);
+  if (st) return st;
+  if (m > 0 && !nbr) return fail(VIF_E_ARG, "nbr is NULL");
+  if (m == 0) return ok();
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  char* ws = reinterpret_cast<char*>(wsv);
+  if ((st = init_flags(ws, L, s))) return st;
+  Flags* dflags = reinterpret_cast<Flags*>(ws + L.flags);
+  HIPCHK(vif::launch_validate_times(p->n, p->t, &dflags->tflag, s));
+  Flags f;
+  double tt[2];
+  HIPCHK(hipMemcpyAsync(&f, ws + L.flags, sizeof(f), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&tt[0], p->t, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&tt[1], p->t + (p->n - 1), sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (f.tflag & 1u) return fail(VIF_E_ARG, "times must be finite");
+  if (f.tflag & 2u) return fail(VIF_E_UNSUPPORTED, "neighbor search requires integer-valued times");
+  if (f.tflag & 4u) return fail(VIF_E_ARG, "times must be nondecreasing in index");
+  const double span = tt[1] - tt[0];
+  if (!(span >= 0) || span >= (double)VIF_MAX_LAGS)
+    return fail(VIF_E_UNSUPPORTED, "time span %g exceeds VIF_MAX_LAGS - 1", span);
+  const int Lmax = (int)span;
+
+  // Per-lag factors from the host C math library, in the operation order the
+  // ranking key specifies; bnd is the suffix maximum of -tab1.
+  std::vector<double> tab((size_t)3 * (Lmax + 1), 0.0);
+  double* tab1 = tab.data();
+  double* tab2 = tab1 + (Lmax + 1);
+  double* bnd = tab2 + (Lmax + 1);
+  int mode;
+  const vif::KernDev kd = to_dev(kern);
+  if (kern->kind == VIF_KERNEL_MATERN_ANISO) {
+    mode = 1;
+    const double ir_t = 1.0 / kern->range_t;
+    for (int l = 0; l <= Lmax; ++l) {
+      const double w = (double)l * ir_t;
+      tab1[l] = w * w;
+    }
+  } else {
+    const double two_alpha = 2.0 * kern->alpha;
+    for (int l = 0; l <= Lmax; ++l) {
+      const double pw = pow((double)l, two_alpha);
+      const double psi = kern->a * pw + 1.0;
+      if (kern->kind == VIF_KERNEL_GNEITING) {
+        tab1[l] = kern->tau * log(psi);
+        tab2[l] = kern->c * pow(psi, -(kern->beta * kern->gamma));
+      } else {
+        tab1[l] = (kern->delta + kern->gamma) * log(psi);
+        tab2[l] = kern->c * pow(psi, -(kern->gamma / 2.0));
+      }
+    }
+    if (kern->kind == VIF_KERNEL_GNEITING)
+      mode = kern->gamma == 0.5 ? 0 : 2;
+    else
+      mode = kd.nu_code == 0 ? 0 : 3;
+  }
+  double run = -INFINITY;
+  for (int l = Lmax; l >= 0; --l) {
+    const double b = -tab1[l];
+    run = b > run ? b : run;
+    bnd[l] = run;
+  }
+  HIPCHK(hipMemcpyAsync(ws + L.tab1, tab1, sizeof(double) * (Lmax + 1), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ws + L.tab2, tab2, sizeof(double) * (Lmax + 1), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ws + L.bnd, bnd, sizeof(double) * (Lmax + 1), hipMemcpyHostToDevice, s));
+  int32_t* slab = reinterpret_cast<int32_t*>(ws + L.slab);
+  HIPCHK(vif::launch_slab_start(p->n, p->t, tt[0], Lmax, slab, s));
+  vif::NbrArgs a{};
+  a.n = p->n;
+  a.m = m;
+  a.mode = mode;
+  a.nu_code = kd.nu_code;
+  a.ir_s = kern->kind == VIF_KERNEL_MATERN_ANISO ? 1.0 / kern->range_s : 0.0;
+  a.gamma = kern->gamma;
+  a.t0 = tt[0];
+  a.sx = p->sx; a.sy = p->sy; a.t = p->t;
+  a.slab_start = slab;
+  a.tab1 = reinterpret_cast<const double*>(ws + L.tab1);
+  a.tab2 = reinterpret_cast<const double*>(ws + L.tab2);
+  a.bnd = reinterpret_cast<const double*>(ws + L.bnd);
+  a.nbr = nbr;
+  HIPCHK(vif::launch_neighbors(a, s));
+  // The host tables must outlive the copies above.
+  HIPCHK(hipStreamSynchronize(s));
+  return ok();
+}
+
+int32_t vif_factor(const vif_points* p, const vif_kernel* kern, int32_t m, const int32_t* nbr,
+                   const vif_points* ind, int32_t prec, double* B, double* D, void* wsv,
+                   size_t ws_bytes, void* hip_stream) {
+  int k = 0;
+  int32_t st = check_ind(ind, &k);
+  if (st) return st;
+  if (prec < VIF_PREC_FP64 || prec > VIF_PREC_BF16X3) return fail(VIF_E_ARG, "unknown precision %d", prec);
+  if (!p) return fail(VIF_E_ARG, "points is NULL");
+  const Layout L = make_layout(p->n, m, k, prec, VIF_OP_FACTOR);
+  st = check_common(p, kern, m, wsv, ws_bytes, L.total);
+  if (st) return st;
+  if (m > 0 && (!nbr || !B)) return fail(VIF_E_ARG, "nbr or B is NULL");
+  if (!D) return fail(VIF_E_ARG, "D is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  char* ws = reinterpret_cast<char*>(wsv);
+  auto* fl = reinterpret_cast<unsigned long long*>(ws + L.flags);
+  if ((st = init_flags(ws, L, s))) return st;
+  vif::FactorArgs fa{};
+  fa.n = p->n;
+  fa.m = m;
+  fa.k = k;
+  fa.ldu = L.kpad;
+  fa.K = to_dev(kern);
+  fa.sx = p->sx; fa.sy = p->sy; fa.t = p->t; fa.y = nullptr;
+  fa.nbr = nbr;
+  fa.B = B;
+  fa.D = D;
+  fa.fail = fl;
+  fa.bad_nbr = fl + 3;
+  if (k > 0) {
+    if ((st = run_lowrank(p, ind, kern, prec, ws, L, s))) return st;
+    fa.U = ws + L.U;
+  }
+  HIPCHK(vif::launch_point_factor(fa, 1, prec, s));
+  Flags f;
+  if ((st = read_flags(ws, L, &f, nullptr, 0, s))) return st;
+  if ((st = report_flags(f))) return st;
+  return ok();
+}
+
+int32_t vif_nll(const vif_points* p, const double* y, const vif_kernel* kern, int32_t m,
+                const int32_t* nbr, const vif_points* ind, int32_t prec, double* nll, void* ws,
+                size_t ws_bytes, void* hip_stream) {
+  return nll_impl(p, y, kern, m, nbr, ind, prec, nll, nullptr, ws, ws_bytes, hip_stream);
+}
+
+int32_t vif_nll_terms(const vif_points* p, const double* y, const vif_kernel* kern, int32_t m,
+                      const int32_t* nbr, const vif_points* ind, int32_t prec, double* nll,
+                      double* terms, void* ws, size_t ws_bytes, void* hip_stream) {
+  return nll_impl(p, y, kern, m, nbr, ind, prec, nll, terms, ws, ws_bytes, hip_stream);
+}
+
+}  // extern "C"

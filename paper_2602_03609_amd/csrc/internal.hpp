@@ -1,0 +1,93 @@
+// Internal launch interface between the host C ABI (api.cpp) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace vif {
+
+// ---- neighbor search --------------------------------------------------------
+// Key modes: 0 = -(tab1 + sqrt(h2)*tab2) (GNEITING gamma=1/2, GNEITING_MATERN nu=1/2)
+//            1 = -(tab1 + (u*u + v*v))     (MATERN_ANISO, u = dx/range_s)
+//            2 = -(tab1 + h2^gamma*tab2)   (GNEITING, general gamma)
+//            3 = -(tab1 + s(x))            (GNEITING_MATERN nu in {3/2, 5/2})
+struct NbrArgs {
+  int64_t n;
+  int m;
+  int mode;
+  int nu_code;
+  double ir_s, gamma, t0;
+  const double *sx, *sy, *t;
+  const int32_t* slab_start;  // [L+2], slab of time t0+l is [slab_start[l], slab_start[l+1])
+  const double *tab1, *tab2, *bnd;
+  int32_t* nbr;
+};
+
+// Checks finite, integer-valued, nondecreasing times; sets bits in *flag.
+hipError_t launch_validate_times(int64_t n, const double* t, uint32_t* flag, hipStream_t s);
+hipError_t launch_slab_start(int64_t n, const double* t, double t0, int L, int32_t* slab_start,
+                             hipStream_t s);
+hipError_t launch_neighbors(const NbrArgs& a, hipStream_t s);
+
+// ---- per-point factor ---------------------------------------------------------
+struct FactorArgs {
+  int64_t n;
+  int m;
+  int k;    // inducing points (0 = plain Vecchia)
+  int ldu;  // row stride of U and W (elements)
+  KernDev K;
+  const double *sx, *sy, *t, *y;
+  const int32_t* nbr;
+  const void* U;  // [n, ldu], FP64 or FP32 by precision
+  void* W;        // [n, ldu]; column k receives z_i
+  double *B, *D;  // factor outputs
+  double *logD, *z;  // NLL outputs (per point)
+  unsigned long long* fail;     // smallest point index with a non-positive-definite block
+  unsigned long long* bad_nbr;  // smallest point index with an invalid neighbor row
+};
+
+// mode: 0 = NLL terms, 1 = factor (B, D). prec: 0 FP64, 1 FP32, 2 BF16X3.
+hipError_t launch_point_factor(const FactorArgs& a, int mode, int prec, hipStream_t s);
+
+// ---- low-rank part ----------------------------------------------------------
+struct LowRankArgs {
+  int64_t n;
+  int k, kpad;
+  KernDev K;
+  double jitter;
+  const double *sx, *sy, *t;     // data points
+  const double *zx, *zy, *zt;    // inducing points
+};
+
+// S = C(Z,Z) + jitter I on the leading k x k block, identity on the padding.
+hipError_t launch_cov_kk(const LowRankArgs& a, double* S, hipStream_t s);
+// In-place lower Cholesky of an N x N FP64 matrix (N multiple of 64; upper part of
+// the diagonal blocks zeroed, other upper blocks untouched). scratch: 64*64 doubles.
+hipError_t launch_cholesky(int N, double* A, double* scratch, unsigned long long* fail,
+                           hipStream_t s);
+// P = L^-1 for lower-triangular L (N x N, N multiple of 64); upper part of P set to 0.
+hipError_t launch_trinv(int N, const double* L, double* P, hipStream_t s);
+// U[i, :] = C(x_i, Z) P^T, U stored [n, kpad], FP64 (prec 0) or FP32 (prec 1, 2).
+hipError_t launch_lowrank_u(const LowRankArgs& a, const double* P, void* U, int prec,
+                            void* scratch, hipStream_t s);
+// Partial Gram of W over row chunks: part[s][tile] = sum over rows of chunk s of W_I' W_J.
+int syrk_splits(int64_t n, int kpad);
+hipError_t launch_syrk(int64_t n, int kpad, const void* W, int prec, double* part, int splits,
+                       hipStream_t s);
+// M = I + (sum_s part[s])[0:k,0:k] with identity padding; q = column k; zz = entry (k,k).
+hipError_t launch_syrk_reduce(int k, int kpad, const double* part, int splits, double* M,
+                              double* q, double* zz, hipStream_t s);
+
+// ---- reductions and final assembly ------------------------------------------
+// flags[0..3] = ~0 (no failure recorded), flags[4] = 0 (time checks).
+hipError_t launch_init_flags(void* flags, hipStream_t s);
+// Deterministic sum of x[0..n) into *out (two-level tree, fixed order). partial: [256] scratch.
+hipError_t launch_sum(int64_t n, const double* x, int squared, double* partial, double* out,
+                      hipStream_t s);
+// out[0] = nll, out[1..4] = terms; uses logdet/quad from the Cholesky of M when k > 0.
+hipError_t launch_finalize(int64_t n, int k, int kpad, const double* LM, const double* q,
+                           const double* sum_logD, const double* zz, double* out, hipStream_t s);
+
+}  // namespace vif
