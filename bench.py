@@ -1,0 +1,268 @@
+#!/usr/bin/env python3
+"""Benchmark of the Vecchia/VIF likelihood hot path on one MI355X.
+
+One step = one exact correlation-based neighbor search plus one VIF negative
+log-likelihood evaluation (low-rank U, per-point residual factor, Woodbury
+assembly) over a synthetic continental station network: 3340 stations drawn
+from a 40-component Gaussian mixture over the contiguous US, 365 days, 10 %
+missing at random (n ~ 1.1M), m = 30 neighbors, k = 1000 kMeans++ inducing
+points, Gneiting kernel. Inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line on stdout (progress goes to stderr).
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--prec bf16x6]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "VIF NLL evals/s + neighbor-search pts/s at n=1.1M,m=30,k=1000 vs FP64"
+
+# Published MI355X peaks used for the roofline fractions.
+PEAK = {"hbm_GBs": 8000.0, "bf16_TFs": 2500.0, "fp32_TFs": 157.3, "fp64_TFs": 78.6}
+PREC_ES = {"fp64": 8, "fp32": 4, "bf16x3": 4, "bf16x6": 4}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prec", default="bf16x6", choices=list(PREC_ES))
+    ap.add_argument("--stations", type=int, default=3340)
+    ap.add_argument("--days", type=int, default=365)
+    ap.add_argument("--k", type=int, default=1000)
+    ap.add_argument("--m", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-check", action="store_true")
+    return ap.parse_args()
+
+
+def stage_work(n, m, k, kpad, es):
+    """Algorithmic flops and HBM bytes per launch of each timed stage."""
+    q = m + 1
+    return {
+        # exact key evaluations are counted from the kernel's own scan; bytes: coordinates in,
+        # neighbor rows out
+        "neighbors": {"bytes": n * (3 * 8 + 4 * m), "flops": None},
+        "crosscov": {"bytes": n * kpad * es, "flops": None},
+        # U = C L_k^-T, triangular: sum_j 2(j+1) flops per row; U read and written once
+        "trmm": {"bytes": 2 * n * kpad * es + kpad * kpad * 8, "flops": n * k * (k + 1)},
+        # Gram of the q gathered rows (lower triangle incl. diagonal) + W row; U read once
+        # (cache-ideal gathers), W written, nbr/coords/y in, logD out
+        "point_factor": {"bytes": 2 * n * kpad * es + n * (4 * m + 4 * 8 + 8),
+                         "flops": n * (q * (q + 1) // 2 * 2 * k + 2 * q * k)},
+        # [W z]'[W z], lower triangle incl. diagonal
+        "syrk": {"bytes": n * kpad * es, "flops": n * (k + 1) * (k + 2)},
+    }
+
+
+def mfma_peak(prec):
+    if prec == "fp64":
+        return PEAK["fp64_TFs"]
+    if prec == "fp32":
+        return PEAK["fp32_TFs"]
+    return PEAK["bf16_TFs"]
+
+
+def cpu_baseline(d, m, budget_s=20.0):
+    """The FP64 oracle, timed on a bounded sample of the same workload."""
+    import numpy as np
+    from oracle import likelihood as LK
+    from oracle import neighbors as NB
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        blas_threads = os.cpu_count()
+    n = d["n"]
+    X = (d["sx"], d["sy"], d["t"])
+    Z = (d["zx"], d["zy"], d["zt"])
+    rng = np.random.default_rng(123)
+    # neighbor search: exact lag-pruned oracle on sampled queries
+    q_rows = rng.choice(n, 400, replace=False)
+    t0 = time.perf_counter()
+    nb_rows = NB.lag_pruned(d["kern"], *X, m, rows=q_rows)
+    t_q = (time.perf_counter() - t0) / q_rows.shape[0]
+    # NLL: L_k once, then per-row work (U rows, per-point factor, W'W) on sampled rows
+    t0 = time.perf_counter()
+    Lk = LK.low_rank_factor(d["kern"], Z)
+    t_lk = time.perf_counter() - t0
+    s_rows = np.sort(rng.choice(np.arange(m, n), 1500, replace=False))
+    nb_s = NB.lag_pruned(d["kern"], *X, m, rows=s_rows)
+    nbr_full = np.full((n, m), -1, dtype=np.int32)
+    nbr_full[s_rows] = nb_s
+    t0 = time.perf_counter()
+    pt = LK.vif_points(d["kern"], X, d["y"], nbr_full, Z, Lk, s_rows, want_w=True)
+    t_pt = (time.perf_counter() - t0) / s_rows.shape[0]
+    W = pt["W"]
+    t0 = time.perf_counter()
+    _ = W.T @ W
+    t_syrk = (time.perf_counter() - t0) / s_rows.shape[0]
+    k = Z[0].shape[0]
+    t0 = time.perf_counter()
+    np.linalg.cholesky(np.eye(k) + _ / s_rows.shape[0])
+    t_chol = time.perf_counter() - t0
+    t_step = n * (t_q + t_pt + t_syrk) + t_lk + t_chol
+    return {
+        "value": 1.0 / t_step,
+        "unit": "evals/s",
+        "cores": int(blas_threads),
+        "kind": "oracle",
+        "sample": (f"FP64 NumPy/SciPy oracle: lag-pruned exact neighbor search on 400 sampled "
+                   f"queries and the VIF per-point factor (U rows by triangular solve, residual "
+                   f"block solves, W rows) plus W'W on 1500 sampled points, scaled to n={n}; "
+                   f"plus L_k and chol(M) once; step = search + NLL = {t_step:.1f} s"),
+        "neighbor_pts_per_s": 1.0 / t_q,
+        "nll_evals_per_s": 1.0 / (n * (t_pt + t_syrk) + t_lk + t_chol),
+    }
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this library has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2602_03609_amd as vif
+
+    if not torch.cuda.is_available():
+        print("no GPU available", file=sys.stderr)
+        sys.exit(1)
+    vif.load()
+    dev = torch.device("cuda:0")
+
+    t0 = time.perf_counter()
+    d = synth.config_cfg3(n_stations=args.stations, n_days=args.days, k=args.k, m=args.m)
+    n, m, k = d["n"], d["m"], d["k"]
+    log(f"generated {d['name']} in {time.perf_counter() - t0:.1f}s")
+
+    def td(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    X = (td(d["sx"]), td(d["sy"]), td(d["t"]))
+    y = td(d["y"])
+    Z = (td(d["zx"]), td(d["zy"]), td(d["zt"]))
+    kern = d["kern"]
+    nbr = torch.empty((n, m), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    def step(prec):
+        vif.vif_neighbors(*X, kern, m, nbr=nbr)
+        return vif.vif_nll(*X, y, kern, m, nbr, ind=Z, prec=prec)
+
+    for w in range(args.warmup):
+        v = step(args.prec)
+        log(f"warmup {w}: nll={v:.10g}")
+    torch.cuda.synchronize()
+
+    vif.vif_profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nll = None
+    for _ in range(args.steps):
+        nll = step(args.prec)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = vif.vif_profile_read()
+    vif.vif_profile(False)
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, nll={nll:.12g}")
+    stage_ms = {s: (tot / c if c else 0.0) for s, (tot, c) in prof.items()}
+    log("stage ms/launch: " + ", ".join(f"{s}={v:.3f}" for s, v in stage_ms.items()))
+
+    # FP64 reference on the same inputs and neighbor sets.
+    nll64 = None
+    t64 = None
+    if not args.no_fp64_check:
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        nll64 = vif.vif_nll(*X, y, kern, m, nbr, ind=Z, prec="fp64")
+        torch.cuda.synchronize()
+        t64 = (time.perf_counter() - ta) * 1000.0
+        log(f"fp64 nll={nll64:.12g} ({t64:.1f} ms); rel diff {abs(nll - nll64) / abs(nll64):.3e}")
+
+    kpad = ((k + 1 + 63) // 64) * 64
+    es = PREC_ES[args.prec]
+    work = stage_work(n, m, k, kpad, es)
+    # dominant kernel among the single-kernel stages
+    cand = {s: stage_ms[s] for s in ("trmm", "point_factor", "syrk", "neighbors", "crosscov")}
+    dom = max(cand, key=cand.get)
+    t_dom = stage_ms[dom] / 1000.0
+    wk = work[dom]
+    if wk["flops"] is not None:
+        achieved = wk["flops"] / t_dom / 1e12
+        roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": mfma_peak(args.prec),
+                "unit": "TFLOP/s", "frac": achieved / mfma_peak(args.prec), "traffic": None}
+    else:
+        achieved = wk["bytes"] / t_dom / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_GBs"],
+                "unit": "GB/s", "frac": achieved / PEAK["hbm_GBs"], "traffic": None}
+    roof["ms_per_launch"] = stage_ms[dom]
+    stages = {}
+    for s, v in stage_ms.items():
+        e = {"ms": v}
+        if s in work and v > 0:
+            e["GB_per_s"] = work[s]["bytes"] / (v / 1000.0) / 1e9
+            if work[s]["flops"] is not None:
+                e["TFLOP_per_s"] = work[s]["flops"] / (v / 1000.0) / 1e12
+        stages[s] = e
+
+    nll_ms = sum(stage_ms[s] for s in ("sigma_k", "crosscov", "trmm", "point_factor", "syrk",
+                                       "assembly"))
+    out = {
+        "metric": METRIC,
+        "value": 1000.0 / ms_per_step,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": f"continental station network, {args.stations} stations x "
+                               f"{args.days} days, 10% missing (n={n}), m={m}, k={k}, Gneiting "
+                               f"kernel; step = exact neighbor search + VIF NLL",
+                   "n": n, "m": m, "k": k, "precision": args.prec},
+        "neighbor_pts_per_s": n / (stage_ms["neighbors"] / 1000.0) if stage_ms["neighbors"] else None,
+        "nll_evals_per_s_gpu_time": 1000.0 / nll_ms if nll_ms else None,
+        "nll": nll,
+        "nll_fp64": nll64,
+        "nll_rel_err_vs_fp64": abs(nll - nll64) / abs(nll64) if nll64 is not None else None,
+        "fp64_nll_ms": t64,
+        "stages": stages,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(d, m)
+        log(f"cpu baseline in {time.perf_counter() - t0:.1f}s")
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -65,12 +65,19 @@ enum {
 enum { VIF_KERNEL_GNEITING = 1, VIF_KERNEL_GNEITING_MATERN = 2, VIF_KERNEL_MATERN_ANISO = 3 };
 
 /* Arithmetic of the per-point factors and the low-rank contractions.
- * FP64: everything in FP64. FP32: covariance entries, per-point Cholesky and
- * the U / Gram / W / M contractions in FP32 (FP32 MFMA). BF16X3: as FP32 but
- * the contractions use split-BF16 MFMA (hi*hi + hi*lo + lo*hi, FP32 accumulate).
- * In every mode the Sigma_k and M Cholesky factors, log-determinants,
- * quadratic forms and sums over points are FP64. */
-enum { VIF_PREC_FP64 = 0, VIF_PREC_FP32 = 1, VIF_PREC_BF16X3 = 2 };
+ * FP64: everything in FP64 (FP64 MFMA for the contractions).
+ * FP32: covariance entries and per-point Cholesky in FP32; U, the per-point
+ *   Gram U_S U_S' and M = I + W'W on FP32 MFMA; U and W stored in FP32.
+ * BF16X3: as FP32, but the three contractions run on BF16 MFMA with each FP32
+ *   operand split in two bf16 terms, x = h + l, and the products
+ *   h*h + h*l + l*h accumulated in FP32 (about 16 significant bits per product).
+ * BF16X6: as BF16X3 for U; the Gram and M, whose results enter the likelihood
+ *   through cancellation (C - U_S U_S' and z'z - q'M^-1 q), split each operand
+ *   in three bf16 terms and accumulate the six products down to 2^-24.
+ * In every mode Sigma_k and its factor, the M factor, log-determinants,
+ * quadratic forms and sums over points are FP64, and the FP32 partial sums of
+ * M are combined in FP64 every 1024 rows. */
+enum { VIF_PREC_FP64 = 0, VIF_PREC_FP32 = 1, VIF_PREC_BF16X3 = 2, VIF_PREC_BF16X6 = 3 };
 
 enum { VIF_OP_NEIGHBORS = 0, VIF_OP_FACTOR = 1, VIF_OP_NLL = 2 };
 
@@ -146,6 +153,26 @@ int32_t vif_nll_terms(const vif_points* p, const double* y, const vif_kernel* ke
 /* Message for the last error on the calling thread ("" after success). The
  * pointer stays valid until the next call on this thread. */
 const char* vif_last_error(void);
+
+/* Stage timing (instrumentation, not part of the method). When enabled, each
+ * entry point records a pair of HIP events on its stream around every stage
+ * below and, after its final synchronisation, adds the elapsed time to a
+ * process-wide total. Not thread-safe: profile from one host thread. */
+enum {
+  VIF_STAGE_NEIGHBORS = 0,     /* slab table + neighbor search kernels */
+  VIF_STAGE_SIGMA_K = 1,       /* Sigma_k, its Cholesky factor and inverse */
+  VIF_STAGE_CROSSCOV = 2,      /* cross-covariance C(X,Z) into U's buffer */
+  VIF_STAGE_TRMM = 3,          /* U = C(X,Z) L_k^-T, in place */
+  VIF_STAGE_POINT_FACTOR = 4,  /* per-point factor (and W for the VIF NLL) */
+  VIF_STAGE_SYRK = 5,          /* partial sums of [W z]'[W z] */
+  VIF_STAGE_ASSEMBLY = 6,      /* reduction, chol(M), sums, final assembly */
+  VIF_NSTAGES = 7
+};
+/* enable != 0 turns timing on, 0 turns it off; both reset the totals. */
+int32_t vif_profile(int32_t enable);
+/* Copies min(cap, VIF_NSTAGES) totals (ms) and call counts into the HOST
+ * arrays; VIF_E_ARG for NULL outputs. */
+int32_t vif_profile_read(double* total_ms, int32_t* calls, int32_t cap);
 
 #ifdef __cplusplus
 }

@@ -13,6 +13,7 @@ from ._lib import (  # noqa: F401
     VIF_OP_NEIGHBORS,
     VIF_OP_NLL,
     VIF_PREC_BF16X3,
+    VIF_PREC_BF16X6,
     VIF_PREC_FP32,
     VIF_PREC_FP64,
     load,
@@ -21,5 +22,7 @@ from ._lib import (  # noqa: F401
     vif_neighbors,
     vif_nll,
     vif_nll_terms,
+    vif_profile,
+    vif_profile_read,
     vif_workspace_bytes,
 )

@@ -16,12 +16,14 @@ LIB_PATH = os.path.join(PKG, "libvif.so")
 
 VIF_OK, VIF_E_ARG, VIF_E_NOT_PD, VIF_E_DEVICE, VIF_E_WORKSPACE, VIF_E_UNSUPPORTED = range(6)
 VIF_KERNEL_GNEITING, VIF_KERNEL_GNEITING_MATERN, VIF_KERNEL_MATERN_ANISO = 1, 2, 3
-VIF_PREC_FP64, VIF_PREC_FP32, VIF_PREC_BF16X3 = 0, 1, 2
+VIF_PREC_FP64, VIF_PREC_FP32, VIF_PREC_BF16X3, VIF_PREC_BF16X6 = 0, 1, 2, 3
 VIF_OP_NEIGHBORS, VIF_OP_FACTOR, VIF_OP_NLL = 0, 1, 2
-PREC_NAMES = {"fp64": VIF_PREC_FP64, "fp32": VIF_PREC_FP32, "bf16x3": VIF_PREC_BF16X3}
+PREC_NAMES = {"fp64": VIF_PREC_FP64, "fp32": VIF_PREC_FP32, "bf16x3": VIF_PREC_BF16X3,
+              "bf16x6": VIF_PREC_BF16X6}
 
 EXPORTS = ("vif_workspace_bytes", "vif_neighbors", "vif_factor", "vif_nll", "vif_nll_terms",
-           "vif_last_error")
+           "vif_last_error", "vif_profile", "vif_profile_read")
+STAGES = ("neighbors", "sigma_k", "crosscov", "trmm", "point_factor", "syrk", "assembly")
 
 
 class VifError(RuntimeError):
@@ -70,6 +72,10 @@ def load(path=LIB_PATH):
         lib.vif_nll_terms.restype = i32
         lib.vif_last_error.argtypes = []
         lib.vif_last_error.restype = ctypes.c_char_p
+        lib.vif_profile.argtypes = [i32]
+        lib.vif_profile.restype = i32
+        lib.vif_profile_read.argtypes = [pd, ctypes.POINTER(i32), i32]
+        lib.vif_profile_read.restype = i32
         _lib = lib
         return lib
 
@@ -229,3 +235,17 @@ def vif_nll(sx, sy, t, y, kern, m, nbr, ind=None, prec="fp64", stream=None):
                        ctypes.byref(ip) if ip is not None else None, _prec(prec),
                        ctypes.byref(out), ws.data_ptr(), ws.numel(), _stream(stream)))
     return out.value
+
+
+def vif_profile(enable):
+    """Turn the library's stage timing on or off (both reset the totals)."""
+    _check(load().vif_profile(1 if enable else 0))
+
+
+def vif_profile_read():
+    """{stage: (total_ms, calls)} accumulated since the last vif_profile()."""
+    n = len(STAGES)
+    ms = (ctypes.c_double * n)()
+    calls = (ctypes.c_int32 * n)()
+    _check(load().vif_profile_read(ms, calls, n))
+    return {STAGES[i]: (ms[i], calls[i]) for i in range(n)}

@@ -40,6 +40,49 @@ int32_t ok() {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// ---- optional stage timing: HIP events on the caller's stream ----------------
+struct Prof {
+  bool on = false;
+  hipEvent_t beg[VIF_NSTAGES] = {}, end[VIF_NSTAGES] = {};
+  bool used[VIF_NSTAGES] = {};
+  double total_ms[VIF_NSTAGES] = {};
+  int32_t calls[VIF_NSTAGES] = {};
+};
+Prof g_prof;
+
+int32_t prof_mark(int st, bool at_end, hipStream_t s) {
+  if (!g_prof.on) return VIF_OK;
+  hipEvent_t* ev = at_end ? &g_prof.end[st] : &g_prof.beg[st];
+  if (!*ev) {
+    hipError_t e = hipEventCreate(ev);
+    if (e != hipSuccess) return fail(VIF_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+  }
+  hipError_t e = hipEventRecord(*ev, s);
+  if (e != hipSuccess) return fail(VIF_E_DEVICE, "hipEventRecord: %s", hipGetErrorString(e));
+  if (at_end) g_prof.used[st] = true;
+  return VIF_OK;
+}
+
+// Called after the stream has been synchronised.
+void prof_collect() {
+  if (!g_prof.on) return;
+  for (int st = 0; st < VIF_NSTAGES; ++st) {
+    if (!g_prof.used[st]) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, g_prof.beg[st], g_prof.end[st]) == hipSuccess) {
+      g_prof.total_ms[st] += ms;
+      g_prof.calls[st] += 1;
+    }
+    g_prof.used[st] = false;
+  }
+}
+
+#define PROF(st, end)                          \
+  do {                                         \
+    int32_t p_ = prof_mark((st), (end), s);    \
+    if (p_) return p_;                         \
+  } while (0)
+
 int kpad_of(int k) { return k > 0 ? ((k + 1 + 63) / 64) * 64 : 0; }
 
 struct Layout {
@@ -230,10 +273,17 @@ int32_t run_lowrank(const vif_points* p, const vif_points* ind, const vif_kernel
   double* Sk = reinterpret_cast<double*>(ws + L.Sk);
   double* P = reinterpret_cast<double*>(ws + L.P);
   auto* fl = reinterpret_cast<unsigned long long*>(ws + L.flags);
+  PROF(VIF_STAGE_SIGMA_K, false);
   HIPCHK(vif::launch_cov_kk(a, Sk, s));
   HIPCHK(vif::launch_cholesky(L.kpad, Sk, reinterpret_cast<double*>(ws + L.dscr), fl + 1, s));
   HIPCHK(vif::launch_trinv(L.kpad, Sk, P, s));
-  HIPCHK(vif::launch_lowrank_u(a, P, ws + L.U, prec, nullptr, s));
+  PROF(VIF_STAGE_SIGMA_K, true);
+  PROF(VIF_STAGE_CROSSCOV, false);
+  HIPCHK(vif::launch_crosscov(a, ws + L.U, prec, s));
+  PROF(VIF_STAGE_CROSSCOV, true);
+  PROF(VIF_STAGE_TRMM, false);
+  HIPCHK(vif::launch_trmm(a, P, ws + L.U, prec, s));
+  PROF(VIF_STAGE_TRMM, true);
   return VIF_OK;
 }
 
@@ -253,7 +303,7 @@ int32_t nll_impl(const vif_points* p, const double* y, const vif_kernel* kern, i
   int k = 0;
   int32_t st = check_ind(ind, &k);
   if (st) return st;
-  if (prec < VIF_PREC_FP64 || prec > VIF_PREC_BF16X3) return fail(VIF_E_ARG, "unknown precision %d", prec);
+  if (prec < VIF_PREC_FP64 || prec > VIF_PREC_BF16X6) return fail(VIF_E_ARG, "unknown precision %d", prec);
   if (!p) return fail(VIF_E_ARG, "points is NULL");
   const Layout L = make_layout(p->n, m, k, prec, VIF_OP_NLL);
   st = check_common(p, kern, m, wsv, ws_bytes, L.total);
@@ -284,25 +334,36 @@ int32_t nll_impl(const vif_points* p, const double* y, const vif_kernel* kern, i
     if ((st = run_lowrank(p, ind, kern, prec, ws, L, s))) return st;
     fa.U = ws + L.U;
     fa.W = ws + L.W;
+    PROF(VIF_STAGE_POINT_FACTOR, false);
     HIPCHK(vif::launch_point_factor(fa, 0, prec, s));
+    PROF(VIF_STAGE_POINT_FACTOR, true);
     double* syrk = reinterpret_cast<double*>(ws + L.syrk);
     double* M = reinterpret_cast<double*>(ws + L.M);
     double* q = reinterpret_cast<double*>(ws + L.q);
+    PROF(VIF_STAGE_SYRK, false);
     HIPCHK(vif::launch_syrk(p->n, L.kpad, ws + L.W, prec, syrk, L.splits, s));
+    PROF(VIF_STAGE_SYRK, true);
+    PROF(VIF_STAGE_ASSEMBLY, false);
     HIPCHK(vif::launch_syrk_reduce(k, L.kpad, syrk, L.splits, M, q, sums + 1, s));
     HIPCHK(vif::launch_cholesky(L.kpad, M, reinterpret_cast<double*>(ws + L.dscr), fl + 2, s));
     HIPCHK(vif::launch_sum(p->n, fa.logD, 0, part, sums + 0, s));
     HIPCHK(vif::launch_finalize(p->n, k, L.kpad, M, q, sums + 0, sums + 1, out, s));
+    PROF(VIF_STAGE_ASSEMBLY, true);
   } else {
     fa.z = reinterpret_cast<double*>(ws + L.z);
+    PROF(VIF_STAGE_POINT_FACTOR, false);
     HIPCHK(vif::launch_point_factor(fa, 0, prec, s));
+    PROF(VIF_STAGE_POINT_FACTOR, true);
+    PROF(VIF_STAGE_ASSEMBLY, false);
     HIPCHK(vif::launch_sum(p->n, fa.logD, 0, part, sums + 0, s));
     HIPCHK(vif::launch_sum(p->n, fa.z, 1, part, sums + 1, s));
     HIPCHK(vif::launch_finalize(p->n, 0, 0, nullptr, nullptr, sums + 0, sums + 1, out, s));
+    PROF(VIF_STAGE_ASSEMBLY, true);
   }
   Flags f;
   double h[5];
   if ((st = read_flags(ws, L, &f, h, 5, s))) return st;
+  prof_collect();
   if ((st = report_flags(f))) return st;
   *nll = h[0];
   if (terms) {
@@ -320,12 +381,32 @@ extern "C" {
 
 size_t vif_workspace_bytes(int64_t n, int32_t m, int32_t k, int32_t prec, int32_t op) {
   if (n < 1 || m < 0 || m > VIF_MAX_M || k < 0 || k > VIF_MAX_K) return 0;
-  if (prec < VIF_PREC_FP64 || prec > VIF_PREC_BF16X3) return 0;
+  if (prec < VIF_PREC_FP64 || prec > VIF_PREC_BF16X6) return 0;
   if (op < VIF_OP_NEIGHBORS || op > VIF_OP_NLL) return 0;
   return make_layout(n, m, k, prec, op).total;
 }
 
 const char* vif_last_error(void) { return g_err.c_str(); }
+
+int32_t vif_profile(int32_t enable) {
+  g_prof.on = enable != 0;
+  for (int st = 0; st < VIF_NSTAGES; ++st) {
+    g_prof.total_ms[st] = 0.0;
+    g_prof.calls[st] = 0;
+    g_prof.used[st] = false;
+  }
+  return ok();
+}
+
+int32_t vif_profile_read(double* total_ms, int32_t* calls, int32_t cap) {
+  if (!total_ms || !calls || cap < 0) return fail(VIF_E_ARG, "NULL output or negative cap");
+  const int nst = cap < VIF_NSTAGES ? cap : VIF_NSTAGES;
+  for (int st = 0; st < nst; ++st) {
+    total_ms[st] = g_prof.total_ms[st];
+    calls[st] = g_prof.calls[st];
+  }
+  return ok();
+}
 
 int32_t vif_neighbors(const vif_points* p, const vif_kernel* kern, int32_t m, int32_t* nbr,
                       void* wsv, size_t ws_bytes, void* hip_stream) {
@@ -397,6 +478,7 @@ int32_t vif_neighbors(const vif_points* p, const vif_kernel* kern, int32_t m, in
   HIPCHK(hipMemcpyAsync(ws + L.tab2, tab2, sizeof(double) * (Lmax + 1), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ws + L.bnd, bnd, sizeof(double) * (Lmax + 1), hipMemcpyHostToDevice, s));
   int32_t* slab = reinterpret_cast<int32_t*>(ws + L.slab);
+  PROF(VIF_STAGE_NEIGHBORS, false);
   HIPCHK(vif::launch_slab_start(p->n, p->t, tt[0], Lmax, slab, s));
   vif::NbrArgs a{};
   a.n = p->n;
@@ -413,8 +495,10 @@ int32_t vif_neighbors(const vif_points* p, const vif_kernel* kern, int32_t m, in
   a.bnd = reinterpret_cast<const double*>(ws + L.bnd);
   a.nbr = nbr;
   HIPCHK(vif::launch_neighbors(a, s));
+  PROF(VIF_STAGE_NEIGHBORS, true);
   // The host tables must outlive the copies above.
   HIPCHK(hipStreamSynchronize(s));
+  prof_collect();
   return ok();
 }
 
@@ -424,7 +508,7 @@ int32_t vif_factor(const vif_points* p, const vif_kernel* kern, int32_t m, const
   int k = 0;
   int32_t st = check_ind(ind, &k);
   if (st) return st;
-  if (prec < VIF_PREC_FP64 || prec > VIF_PREC_BF16X3) return fail(VIF_E_ARG, "unknown precision %d", prec);
+  if (prec < VIF_PREC_FP64 || prec > VIF_PREC_BF16X6) return fail(VIF_E_ARG, "unknown precision %d", prec);
   if (!p) return fail(VIF_E_ARG, "points is NULL");
   const Layout L = make_layout(p->n, m, k, prec, VIF_OP_FACTOR);
   st = check_common(p, kern, m, wsv, ws_bytes, L.total);
@@ -451,9 +535,12 @@ int32_t vif_factor(const vif_points* p, const vif_kernel* kern, int32_t m, const
     if ((st = run_lowrank(p, ind, kern, prec, ws, L, s))) return st;
     fa.U = ws + L.U;
   }
+  PROF(VIF_STAGE_POINT_FACTOR, false);
   HIPCHK(vif::launch_point_factor(fa, 1, prec, s));
+  PROF(VIF_STAGE_POINT_FACTOR, true);
   Flags f;
   if ((st = read_flags(ws, L, &f, nullptr, 0, s))) return st;
+  prof_collect();
   if ((st = report_flags(f))) return st;
   return ok();
 }

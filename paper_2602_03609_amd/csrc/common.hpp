@@ -69,6 +69,12 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Accumulator layout of the 16x16 MFMA tiles: element e of `lane` holds
+// D[row][lane % 16]. The FP32-accumulating forms stack four consecutive rows
+// per lane group; the FP64 form interleaves them with stride 4.
+__device__ __forceinline__ int mfma16_row_f32acc(int lane, int e) { return 4 * (lane >> 4) + e; }
+__device__ __forceinline__ int mfma16_row_f64(int lane, int e) { return (lane >> 4) + 4 * e; }
+
 // Record the smallest failing index (vector atomic on global memory).
 __device__ __forceinline__ void flag_fail(unsigned long long* flag, long long idx) {
   atomicMin(flag, (unsigned long long)idx);

@@ -69,9 +69,10 @@ hipError_t launch_cholesky(int N, double* A, double* scratch, unsigned long long
                            hipStream_t s);
 // P = L^-1 for lower-triangular L (N x N, N multiple of 64); upper part of P set to 0.
 hipError_t launch_trinv(int N, const double* L, double* P, hipStream_t s);
-// U[i, :] = C(x_i, Z) P^T, U stored [n, kpad], FP64 (prec 0) or FP32 (prec 1, 2).
-hipError_t launch_lowrank_u(const LowRankArgs& a, const double* P, void* U, int prec,
-                            void* scratch, hipStream_t s);
+// U[i, l] = C(x_i, z_l) for l < k, 0 for k <= l < kpad; FP64 (prec 0) or FP32 (prec >= 1).
+hipError_t launch_crosscov(const LowRankArgs& a, void* U, int prec, hipStream_t s);
+// In place: U[i, :] <- U[i, :] P^T with P lower triangular (U = C(X,Z) L_k^-T).
+hipError_t launch_trmm(const LowRankArgs& a, const double* P, void* U, int prec, hipStream_t s);
 // Partial Gram of W over row chunks: part[s][tile] = sum over rows of chunk s of W_I' W_J.
 int syrk_splits(int64_t n, int kpad);
 hipError_t launch_syrk(int64_t n, int kpad, const void* W, int prec, double* part, int splits,

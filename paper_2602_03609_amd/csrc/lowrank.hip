@@ -300,7 +300,7 @@ __global__ __launch_bounds__(256) void trmm_f64_kernel(int64_t n, int kpad,
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int64_t row = I0 + wr * 32 + a * 16 + 4 * (lane >> 4) + e;
+          const int64_t row = I0 + wr * 32 + a * 16 + mfma16_row_f64(lane, e);
           const int col = J0 + wc * 32 + b * 16 + (lane & 15);
           if (row < n) U[row * kpad + col] = acc[a][b][e];
         }
@@ -398,7 +398,7 @@ __global__ __launch_bounds__(256) void trmm_f32_kernel(int64_t n, int kpad, floa
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int64_t row = I0 + wr * 32 + a * 16 + 4 * (lane >> 4) + e;
+          const int64_t row = I0 + wr * 32 + a * 16 + mfma16_row_f32acc(lane, e);
           const int col = J0 + wc * 32 + b * 16 + (lane & 15);
           if (row < n) U[row * kpad + col] = acc[a][b][e];
         }
@@ -419,7 +419,7 @@ __device__ __forceinline__ void tile_of(int t, int& TI, int& TJ) {
 template <int PREC>
 __global__ __launch_bounds__(256) void syrk_kernel(int64_t n, int kpad, const void* __restrict__ Wv,
                                                    double* __restrict__ part, int splits) {
-  constexpr int BK = PREC == 2 ? 32 : 16;
+  constexpr int BK = PREC >= 2 ? 32 : 16;
   constexpr int EPT = BK / 4;  // elements per thread per operand in the loader
   using UT = typename std::conditional<PREC == 0, double, float>::type;
   __shared__ UT Wa[BK][NB + 4];
@@ -486,33 +486,46 @@ __global__ __launch_bounds__(256) void syrk_kernel(int64_t n, int kpad, const vo
             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
       }
     } else {
+      // Split-BF16: 2 terms / 3 products (PREC 2) or 3 terms / 6 products (PREC 3).
+      constexpr int NS = PREC == 3 ? 3 : 2;
       const int kb = (lane >> 4) * 8;
-      bf8v ah[2], al[2], bh[2], bl[2];
+      bf8v pa[2][NS], pb[2][NS];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           float x = (float)Wa[kb + e][wr * 32 + a * 16 + (lane & 15)];
-          __bf16 h = (__bf16)x;
-          ah[a][e] = h;
-          al[a][e] = (__bf16)(x - (float)h);
+#pragma unroll
+          for (int sp = 0; sp < NS; ++sp) {
+            const __bf16 h = (__bf16)x;
+            pa[a][sp][e] = h;
+            x -= (float)h;
+          }
         }
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           float x = (float)Wb[kb + e][wc * 32 + b * 16 + (lane & 15)];
-          __bf16 h = (__bf16)x;
-          bh[b][e] = h;
-          bl[b][e] = (__bf16)(x - (float)h);
+#pragma unroll
+          for (int sp = 0; sp < NS; ++sp) {
+            const __bf16 h = (__bf16)x;
+            pb[b][sp][e] = h;
+            x -= (float)h;
+          }
         }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+          if constexpr (NS == 3) {
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa[a][2], pb[b][0], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa[a][1], pb[b][1], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa[a][0], pb[b][2], acc[a][b], 0, 0, 0);
+          }
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa[a][1], pb[b][0], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa[a][0], pb[b][1], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa[a][0], pb[b][0], acc[a][b], 0, 0, 0);
         }
     }
     if constexpr (PREC != 0) {
@@ -537,7 +550,8 @@ __global__ __launch_bounds__(256) void syrk_kernel(int64_t n, int kpad, const vo
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int row = wr * 32 + a * 16 + 4 * (lane >> 4) + e;
+        const int row = wr * 32 + a * 16 +
+                          (PREC == 0 ? mfma16_row_f64(lane, e) : mfma16_row_f32acc(lane, e));
         const int col = wc * 32 + b * 16 + (lane & 15);
         out[row * NB + col] = accd[a][b][e] + (double)acc[a][b][e];
       }
@@ -586,22 +600,25 @@ hipError_t launch_trinv(int N, const double* L, double* P, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_lowrank_u(const LowRankArgs& a, const double* P, void* U, int prec, void*,
-                            hipStream_t s) {
+hipError_t launch_crosscov(const LowRankArgs& a, void* U, int prec, hipStream_t s) {
   dim3 g1((unsigned)a.n, (a.kpad + 255) / 256);
-  const unsigned g2 = (unsigned)((a.n + 63) / 64);
-  if (prec == 0) {
+  if (prec == 0)
     hipLaunchKernelGGL(crosscov_kernel<double>, g1, dim3(256), 0, s, a, (double*)U);
-    hipLaunchKernelGGL(trmm_f64_kernel, dim3(g2), dim3(256), 0, s, a.n, a.kpad, (double*)U, P);
-  } else {
+  else
     hipLaunchKernelGGL(crosscov_kernel<float>, g1, dim3(256), 0, s, a, (float*)U);
-    if (prec == 1)
-      hipLaunchKernelGGL(trmm_f32_kernel<false>, dim3(g2), dim3(256), 0, s, a.n, a.kpad,
-                         (float*)U, P);
-    else
-      hipLaunchKernelGGL(trmm_f32_kernel<true>, dim3(g2), dim3(256), 0, s, a.n, a.kpad,
-                         (float*)U, P);
-  }
+  return hipGetLastError();
+}
+
+hipError_t launch_trmm(const LowRankArgs& a, const double* P, void* U, int prec, hipStream_t s) {
+  const unsigned g2 = (unsigned)((a.n + 63) / 64);
+  if (prec == 0)
+    hipLaunchKernelGGL(trmm_f64_kernel, dim3(g2), dim3(256), 0, s, a.n, a.kpad, (double*)U, P);
+  else if (prec == 1)
+    hipLaunchKernelGGL(trmm_f32_kernel<false>, dim3(g2), dim3(256), 0, s, a.n, a.kpad, (float*)U,
+                       P);
+  else
+    hipLaunchKernelGGL(trmm_f32_kernel<true>, dim3(g2), dim3(256), 0, s, a.n, a.kpad, (float*)U,
+                       P);
   return hipGetLastError();
 }
 
@@ -624,8 +641,10 @@ hipError_t launch_syrk(int64_t n, int kpad, const void* W, int prec, double* par
     hipLaunchKernelGGL(syrk_kernel<0>, grid, dim3(256), 0, s, n, kpad, W, part, splits);
   else if (prec == 1)
     hipLaunchKernelGGL(syrk_kernel<1>, grid, dim3(256), 0, s, n, kpad, W, part, splits);
-  else
+  else if (prec == 2)
     hipLaunchKernelGGL(syrk_kernel<2>, grid, dim3(256), 0, s, n, kpad, W, part, splits);
+  else
+    hipLaunchKernelGGL(syrk_kernel<3>, grid, dim3(256), 0, s, n, kpad, W, part, splits);
   return hipGetLastError();
 }
 

@@ -14,7 +14,7 @@
 // Cholesky broadcasts each new column through a double-buffered LDS vector and
 // pivots through cross-lane permutes. The VIF Gram U_S U_S' runs on MFMA with
 // the whole wavefront per point (FP64 16x16x4 MFMA, FP32 16x16x4 MFMA, or
-// split-BF16 16x16x32 MFMA with FP32 accumulation).
+// split-BF16 16x16x32 MFMA with FP32 accumulation, 3 or 6 products).
 #include <math.h>
 
 #include "internal.hpp"
@@ -31,6 +31,7 @@ template <int PREC> struct PrecT;
 template <> struct PrecT<0> { using T = double; using UT = double; };
 template <> struct PrecT<1> { using T = float; using UT = float; };
 template <> struct PrecT<2> { using T = float; using UT = float; };
+template <> struct PrecT<3> { using T = float; using UT = float; };
 
 // ---- Gram U_S U_S' on MFMA, whole wave, result (full symmetric) into G[ROWS*ROWS] ----
 template <int ROWS>
@@ -79,7 +80,7 @@ __device__ void gram_mfma_f64(const double* __restrict__ U, int ldu, const int* 
     for (int tj = 0; tj <= ti; ++tj) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        int row = ti * 16 + 4 * kq + e, col = tj * 16 + rr;
+        int row = ti * 16 + mfma16_row_f64(lane, e), col = tj * 16 + rr;
         G[row * ROWS + col] = acc[t][e];
         if (ti != tj) G[col * ROWS + row] = acc[t][e];
       }
@@ -132,7 +133,7 @@ __device__ void gram_mfma_f32(const float* __restrict__ U, int ldu, const int* s
     for (int tj = 0; tj <= ti; ++tj) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        int row = ti * 16 + 4 * kq + e, col = tj * 16 + rr;
+        int row = ti * 16 + mfma16_row_f32acc(lane, e), col = tj * 16 + rr;
         G[row * ROWS + col] = acc[t][e];
         if (ti != tj) G[col * ROWS + row] = acc[t][e];
       }
@@ -140,17 +141,16 @@ __device__ void gram_mfma_f32(const float* __restrict__ U, int ldu, const int* s
     }
 }
 
-// Split x = hi + lo with hi = bf16(x), lo = bf16(x - hi).
-__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
-  hi = (__bf16)x;
-  lo = (__bf16)(x - (float)hi);
-}
-
-template <int ROWS>
-__device__ void gram_mfma_bf16x3(const float* __restrict__ U, int ldu, const int* sidx, float* G,
-                                 int lane) {
+// Split-BF16 products with FP32 accumulation. NPROD = 3: x = h + l (two bf16
+// terms), products h*h + h*l + l*h (about 16 significant bits). NPROD = 6:
+// x = h + m + l (three terms), products down to the 2^-24 level:
+// h*h + (h*m + m*h) + (h*l + m*m + l*h), smallest issued first.
+template <int ROWS, int NPROD>
+__device__ void gram_mfma_bf16(const float* __restrict__ U, int ldu, const int* sidx, float* G,
+                               int lane) {
   constexpr int NT = ROWS / 16;
   constexpr int NTT = NT * (NT + 1) / 2;
+  constexpr int NS = NPROD == 3 ? 2 : 3;
   const int rr = lane & 15, kq = lane >> 4;
   f4v acc[NTT];
 #pragma unroll
@@ -162,7 +162,7 @@ __device__ void gram_mfma_bf16x3(const float* __restrict__ U, int ldu, const int
     rowp[ti] = s >= 0 ? U + (int64_t)s * ldu + kq * 8 : nullptr;
   }
   for (int kb = 0; kb < ldu; kb += 32) {
-    bf8v hi[NT], lo[NT];
+    bf8v part[NT][NS];
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti) {
       float x[8];
@@ -177,10 +177,13 @@ __device__ void gram_mfma_bf16x3(const float* __restrict__ U, int ldu, const int
       }
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        __bf16 h, l;
-        split_bf16(x[e], h, l);
-        hi[ti][e] = h;
-        lo[ti][e] = l;
+        float r = x[e];
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) {
+          const __bf16 h = (__bf16)r;
+          part[ti][sp][e] = h;
+          r -= (float)h;
+        }
       }
     }
     int t = 0;
@@ -188,9 +191,14 @@ __device__ void gram_mfma_bf16x3(const float* __restrict__ U, int ldu, const int
     for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
       for (int tj = 0; tj <= ti; ++tj) {
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo[ti], hi[tj], acc[t], 0, 0, 0);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[ti], lo[tj], acc[t], 0, 0, 0);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[ti], hi[tj], acc[t], 0, 0, 0);
+        if constexpr (NPROD == 6) {
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][2], part[tj][0], acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][1], part[tj][1], acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][0], part[tj][2], acc[t], 0, 0, 0);
+        }
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][1], part[tj][0], acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][0], part[tj][1], acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][0], part[tj][0], acc[t], 0, 0, 0);
         ++t;
       }
   }
@@ -201,7 +209,7 @@ __device__ void gram_mfma_bf16x3(const float* __restrict__ U, int ldu, const int
     for (int tj = 0; tj <= ti; ++tj) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        int row = ti * 16 + 4 * kq + e, col = tj * 16 + rr;
+        int row = ti * 16 + mfma16_row_f32acc(lane, e), col = tj * 16 + rr;
         G[row * ROWS + col] = acc[t][e];
         if (ti != tj) G[col * ROWS + row] = acc[t][e];
       }
@@ -311,8 +319,9 @@ __global__ __launch_bounds__(64 * wpb<ROWS>()) void point_factor_kernel(FactorAr
         gram_mfma_f32<ROWS>(reinterpret_cast<const float*>(A.U), A.ldu, sIdx[wave][s2],
                             reinterpret_cast<float*>(sM[wave][s2]), lane);
       else
-        gram_mfma_bf16x3<ROWS>(reinterpret_cast<const float*>(A.U), A.ldu, sIdx[wave][s2],
-                               reinterpret_cast<float*>(sM[wave][s2]), lane);
+        gram_mfma_bf16<ROWS, PREC == 3 ? 6 : 3>(reinterpret_cast<const float*>(A.U), A.ldu,
+                                                 sIdx[wave][s2],
+                                                 reinterpret_cast<float*>(sM[wave][s2]), lane);
     }
     wave_lds_sync();
   }
@@ -390,7 +399,8 @@ __global__ __launch_bounds__(64 * wpb<ROWS>()) void point_factor_kernel(FactorAr
   } else {
     if (active && r == 0) {
       A.logD[i] = 2.0 * log((double)Lpp_b);
-      A.z[i] = (double)zi;
+      // VIF stores z_i in column k of W instead (it feeds q = W'z).
+      if constexpr (!VIF) A.z[i] = (double)zi;
     }
   }
 
@@ -461,7 +471,8 @@ hipError_t launch_point_factor(const FactorArgs& a, int mode, int prec, hipStrea
   if (a.n <= 0) return hipSuccess;
   if (prec == 0) return launch_prec<0>(a, mode, s);
   if (prec == 1) return launch_prec<1>(a, mode, s);
-  return launch_prec<2>(a, mode, s);
+  if (prec == 2) return launch_prec<2>(a, mode, s);
+  return launch_prec<3>(a, mode, s);
 }
 
 }  // namespace vif

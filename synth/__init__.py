@@ -90,28 +90,32 @@ def station_days(n_stations, n_days, missing, rng):
     return sx[keep], sy[keep], t[keep]
 
 
-def kmeanspp(X, k, rng, lloyd_iters=10, lloyd_sample=200_000, chunk=65536):
-    """kMeans++ D^2 seeding, then Lloyd iterations on a subsample.
+def kmeanspp(X, k, rng, lloyd_iters=10, lloyd_sample=200_000, seed_sample=100_000, chunk=65536):
+    """kMeans++ D^2 seeding on a random subsample, then Lloyd iterations on a subsample.
 
     X is (n, d) in already scaled coordinates. Returns (k, d) centers.
     """
-    n = X.shape[0]
+    if X.shape[0] > seed_sample:
+        Xs = X[rng.choice(X.shape[0], seed_sample, replace=False)]
+    else:
+        Xs = X
+    n = Xs.shape[0]
     if k <= 0:
         return np.zeros((0, X.shape[1]))
     centers = np.empty((k, X.shape[1]))
-    centers[0] = X[rng.integers(n)]
-    d2 = ((X - centers[0]) ** 2).sum(1)
+    centers[0] = Xs[rng.integers(n)]
+    d2 = ((Xs - centers[0]) ** 2).sum(1)
     for c in range(1, k):
         tot = d2.sum()
         if tot <= 0:
-            centers[c] = X[rng.integers(n)]
+            centers[c] = Xs[rng.integers(n)]
         else:
             r = rng.random() * tot
             idx = int(np.searchsorted(np.cumsum(d2), r, side="right"))
-            centers[c] = X[min(idx, n - 1)]
-        d2 = np.minimum(d2, ((X - centers[c]) ** 2).sum(1))
+            centers[c] = Xs[min(idx, n - 1)]
+        d2 = np.minimum(d2, ((Xs - centers[c]) ** 2).sum(1))
     if lloyd_iters > 0:
-        S = X if n <= lloyd_sample else X[rng.choice(n, lloyd_sample, replace=False)]
+        S = X if X.shape[0] <= lloyd_sample else X[rng.choice(X.shape[0], lloyd_sample, replace=False)]
         for _ in range(lloyd_iters):
             lab = np.empty(S.shape[0], dtype=np.int64)
             cn = (centers ** 2).sum(1)
