@@ -87,13 +87,17 @@ int kpad_of(int k) { return k > 0 ? ((k + 1 + 63) / 64) * 64 : 0; }
 
 struct Layout {
   size_t flags = 0, out = 0, part = 0, sums = 0, logD = 0, z = 0, Sk = 0, P = 0, U = 0, W = 0,
-         syrk = 0, M = 0, q = 0, dscr = 0, slab = 0, tab1 = 0, tab2 = 0, bnd = 0, total = 0;
+         syrk = 0, M = 0, q = 0, dscr = 0, tab1 = 0, tab2 = 0, bnd = 0, bbox = 0, counts = 0,
+         fill = 0, bsum = 0, key = 0, px = 0, py = 0, pidx = 0, total = 0;
   int kpad = 0, splits = 0;
 };
 
 // Flags block: [0] fail_points, [1] fail_sigma_k, [2] fail_M, [3] bad_nbr (uint64 each),
 // [4] time flags (uint32).
 constexpr size_t kFlagBytes = 256;
+
+// Average number of points of one time slab per grid cell of the neighbor index.
+constexpr double kCellTarget = 32.0;
 
 Layout make_layout(int64_t n, int m, int k, int prec, int op) {
   Layout L;
@@ -106,10 +110,17 @@ Layout make_layout(int64_t n, int m, int k, int prec, int op) {
   const size_t es = prec == VIF_PREC_FP64 ? 8 : 4;
   L.flags = take(kFlagBytes);
   if (op == VIF_OP_NEIGHBORS) {
-    L.slab = take(sizeof(int32_t) * (VIF_MAX_LAGS + 2));
     L.tab1 = take(sizeof(double) * VIF_MAX_LAGS);
     L.tab2 = take(sizeof(double) * VIF_MAX_LAGS);
     L.bnd = take(sizeof(double) * VIF_MAX_LAGS);
+    L.bbox = take(sizeof(double) * (4 * 256 + 4));
+    L.counts = take(sizeof(int32_t) * ((size_t)vif::kMaxCells + 1));
+    L.fill = take(sizeof(int32_t) * ((size_t)vif::kMaxCells + 1));
+    L.bsum = take(sizeof(int32_t) * ((size_t)vif::kMaxCells / 1024 + 2));
+    L.key = take(sizeof(int32_t) * (size_t)n);
+    L.px = take(sizeof(double) * (size_t)n);
+    L.py = take(sizeof(double) * (size_t)n);
+    L.pidx = take(sizeof(int32_t) * (size_t)n);
     L.total = off;
     return L;
   }
@@ -420,13 +431,18 @@ int32_t vif_neighbors(const vif_points* p, const vif_kernel* kern, int32_t m, in
   char* ws = reinterpret_cast<char*>(wsv);
   if ((st = init_flags(ws, L, s))) return st;
   Flags* dflags = reinterpret_cast<Flags*>(ws + L.flags);
+  double* bbox = reinterpret_cast<double*>(ws + L.bbox);
   HIPCHK(vif::launch_validate_times(p->n, p->t, &dflags->tflag, s));
+  HIPCHK(vif::launch_bbox(p->n, p->sx, p->sy, bbox, bbox + 4 * 256, s));
   Flags f;
-  double tt[2];
+  double tt[2], bb[4];
   HIPCHK(hipMemcpyAsync(&f, ws + L.flags, sizeof(f), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&tt[0], p->t, sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&tt[1], p->t + (p->n - 1), sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(bb, bbox + 4 * 256, sizeof(bb), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  if (!isfinite(bb[0]) || !isfinite(bb[1]) || !isfinite(bb[2]) || !isfinite(bb[3]))
+    return fail(VIF_E_ARG, "coordinates must be finite");
   if (f.tflag & 1u) return fail(VIF_E_ARG, "times must be finite");
   if (f.tflag & 2u) return fail(VIF_E_UNSUPPORTED, "neighbor search requires integer-valued times");
   if (f.tflag & 4u) return fail(VIF_E_ARG, "times must be nondecreasing in index");
@@ -477,9 +493,57 @@ int32_t vif_neighbors(const vif_points* p, const vif_kernel* kern, int32_t m, in
   HIPCHK(hipMemcpyAsync(ws + L.tab1, tab1, sizeof(double) * (Lmax + 1), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ws + L.tab2, tab2, sizeof(double) * (Lmax + 1), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ws + L.bnd, bnd, sizeof(double) * (Lmax + 1), hipMemcpyHostToDevice, s));
-  int32_t* slab = reinterpret_cast<int32_t*>(ws + L.slab);
+  // Spatial grid: about kCellTarget points of one time slab per cell.
+  vif::GridArgs g{};
+  {
+    const int nslab = Lmax + 1;
+    const double w = bb[1] - bb[0], h = bb[3] - bb[2];
+    const double per_slab = (double)p->n / nslab;
+    double cells = per_slab / kCellTarget;
+    const double cap = (double)vif::kMaxCells / nslab;
+    if (cells > cap) cells = cap;
+    if (cells > 65536.0) cells = 65536.0;
+    if (cells < 1.0) cells = 1.0;
+    int gx = 1, gy = 1;
+    if (w > 0 && h > 0) {
+      gx = (int)lround(sqrt(cells * w / h));
+      if (gx < 1) gx = 1;
+      gy = (int)ceil(cells / gx);
+      if (gy < 1) gy = 1;
+    } else if (w > 0) {
+      gx = (int)cells;
+    } else if (h > 0) {
+      gy = (int)cells;
+    }
+    while ((int64_t)gx * gy * nslab > vif::kMaxCells) {
+      if (gx >= gy && gx > 1) --gx; else if (gy > 1) --gy; else break;
+    }
+    g.gx = gx;
+    g.gy = gy;
+    g.ncell = gx * gy;
+    g.nslab = nslab;
+    g.xmin = bb[0];
+    g.ymin = bb[2];
+    g.cw = w > 0 ? w / gx : 1.0;
+    g.ch = h > 0 ? h / gy : 1.0;
+    g.icw = w > 0 ? gx / w : 0.0;
+    g.ich = h > 0 ? gy / h : 0.0;
+    const double scale = fabs(bb[0]) + fabs(bb[1]) + fabs(bb[2]) + fabs(bb[3]) + w + h + 1.0;
+    g.margin = 1e-9 * scale;
+    g.off = reinterpret_cast<const int32_t*>(ws + L.counts);
+    g.px = reinterpret_cast<const double*>(ws + L.px);
+    g.py = reinterpret_cast<const double*>(ws + L.py);
+    g.pidx = reinterpret_cast<const int32_t*>(ws + L.pidx);
+  }
   PROF(VIF_STAGE_NEIGHBORS, false);
-  HIPCHK(vif::launch_slab_start(p->n, p->t, tt[0], Lmax, slab, s));
+  HIPCHK(vif::launch_grid_build(p->n, p->sx, p->sy, p->t, tt[0], g,
+                                reinterpret_cast<int32_t*>(ws + L.counts),
+                                reinterpret_cast<int32_t*>(ws + L.fill),
+                                reinterpret_cast<int32_t*>(ws + L.bsum),
+                                reinterpret_cast<int32_t*>(ws + L.key),
+                                reinterpret_cast<double*>(ws + L.px),
+                                reinterpret_cast<double*>(ws + L.py),
+                                reinterpret_cast<int32_t*>(ws + L.pidx), s));
   vif::NbrArgs a{};
   a.n = p->n;
   a.m = m;
@@ -489,12 +553,11 @@ int32_t vif_neighbors(const vif_points* p, const vif_kernel* kern, int32_t m, in
   a.gamma = kern->gamma;
   a.t0 = tt[0];
   a.sx = p->sx; a.sy = p->sy; a.t = p->t;
-  a.slab_start = slab;
   a.tab1 = reinterpret_cast<const double*>(ws + L.tab1);
   a.tab2 = reinterpret_cast<const double*>(ws + L.tab2);
   a.bnd = reinterpret_cast<const double*>(ws + L.bnd);
   a.nbr = nbr;
-  HIPCHK(vif::launch_neighbors(a, s));
+  HIPCHK(vif::launch_neighbors(a, g, s));
   PROF(VIF_STAGE_NEIGHBORS, true);
   // The host tables must outlive the copies above.
   HIPCHK(hipStreamSynchronize(s));

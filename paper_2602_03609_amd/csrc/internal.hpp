@@ -20,16 +20,35 @@ struct NbrArgs {
   int nu_code;
   double ir_s, gamma, t0;
   const double *sx, *sy, *t;
-  const int32_t* slab_start;  // [L+2], slab of time t0+l is [slab_start[l], slab_start[l+1])
   const double *tab1, *tab2, *bnd;
   int32_t* nbr;
 };
 
+// Uniform spatial grid shared by all time slabs; cell (cx, cy) of slab l holds
+// the points of time t0 + l whose coordinates fall in it, stored contiguously
+// (CSR over key = l * ncell + cy * gx + cx).
+struct GridArgs {
+  int gx, gy, ncell, nslab;
+  double xmin, ymin, cw, ch, icw, ich;  // cell sizes and their inverses
+  double margin;                        // absolute slack on distance bounds
+  const int32_t* off;                   // [nslab * ncell + 1]
+  const double *px, *py;                // coordinates in CSR order
+  const int32_t* pidx;                  // original index in CSR order
+};
+
+constexpr int kMaxCells = 1 << 22;  // nslab * ncell
+
 // Checks finite, integer-valued, nondecreasing times; sets bits in *flag.
 hipError_t launch_validate_times(int64_t n, const double* t, uint32_t* flag, hipStream_t s);
-hipError_t launch_slab_start(int64_t n, const double* t, double t0, int L, int32_t* slab_start,
+// out[0..3] = min sx, max sx, min sy, max sy (partial: 4 * 256 doubles of scratch).
+hipError_t launch_bbox(int64_t n, const double* sx, const double* sy, double* partial,
+                       double* out, hipStream_t s);
+// Builds the CSR grid: counts/fill [nslab*ncell + 1], bsum [scan scratch], key [n].
+hipError_t launch_grid_build(int64_t n, const double* sx, const double* sy, const double* t,
+                             double t0, const GridArgs& g, int32_t* counts, int32_t* fill,
+                             int32_t* bsum, int32_t* key, double* px, double* py, int32_t* pidx,
                              hipStream_t s);
-hipError_t launch_neighbors(const NbrArgs& a, hipStream_t s);
+hipError_t launch_neighbors(const NbrArgs& a, const GridArgs& g, hipStream_t s);
 
 // ---- per-point factor ---------------------------------------------------------
 struct FactorArgs {

@@ -2,13 +2,18 @@
 // selection", Alg. 2 semantics): exact top-m earlier points per query under a
 // FP64 log-correlation key, ties to the lower index.
 //
-// Design (gfx950): one wavefront per query. Candidate slabs (all points sharing
-// one integer time) are visited in increasing lag; within a slab, 64 candidates
-// are keyed per step (coalesced SoA loads), candidates that beat the current
-// m-th entry are found with a ballot and inserted one at a time into a sorted
-// list held one entry per lane. The scan stops at the first lag whose bound
-// (suffix maximum of -tab1) is strictly below the m-th key: no later slab can
-// contain a better or tying candidate with a lower index.
+// Design (gfx950): the points of each integer time (a "slab") are bucketed in a
+// uniform spatial grid shared by all slabs and stored contiguously (CSR built on
+// the device: count, scan, scatter). One wavefront serves one query. Slabs are
+// visited in increasing lag; within a slab, cells are visited in Chebyshev rings
+// around the query's cell. Two exact bounds stop the scan: the lag bound (no
+// candidate of a later slab can beat the current m-th key) and the ring bound
+// (a candidate outside the rings visited so far lies at least d away, and the
+// key is monotone in the distance; d carries a slack far above rounding error).
+// Keys of 64 candidates are evaluated per step from coalesced loads; candidates
+// beating the m-th entry are found with a ballot and either inserted one at a
+// time into a sorted list held one entry per lane, or, when many, sorted across
+// the wave (bitonic) and merged with the list.
 #include <limits.h>
 #include <math.h>
 
@@ -30,13 +35,131 @@ __global__ void validate_times_kernel(int64_t n, const double* __restrict__ t,
   if (bits) atomicOr(flag, bits);
 }
 
-__global__ void slab_start_kernel(int64_t n, const double* __restrict__ t, double t0, int L,
-                                  int32_t* __restrict__ slab_start) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i > n) return;
-  int cur = (i < n) ? (int)(t[i] - t0) : L + 1;
-  int prev = (i == 0) ? -1 : (int)(t[i - 1] - t0);
-  for (int s = prev + 1; s <= cur; ++s) slab_start[s] = (int32_t)i;
+// ---- bounding box and grid index ---------------------------------------------
+constexpr int kRedBlocks = 256;
+
+__global__ __launch_bounds__(256) void bbox_stage1(int64_t n, const double* __restrict__ sx,
+                                                   const double* __restrict__ sy,
+                                                   double* __restrict__ part) {
+  __shared__ double sh[4][256];
+  double v[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)kRedBlocks * 256) {
+    const double x = sx[i], y = sy[i];
+    v[0] = fmin(v[0], x);
+    v[1] = fmax(v[1], x);
+    v[2] = fmin(v[2], y);
+    v[3] = fmax(v[3], y);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] = v[c];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      sh[0][threadIdx.x] = fmin(sh[0][threadIdx.x], sh[0][threadIdx.x + st]);
+      sh[1][threadIdx.x] = fmax(sh[1][threadIdx.x], sh[1][threadIdx.x + st]);
+      sh[2][threadIdx.x] = fmin(sh[2][threadIdx.x], sh[2][threadIdx.x + st]);
+      sh[3][threadIdx.x] = fmax(sh[3][threadIdx.x], sh[3][threadIdx.x + st]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) part[threadIdx.x * kRedBlocks + blockIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void bbox_stage2(const double* __restrict__ part,
+                                                   double* __restrict__ out) {
+  if (threadIdx.x < 4) {
+    const int c = threadIdx.x;
+    double r = part[c * kRedBlocks];
+    for (int b = 1; b < kRedBlocks; ++b) {
+      const double v = part[c * kRedBlocks + b];
+      r = (c & 1) ? fmax(r, v) : fmin(r, v);
+    }
+    out[c] = r;
+  }
+}
+
+__device__ __forceinline__ int cell_of(double v, double lo, double inv, int g) {
+  int c = (int)((v - lo) * inv);
+  return c < 0 ? 0 : (c >= g ? g - 1 : c);
+}
+
+__global__ void fill_i32_kernel(int32_t* __restrict__ p, int64_t cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) p[i] = 0;
+}
+
+__global__ void grid_count_kernel(int64_t n, const double* __restrict__ sx,
+                                  const double* __restrict__ sy, const double* __restrict__ t,
+                                  double t0, GridArgs G, int32_t* __restrict__ counts,
+                                  int32_t* __restrict__ key) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int slab = (int)(t[i] - t0);
+  const int cx = cell_of(sx[i], G.xmin, G.icw, G.gx);
+  const int cy = cell_of(sy[i], G.ymin, G.ich, G.gy);
+  const int k = slab * G.ncell + cy * G.gx + cx;
+  key[i] = k;
+  atomicAdd(&counts[k], 1);
+}
+
+// Exclusive scan of counts[0..len) into counts (in place), tile of 1024.
+__global__ __launch_bounds__(1024) void scan_tiles_kernel(int32_t* __restrict__ a, int64_t len,
+                                                          int32_t* __restrict__ bsum) {
+  __shared__ int32_t sh[1024];
+  const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  const int32_t v = i < len ? a[i] : 0;
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int32_t add = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += add;
+    __syncthreads();
+  }
+  if (i < len) a[i] = sh[threadIdx.x] - v;
+  if (threadIdx.x == 1023) bsum[blockIdx.x] = sh[1023];
+}
+
+__global__ __launch_bounds__(1024) void scan_sums_kernel(int32_t* __restrict__ bsum, int nb) {
+  __shared__ int32_t sh[1024];
+  int32_t carry = 0;
+  for (int base = 0; base < nb; base += 1024) {
+    const int i = base + threadIdx.x;
+    const int32_t v = i < nb ? bsum[i] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int32_t add = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (i < nb) bsum[i] = carry + sh[threadIdx.x] - v;
+    const int32_t tot = sh[1023];
+    __syncthreads();
+    carry += tot;
+  }
+}
+
+__global__ __launch_bounds__(1024) void scan_add_kernel(int32_t* __restrict__ a, int64_t len,
+                                                        const int32_t* __restrict__ bsum) {
+  const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  if (i < len) a[i] += bsum[blockIdx.x];
+}
+
+__global__ void grid_scatter_kernel(int64_t n, const double* __restrict__ sx,
+                                    const double* __restrict__ sy,
+                                    const int32_t* __restrict__ key,
+                                    const int32_t* __restrict__ off, int32_t* __restrict__ fill,
+                                    double* __restrict__ px, double* __restrict__ py,
+                                    int32_t* __restrict__ pidx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int k = key[i];
+  const int pos = off[k] + atomicAdd(&fill[k], 1);
+  px[pos] = sx[i];
+  py[pos] = sy[i];
+  pidx[pos] = (int32_t)i;
 }
 
 // Ranking keys. Fixed operation order and no contraction, so that any IEEE FP64
@@ -66,14 +189,136 @@ __device__ __forceinline__ double rank_key(double dx, double dy, double t1, doub
   return -(t1 + s);
 }
 
+// Upper bound of the key over candidates at distance >= d (d already reduced by
+// the slack): the same operation sequence as rank_key at that distance.
 template <int MODE>
-__global__ __launch_bounds__(256) void neighbors_wave_kernel(NbrArgs A) {
+__device__ __forceinline__ double bound_key(double d, double t1, double t2, const NbrArgs& A) {
+#pragma clang fp contract(off)
+  if (MODE == 1) {
+    double u = d * A.ir_s;
+    return -(t1 + u * u);
+  }
+  if (MODE == 0) return -(t1 + d * t2);
+  if (MODE == 2) return -(t1 + pow(d * d, A.gamma) * t2);
+  double x = d * t2;
+  double s = A.nu_code == 1 ? x - log1p(x) : x - log1p(x + x * x / 3.0);
+  s = s > 0.0 ? s : 0.0;
+  return -(t1 + s);
+}
+
+// Rank order of candidates: larger key first, then lower index.
+__device__ __forceinline__ bool ranks_before(double ka, int ia, double kb, int ib) {
+  return ka > kb || (ka == kb && ia < ib);
+}
+
+// Compare-exchange with lane ^ stride; the lower lane keeps the better pair
+// when `desc`, the worse one otherwise.
+__device__ __forceinline__ void cmpx(double& k, int& id, int lane, int stride, bool desc) {
+  const double pk = __shfl_xor(k, stride);
+  const int pi = __shfl_xor(id, stride);
+  const bool lower = (lane & stride) == 0;
+  const bool pb = ranks_before(pk, pi, k, id);
+  const bool take = (lower == desc) ? pb : !pb;
+  k = take ? pk : k;
+  id = take ? pi : id;
+}
+
+// Bitonic sort of one (key, index) pair per lane into rank order (lane 0 best).
+__device__ __forceinline__ void wave_sort64(double& k, int& id, int lane) {
+#pragma unroll
+  for (int size = 2; size <= 64; size <<= 1)
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1)
+      cmpx(k, id, lane, stride, (lane & size) == 0 || size == 64);
+}
+
+// Rank-order a bitonic sequence held one pair per lane.
+__device__ __forceinline__ void wave_merge64(double& k, int& id, int lane) {
+#pragma unroll
+  for (int stride = 32; stride > 0; stride >>= 1) cmpx(k, id, lane, stride, true);
+}
+
+// Offer one chunk of candidates (one per lane) to the running top-m list.
+__device__ __forceinline__ void offer(double key, int j, bool valid, double& K, int& I, int& cnt,
+                                      double& thr, int& thr_i, int lane, int m) {
+  const bool better = valid && (cnt < m || key > thr || (key == thr && j < thr_i));
+  unsigned long long mask = __ballot(better);
+  const int nsurv = __popcll(mask);
+  if (nsurv > 8) {
+    // Many survivors: sort them across the wave and merge with the list. The
+    // list and the reversed sorted chunk form a bitonic sequence whose
+    // lane-wise better halves are the best 64 of the union.
+    double ck = better ? key : -INFINITY;
+    int cj = better ? j : INT_MAX;
+    wave_sort64(ck, cj, lane);
+    const double rk = __shfl(ck, 63 - lane);
+    const int rj = __shfl(cj, 63 - lane);
+    if (ranks_before(rk, rj, K, I)) {
+      K = rk;
+      I = rj;
+    }
+    wave_merge64(K, I, lane);
+    cnt = cnt + nsurv < m ? cnt + nsurv : m;
+    if (cnt >= m) {
+      thr = __shfl(K, m - 1);
+      thr_i = __shfl(I, m - 1);
+    }
+    return;
+  }
+  while (mask) {
+    const int s = __ffsll((long long)mask) - 1;
+    mask &= mask - 1;
+    const double ck = __shfl(key, s);
+    const int cj = __shfl(j, s);
+    if (cnt >= m && !(ck > thr || (ck == thr && cj < thr_i))) continue;
+    const bool before = lane < cnt && (K > ck || (K == ck && I < cj));
+    const int pos = __popcll(__ballot(before));
+    const double pK = __shfl_up(K, 1);
+    const int pI = __shfl_up(I, 1);
+    if (lane == pos) {
+      K = ck;
+      I = cj;
+    } else if (lane > pos) {
+      K = pK;
+      I = pI;
+    }
+    if (cnt < m) ++cnt;
+    if (cnt >= m) {
+      thr = __shfl(K, m - 1);
+      thr_i = __shfl(I, m - 1);
+    }
+  }
+}
+
+// Key and offer the candidates of cells xa..xb of row cy (one CSR range).
+template <int MODE>
+__device__ __forceinline__ void scan_run(const NbrArgs& A, const GridArgs& G, const int32_t* off,
+                                         int cy, int xa, int xb, double qx, double qy, double t1,
+                                         double t2, int jmax, double& K, int& I, int& cnt,
+                                         double& thr, int& thr_i, int lane, int m) {
+  const int beg = off[cy * G.gx + xa];
+  const int end = off[cy * G.gx + xb + 1];
+  for (int base = beg; base < end; base += 64) {
+    const int p = base + lane;
+    const bool inrun = p < end;
+    const int j = inrun ? G.pidx[p] : INT_MAX;
+    const bool valid = inrun && j < jmax;
+    double key = -INFINITY;
+    if (valid) key = rank_key<MODE>(G.px[p] - qx, G.py[p] - qy, t1, t2, A);
+    offer(key, j, valid, K, I, cnt, thr, thr_i, lane, m);
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void neighbors_grid_kernel(NbrArgs A, GridArgs G) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= A.n) return;  // uniform per wave
   const int m = A.m;
   const double qx = A.sx[i], qy = A.sy[i];
   const int ti = (int)(A.t[i] - A.t0);
+  const int qcx = cell_of(qx, G.xmin, G.icw, G.gx);
+  const int qcy = cell_of(qy, G.ymin, G.ich, G.gy);
   double K = -INFINITY;
   int I = INT_MAX;
   int cnt = 0;
@@ -82,37 +327,42 @@ __global__ __launch_bounds__(256) void neighbors_wave_kernel(NbrArgs A) {
   for (int lag = 0; lag <= ti; ++lag) {
     if (cnt >= m && A.bnd[lag] < thr) break;
     const int slab = ti - lag;
-    const int lo = A.slab_start[slab];
-    const int hi = (lag == 0) ? (int)i : A.slab_start[slab + 1];
+    const int32_t* off = G.off + (int64_t)slab * G.ncell;
+    const int jmax = (lag == 0) ? (int)i : INT_MAX;
     const double t1 = A.tab1[lag], t2 = A.tab2[lag];
-    for (int base = lo; base < hi; base += 64) {
-      const int j = base + lane;
-      const bool valid = j < hi;
-      double key = -INFINITY;
-      if (valid) key = rank_key<MODE>(A.sx[j] - qx, A.sy[j] - qy, t1, t2, A);
-      const bool better = valid && (cnt < m || key > thr || (key == thr && j < thr_i));
-      unsigned long long mask = __ballot(better);
-      while (mask) {
-        const int s = __ffsll((long long)mask) - 1;
-        mask &= mask - 1;
-        const double ck = __shfl(key, s);
-        const int cj = __shfl(j, s);
-        if (cnt >= m && !(ck > thr || (ck == thr && cj < thr_i))) continue;
-        const bool before = lane < cnt && (K > ck || (K == ck && I < cj));
-        const int pos = __popcll(__ballot(before));
-        const double pK = __shfl_up(K, 1);
-        const int pI = __shfl_up(I, 1);
-        if (lane == pos) {
-          K = ck;
-          I = cj;
-        } else if (lane > pos) {
-          K = pK;
-          I = pI;
-        }
-        if (cnt < m) ++cnt;
+    for (int r = 0;; ++r) {
+      if (r > 0) {
+        // Everything not yet visited lies outside the block of cells within
+        // Chebyshev distance r - 1; d is the distance to that block's edges.
+        const int bx0 = qcx - (r - 1), bx1 = qcx + (r - 1);
+        const int by0 = qcy - (r - 1), by1 = qcy + (r - 1);
+        double d = INFINITY;
+        if (bx0 > 0) d = fmin(d, qx - (G.xmin + bx0 * G.cw));
+        if (bx1 < G.gx - 1) d = fmin(d, (G.xmin + (bx1 + 1) * G.cw) - qx);
+        if (by0 > 0) d = fmin(d, qy - (G.ymin + by0 * G.ch));
+        if (by1 < G.gy - 1) d = fmin(d, (G.ymin + (by1 + 1) * G.ch) - qy);
+        if (d == INFINITY) break;  // the grid is covered
         if (cnt >= m) {
-          thr = __shfl(K, m - 1);
-          thr_i = __shfl(I, m - 1);
+          const double ds = fmax(0.0, d * (1.0 - 1e-9) - G.margin);
+          if (bound_key<MODE>(ds, t1, t2, A) < thr) break;
+        }
+      }
+      const int y0 = qcy - r, y1 = qcy + r;
+      const int ya = y0 < 0 ? 0 : y0, yb = y1 >= G.gy ? G.gy - 1 : y1;
+      for (int cy = ya; cy <= yb; ++cy) {
+        if (cy == y0 || cy == y1) {
+          // top or bottom row of the ring: one contiguous run of cells
+          scan_run<MODE>(A, G, off, cy, qcx - r < 0 ? 0 : qcx - r,
+                         qcx + r >= G.gx ? G.gx - 1 : qcx + r, qx, qy, t1, t2, jmax, K, I, cnt, thr,
+                         thr_i, lane, m);
+        } else {
+          // rows in between: the two cells at the ring's left and right ends
+          if (qcx - r >= 0)
+            scan_run<MODE>(A, G, off, cy, qcx - r, qcx - r, qx, qy, t1, t2, jmax, K, I, cnt, thr,
+                           thr_i, lane, m);
+          if (qcx + r < G.gx)
+            scan_run<MODE>(A, G, off, cy, qcx + r, qcx + r, qx, qy, t1, t2, jmax, K, I, cnt, thr,
+                           thr_i, lane, m);
         }
       }
     }
@@ -129,21 +379,42 @@ hipError_t launch_validate_times(int64_t n, const double* t, uint32_t* flag, hip
   return hipGetLastError();
 }
 
-hipError_t launch_slab_start(int64_t n, const double* t, double t0, int L, int32_t* slab_start,
-                             hipStream_t s) {
-  unsigned grid = (unsigned)((n + 1 + 255) / 256);
-  hipLaunchKernelGGL(slab_start_kernel, dim3(grid), dim3(256), 0, s, n, t, t0, L, slab_start);
+hipError_t launch_bbox(int64_t n, const double* sx, const double* sy, double* partial,
+                       double* out, hipStream_t s) {
+  hipLaunchKernelGGL(bbox_stage1, dim3(kRedBlocks), dim3(256), 0, s, n, sx, sy, partial);
+  hipLaunchKernelGGL(bbox_stage2, dim3(1), dim3(256), 0, s, (const double*)partial, out);
   return hipGetLastError();
 }
 
-hipError_t launch_neighbors(const NbrArgs& a, hipStream_t s) {
+hipError_t launch_grid_build(int64_t n, const double* sx, const double* sy, const double* t,
+                             double t0, const GridArgs& g, int32_t* counts, int32_t* fill,
+                             int32_t* bsum, int32_t* key, double* px, double* py, int32_t* pidx,
+                             hipStream_t s) {
+  const int64_t len = (int64_t)g.nslab * g.ncell + 1;
+  const unsigned gl = (unsigned)((len + 255) / 256);
+  const unsigned gn = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(gl), dim3(256), 0, s, counts, len);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(gl), dim3(256), 0, s, fill, len);
+  hipLaunchKernelGGL(grid_count_kernel, dim3(gn), dim3(256), 0, s, n, sx, sy, t, t0, g, counts,
+                     key);
+  const int nb = (int)((len + 1023) / 1024);
+  hipLaunchKernelGGL(scan_tiles_kernel, dim3(nb), dim3(1024), 0, s, counts, len, bsum);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, s, bsum, nb);
+  hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(1024), 0, s, counts, len,
+                     (const int32_t*)bsum);
+  hipLaunchKernelGGL(grid_scatter_kernel, dim3(gn), dim3(256), 0, s, n, sx, sy,
+                     (const int32_t*)key, (const int32_t*)counts, fill, px, py, pidx);
+  return hipGetLastError();
+}
+
+hipError_t launch_neighbors(const NbrArgs& a, const GridArgs& g, hipStream_t s) {
   if (a.n <= 0 || a.m <= 0) return hipSuccess;
   unsigned grid = (unsigned)((a.n + 3) / 4);
   switch (a.mode) {
-    case 0: hipLaunchKernelGGL(neighbors_wave_kernel<0>, dim3(grid), dim3(256), 0, s, a); break;
-    case 1: hipLaunchKernelGGL(neighbors_wave_kernel<1>, dim3(grid), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(neighbors_wave_kernel<2>, dim3(grid), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL(neighbors_wave_kernel<3>, dim3(grid), dim3(256), 0, s, a); break;
+    case 0: hipLaunchKernelGGL(neighbors_grid_kernel<0>, dim3(grid), dim3(256), 0, s, a, g); break;
+    case 1: hipLaunchKernelGGL(neighbors_grid_kernel<1>, dim3(grid), dim3(256), 0, s, a, g); break;
+    case 2: hipLaunchKernelGGL(neighbors_grid_kernel<2>, dim3(grid), dim3(256), 0, s, a, g); break;
+    default: hipLaunchKernelGGL(neighbors_grid_kernel<3>, dim3(grid), dim3(256), 0, s, a, g); break;
   }
   return hipGetLastError();
 }
