@@ -72,6 +72,49 @@ def stage_work(n, m, k, kpad, es):
     }
 
 
+PREC_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
+KERNEL_SOURCES = {"point_factor": "paper_2602_03609_amd/csrc/point_factor.hip",
+                  "syrk": "paper_2602_03609_amd/csrc/lowrank.hip",
+                  "trmm": "paper_2602_03609_amd/csrc/lowrank.hip",
+                  "crosscov": "paper_2602_03609_amd/csrc/lowrank.hip",
+                  "neighbors": "paper_2602_03609_amd/csrc/neighbors.hip"}
+
+
+def kernel_name(stage, prec, m):
+    """Template instance launched for a stage on this workload (as rocprofv3 names it)."""
+    c = PREC_CODE[prec]
+    rows = 16 if m + 1 <= 16 else (32 if m + 1 <= 32 else 64)
+    if stage == "point_factor":
+        return f"point_factor_kernel<{rows}, true, false, {c}>"
+    if stage == "syrk":
+        return f"syrk_kernel<{c}>"
+    if stage == "trmm":
+        return "trmm_f64_kernel" if c == 0 else f"trmm_f32_kernel<{'true' if c >= 2 else 'false'}>"
+    if stage == "crosscov":
+        return f"crosscov_kernel<{'double' if c == 0 else 'float'}>"
+    return "neighbors_grid_kernel<0>"
+
+
+def measured_traffic(stage, prec, m):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
+    kernel's source has changed since the counters were taken."""
+    import glob
+    import hashlib
+    name = kernel_name(stage, prec, m)
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json"))):
+        with open(path) as f:
+            tab = json.load(f)
+        e = tab.get(name)
+        if not e:
+            continue
+        src = os.path.join(ROOT, e["source"])
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        if sha == e["source_sha256"]:
+            return e["read_bytes"], e["write_bytes"], os.path.relpath(path, ROOT)
+    return None
+
+
 def mfma_peak(prec):
     if prec == "fp64":
         return PEAK["fp64_TFs"]
@@ -228,6 +271,12 @@ def main():
         roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_GBs"],
                 "unit": "GB/s", "frac": achieved / PEAK["hbm_GBs"], "traffic": None}
     roof["ms_per_launch"] = stage_ms[dom]
+    roof["algorithmic_bytes"] = wk["bytes"]
+    roof["algorithmic_flops"] = wk["flops"]
+    tr = measured_traffic(dom, args.prec, m)
+    if tr is not None:
+        roof["traffic"] = tr[0] + tr[1]
+        roof["traffic_read"], roof["traffic_write"], roof["traffic_source"] = tr
     stages = {}
     for s, v in stage_ms.items():
         e = {"ms": v}
