@@ -133,6 +133,13 @@ Layout make_layout(int64_t n, int m, int k, int prec, int op) {
     if (k == 0) L.z = take(sizeof(double) * (size_t)n);
   }
   if (k > 0) {
+    // processing order of the per-point kernel (Z order of a fine grid per time slab)
+    L.bbox = take(sizeof(double) * (4 * 256 + 4));
+    L.counts = take(sizeof(int32_t) * ((size_t)vif::kMaxCells + 1));
+    L.fill = take(sizeof(int32_t) * ((size_t)vif::kMaxCells + 1));
+    L.bsum = take(sizeof(int32_t) * ((size_t)vif::kMaxCells / 1024 + 2));
+    L.key = take(sizeof(int32_t) * (size_t)n);
+    L.pidx = take(sizeof(int32_t) * (size_t)n);
     L.kpad = kpad_of(k);
     const size_t kk = (size_t)L.kpad * L.kpad;
     L.Sk = take(sizeof(double) * kk);
@@ -270,6 +277,57 @@ int32_t report_flags(const Flags& f) {
   return VIF_OK;
 }
 
+// Processing order for the per-point VIF kernel: points sorted by time slab and
+// then by the Z order of a fine spatial grid, so that consecutive points (and
+// the workgroups one XCD runs together) share most of their neighbors' U rows.
+int32_t build_order(const vif_points* p, char* ws, const Layout& L, hipStream_t s,
+                    const int32_t** ord) {
+  Flags* dflags = reinterpret_cast<Flags*>(ws + L.flags);
+  double* bbox = reinterpret_cast<double*>(ws + L.bbox);
+  HIPCHK(vif::launch_validate_times(p->n, p->t, &dflags->tflag, s));
+  HIPCHK(vif::launch_bbox(p->n, p->sx, p->sy, bbox, bbox + 4 * 256, s));
+  Flags f;
+  double tt[2], bb[4];
+  HIPCHK(hipMemcpyAsync(&f, ws + L.flags, sizeof(f), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&tt[0], p->t, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&tt[1], p->t + (p->n - 1), sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(bb, bbox + 4 * 256, sizeof(bb), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *ord = nullptr;
+  if (f.tflag & 1u) return fail(VIF_E_ARG, "times must be finite");
+  if (!isfinite(bb[0]) || !isfinite(bb[1]) || !isfinite(bb[2]) || !isfinite(bb[3]))
+    return fail(VIF_E_ARG, "coordinates must be finite");
+  // Integer, nondecreasing times: one slab per time value; otherwise one slab.
+  int nslab = 1;
+  const double span = tt[1] - tt[0];
+  if (!(f.tflag & 6u) && span >= 0 && span < (double)VIF_MAX_LAGS) nslab = (int)span + 1;
+  const double per = (double)p->n / nslab;
+  int bits = 0;
+  while (bits < 10 && (double)(1 << (2 * (bits + 1))) * 3.0 <= per &&
+         (int64_t)(1 << (2 * (bits + 1))) * nslab <= vif::kMaxCells)
+    ++bits;
+  const double w = bb[1] - bb[0], h = bb[3] - bb[2];
+  vif::GridArgs g{};
+  g.gx = g.gy = 1 << bits;
+  g.ncell = g.gx * g.gy;
+  g.nslab = nslab;
+  g.morton = 1;
+  g.xmin = bb[0];
+  g.ymin = bb[2];
+  g.cw = w > 0 ? w / g.gx : 1.0;
+  g.ch = h > 0 ? h / g.gy : 1.0;
+  g.icw = w > 0 ? g.gx / w : 0.0;
+  g.ich = h > 0 ? g.gy / h : 0.0;
+  HIPCHK(vif::launch_grid_build(p->n, p->sx, p->sy, p->t, tt[0], g,
+                                reinterpret_cast<int32_t*>(ws + L.counts),
+                                reinterpret_cast<int32_t*>(ws + L.fill),
+                                reinterpret_cast<int32_t*>(ws + L.bsum),
+                                reinterpret_cast<int32_t*>(ws + L.key), nullptr, nullptr,
+                                reinterpret_cast<int32_t*>(ws + L.pidx), s));
+  *ord = reinterpret_cast<const int32_t*>(ws + L.pidx);
+  return VIF_OK;
+}
+
 // Sigma_k, its Cholesky factor and inverse, then U = C(X,Z) L_k^-T.
 int32_t run_lowrank(const vif_points* p, const vif_points* ind, const vif_kernel* kern, int prec,
                     char* ws, const Layout& L, hipStream_t s) {
@@ -342,6 +400,7 @@ int32_t nll_impl(const vif_points* p, const double* y, const vif_kernel* kern, i
   fa.fail = fl;
   fa.bad_nbr = fl + 3;
   if (k > 0) {
+    if ((st = build_order(p, ws, L, s, &fa.ord))) return st;
     if ((st = run_lowrank(p, ind, kern, prec, ws, L, s))) return st;
     fa.U = ws + L.U;
     fa.W = ws + L.W;
@@ -595,6 +654,7 @@ int32_t vif_factor(const vif_points* p, const vif_kernel* kern, int32_t m, const
   fa.fail = fl;
   fa.bad_nbr = fl + 3;
   if (k > 0) {
+    if ((st = build_order(p, ws, L, s, &fa.ord))) return st;
     if ((st = run_lowrank(p, ind, kern, prec, ws, L, s))) return st;
     fa.U = ws + L.U;
   }

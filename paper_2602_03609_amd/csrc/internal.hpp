@@ -29,6 +29,7 @@ struct NbrArgs {
 // (CSR over key = l * ncell + cy * gx + cx).
 struct GridArgs {
   int gx, gy, ncell, nslab;
+  int morton;                           // 1: cells numbered in Z order (gx = gy = 2^b)
   double xmin, ymin, cw, ch, icw, ich;  // cell sizes and their inverses
   double margin;                        // absolute slack on distance bounds
   const int32_t* off;                   // [nslab * ncell + 1]
@@ -63,6 +64,7 @@ struct FactorArgs {
   void* W;        // [n, ldu]; column k receives z_i
   double *B, *D;  // factor outputs
   double *logD, *z;  // NLL outputs (per point)
+  const int32_t* ord;           // processing order (a permutation of 0..n-1) or NULL
   unsigned long long* fail;     // smallest point index with a non-positive-definite block
   unsigned long long* bad_nbr;  // smallest point index with an invalid neighbor row
 };

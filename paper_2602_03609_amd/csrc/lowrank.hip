@@ -415,24 +415,33 @@ __device__ __forceinline__ void tile_of(int t, int& TI, int& TJ) {
   TJ = t;
 }
 
-// part[s][t] = sum over rows of chunk s of W[:, TI]' W[:, TJ] (64 x 64, FP64).
+// part[c][t] = sum over the rows of chunk c of W[:, TI]' W[:, TJ] (64 x 64, FP64).
+//
+// Block b serves row chunk c = b % nchunk and tile pair t = b / nchunk. With
+// nchunk = 8 and the round-robin dispatch of workgroups over the 8 XCDs, every
+// tile pair of one chunk runs on the same XCD, so the chunk's W rows are read
+// from HBM about once and then served by that XCD's L2 to all tile pairs.
+// Staging through LDS is double-buffered: the next rows are loaded into
+// registers while the MFMAs consume the current buffer.
 template <int PREC>
 __global__ __launch_bounds__(256) void syrk_kernel(int64_t n, int kpad, const void* __restrict__ Wv,
-                                                   double* __restrict__ part, int splits) {
-  constexpr int BK = PREC >= 2 ? 32 : 16;
-  constexpr int EPT = BK / 4;  // elements per thread per operand in the loader
+                                                   double* __restrict__ part, int nchunk,
+                                                   int ntile) {
+  constexpr int BK = PREC >= 2 ? 32 : 16;  // rows per step (the MFMA K)
   using UT = typename std::conditional<PREC == 0, double, float>::type;
-  __shared__ UT Wa[BK][NB + 4];
-  __shared__ UT Wb[BK][NB + 4];
+  constexpr int EPT = BK * NB / 256;       // elements per thread per operand per step
+  constexpr int VW = 16 / sizeof(UT);      // elements per 16-byte load
+  __shared__ UT Wa[2][BK][NB + 4];
+  __shared__ UT Wb[2][BK][NB + 4];
   const UT* W = reinterpret_cast<const UT*>(Wv);
-  const int ntile = gridDim.x;
-  const int t = blockIdx.x, s = blockIdx.y;
+  const int c = blockIdx.x % nchunk;
+  const int t = blockIdx.x / nchunk;
   int TI, TJ;
   tile_of(t, TI, TJ);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  const int64_t chunk = (n + splits - 1) / splits;
-  const int64_t rbeg = (int64_t)s * chunk;
+  const int64_t chunk = (n + nchunk - 1) / nchunk;
+  const int64_t rbeg = (int64_t)c * chunk;
   const int64_t rend = rbeg + chunk < n ? rbeg + chunk : n;
   const int lrow = tid / (NB / EPT), lcol = (tid % (NB / EPT)) * EPT;
   using AccT = typename std::conditional<PREC == 0, d4v, f4v>::type;
@@ -440,50 +449,67 @@ __global__ __launch_bounds__(256) void syrk_kernel(int64_t n, int kpad, const vo
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = AccT{0, 0, 0, 0};
+    for (int b2 = 0; b2 < 2; ++b2) acc[a][b2] = AccT{0, 0, 0, 0};
   double accd[2][2][4] = {};
   int flush = 0;
-  for (int64_t r0 = rbeg; r0 < rend; r0 += BK) {
-    __syncthreads();
-    {
-      const int64_t row = r0 + lrow;
-      const bool ok = row < rend;
+
+  UT ra[EPT], rb[EPT];
+  auto load = [&](int64_t r0) {
+    const int64_t row = r0 + lrow;
+    if (row < rend) {
+      const UT* pa = W + row * kpad + TI * NB + lcol;
+      const UT* pb = W + row * kpad + TJ * NB + lcol;
+#pragma unroll
+      for (int v = 0; v < EPT / VW; ++v) {
+        const float4 xa = reinterpret_cast<const float4*>(pa)[v];
+        const float4 xb = reinterpret_cast<const float4*>(pb)[v];
+        *reinterpret_cast<float4*>(&ra[v * VW]) = xa;
+        *reinterpret_cast<float4*>(&rb[v * VW]) = xb;
+      }
+    } else {
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
-        Wa[lrow][lcol + e] = ok ? W[row * kpad + TI * NB + lcol + e] : UT(0);
-        Wb[lrow][lcol + e] = ok ? W[row * kpad + TJ * NB + lcol + e] : UT(0);
+        ra[e] = UT(0);
+        rb[e] = UT(0);
       }
     }
-    __syncthreads();
-    if constexpr (PREC == 0) {
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      Wa[buf][lrow][lcol + e] = ra[e];
+      Wb[buf][lrow][lcol + e] = rb[e];
+    }
+  };
+
+  const int64_t nsteps = (rend - rbeg + BK - 1) / BK;
+  if (nsteps > 0) {
+    load(rbeg);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t st = 0; st < nsteps; ++st) {
+    const int buf = (int)(st & 1);
+    const bool more = st + 1 < nsteps;
+    if (more) load(rbeg + (st + 1) * BK);
+    if constexpr (PREC <= 1) {
 #pragma unroll
       for (int ks = 0; ks < BK / 4; ++ks) {
         const int kk = ks * 4 + (lane >> 4);
-        double av[2], bv[2];
+        UT av[2], bv[2];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) av[a] = Wa[kk][wr * 32 + a * 16 + (lane & 15)];
+        for (int a = 0; a < 2; ++a) av[a] = Wa[buf][kk][wr * 32 + a * 16 + (lane & 15)];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) bv[b] = Wb[kk][wc * 32 + b * 16 + (lane & 15)];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
-      }
-    } else if constexpr (PREC == 1) {
-#pragma unroll
-      for (int ks = 0; ks < BK / 4; ++ks) {
-        const int kk = ks * 4 + (lane >> 4);
-        float av[2], bv[2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) av[a] = Wa[kk][wr * 32 + a * 16 + (lane & 15)];
-#pragma unroll
-        for (int b = 0; b < 2; ++b) bv[b] = Wb[kk][wc * 32 + b * 16 + (lane & 15)];
+        for (int b2 = 0; b2 < 2; ++b2) bv[b2] = Wb[buf][kk][wc * 32 + b2 * 16 + (lane & 15)];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+          for (int b2 = 0; b2 < 2; ++b2) {
+            if constexpr (PREC == 0)
+              acc[a][b2] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b2], acc[a][b2], 0, 0, 0);
+            else
+              acc[a][b2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b2], acc[a][b2], 0, 0, 0);
+          }
       }
     } else {
       // Split-BF16: 2 terms / 3 products (PREC 2) or 3 terms / 6 products (PREC 3).
@@ -494,7 +520,7 @@ __global__ __launch_bounds__(256) void syrk_kernel(int64_t n, int kpad, const vo
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          float x = (float)Wa[kb + e][wr * 32 + a * 16 + (lane & 15)];
+          float x = (float)Wa[buf][kb + e][wr * 32 + a * 16 + (lane & 15)];
 #pragma unroll
           for (int sp = 0; sp < NS; ++sp) {
             const __bf16 h = (__bf16)x;
@@ -503,29 +529,29 @@ __global__ __launch_bounds__(256) void syrk_kernel(int64_t n, int kpad, const vo
           }
         }
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+      for (int b2 = 0; b2 < 2; ++b2)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          float x = (float)Wb[kb + e][wc * 32 + b * 16 + (lane & 15)];
+          float x = (float)Wb[buf][kb + e][wc * 32 + b2 * 16 + (lane & 15)];
 #pragma unroll
           for (int sp = 0; sp < NS; ++sp) {
             const __bf16 h = (__bf16)x;
-            pb[b][sp][e] = h;
+            pb[b2][sp][e] = h;
             x -= (float)h;
           }
         }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b2 = 0; b2 < 2; ++b2) {
           if constexpr (NS == 3) {
-            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa[a][2], pb[b][0], acc[a][b], 0, 0, 0);
-            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa[a][1], pb[b][1], acc[a][b], 0, 0, 0);
-            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa[a][0], pb[b][2], acc[a][b], 0, 0, 0);
+            acc[a][b2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa[a][2], pb[b2][0], acc[a][b2], 0, 0, 0);
+            acc[a][b2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa[a][1], pb[b2][1], acc[a][b2], 0, 0, 0);
+            acc[a][b2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa[a][0], pb[b2][2], acc[a][b2], 0, 0, 0);
           }
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa[a][1], pb[b][0], acc[a][b], 0, 0, 0);
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa[a][0], pb[b][1], acc[a][b], 0, 0, 0);
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa[a][0], pb[b][0], acc[a][b], 0, 0, 0);
+          acc[a][b2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa[a][1], pb[b2][0], acc[a][b2], 0, 0, 0);
+          acc[a][b2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa[a][0], pb[b2][1], acc[a][b2], 0, 0, 0);
+          acc[a][b2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa[a][0], pb[b2][0], acc[a][b2], 0, 0, 0);
         }
     }
     if constexpr (PREC != 0) {
@@ -535,25 +561,27 @@ __global__ __launch_bounds__(256) void syrk_kernel(int64_t n, int kpad, const vo
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b) {
+          for (int b2 = 0; b2 < 2; ++b2) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) accd[a][b][e] += (double)acc[a][b][e];
-            acc[a][b] = AccT{0, 0, 0, 0};
+            for (int e = 0; e < 4; ++e) accd[a][b2][e] += (double)acc[a][b2][e];
+            acc[a][b2] = AccT{0, 0, 0, 0};
           }
       }
     }
+    if (more) store(buf ^ 1);
+    __syncthreads();
   }
-  double* out = part + ((int64_t)s * ntile + t) * (NB * NB);
+  double* out = part + ((int64_t)c * ntile + t) * (NB * NB);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b2 = 0; b2 < 2; ++b2)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int row = wr * 32 + a * 16 +
-                          (PREC == 0 ? mfma16_row_f64(lane, e) : mfma16_row_f32acc(lane, e));
-        const int col = wc * 32 + b * 16 + (lane & 15);
-        out[row * NB + col] = accd[a][b][e] + (double)acc[a][b][e];
+                        (PREC == 0 ? mfma16_row_f64(lane, e) : mfma16_row_f32acc(lane, e));
+        const int col = wc * 32 + b2 * 16 + (lane & 15);
+        out[row * NB + col] = accd[a][b2][e] + (double)acc[a][b2][e];
       }
 }
 
@@ -622,29 +650,21 @@ hipError_t launch_trmm(const LowRankArgs& a, const double* P, void* U, int prec,
   return hipGetLastError();
 }
 
-int syrk_splits(int64_t n, int kpad) {
-  const int nt = kpad / NB;
-  const int ntile = nt * (nt + 1) / 2;
-  int sp = (2048 + ntile - 1) / ntile;
-  const int64_t max_by_rows = (n + 1023) / 1024;
-  if (sp > max_by_rows) sp = (int)max_by_rows;
-  if (sp < 1) sp = 1;
-  if (sp > 256) sp = 256;
-  return sp;
-}
+int syrk_splits(int64_t, int) { return 8; }
 
 hipError_t launch_syrk(int64_t n, int kpad, const void* W, int prec, double* part, int splits,
                        hipStream_t s) {
   const int nt = kpad / NB;
-  dim3 grid(nt * (nt + 1) / 2, splits);
+  const int ntile = nt * (nt + 1) / 2;
+  dim3 grid(ntile * splits);
   if (prec == 0)
-    hipLaunchKernelGGL(syrk_kernel<0>, grid, dim3(256), 0, s, n, kpad, W, part, splits);
+    hipLaunchKernelGGL(syrk_kernel<0>, grid, dim3(256), 0, s, n, kpad, W, part, splits, ntile);
   else if (prec == 1)
-    hipLaunchKernelGGL(syrk_kernel<1>, grid, dim3(256), 0, s, n, kpad, W, part, splits);
+    hipLaunchKernelGGL(syrk_kernel<1>, grid, dim3(256), 0, s, n, kpad, W, part, splits, ntile);
   else if (prec == 2)
-    hipLaunchKernelGGL(syrk_kernel<2>, grid, dim3(256), 0, s, n, kpad, W, part, splits);
+    hipLaunchKernelGGL(syrk_kernel<2>, grid, dim3(256), 0, s, n, kpad, W, part, splits, ntile);
   else
-    hipLaunchKernelGGL(syrk_kernel<3>, grid, dim3(256), 0, s, n, kpad, W, part, splits);
+    hipLaunchKernelGGL(syrk_kernel<3>, grid, dim3(256), 0, s, n, kpad, W, part, splits, ntile);
   return hipGetLastError();
 }
 

@@ -94,10 +94,17 @@ __global__ void grid_count_kernel(int64_t n, const double* __restrict__ sx,
                                   int32_t* __restrict__ key) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int slab = (int)(t[i] - t0);
+  const int slab = G.nslab > 1 ? (int)(t[i] - t0) : 0;
   const int cx = cell_of(sx[i], G.xmin, G.icw, G.gx);
   const int cy = cell_of(sy[i], G.ymin, G.ich, G.gy);
-  const int k = slab * G.ncell + cy * G.gx + cx;
+  int cell;
+  if (G.morton) {
+    cell = 0;
+    for (int b = 0; b < 16; ++b) cell |= (((cx >> b) & 1) << (2 * b)) | (((cy >> b) & 1) << (2 * b + 1));
+  } else {
+    cell = cy * G.gx + cx;
+  }
+  const int k = slab * G.ncell + cell;
   key[i] = k;
   atomicAdd(&counts[k], 1);
 }
@@ -157,8 +164,10 @@ __global__ void grid_scatter_kernel(int64_t n, const double* __restrict__ sx,
   if (i >= n) return;
   const int k = key[i];
   const int pos = off[k] + atomicAdd(&fill[k], 1);
-  px[pos] = sx[i];
-  py[pos] = sy[i];
+  if (px) {
+    px[pos] = sx[i];
+    py[pos] = sy[i];
+  }
   pidx[pos] = (int32_t)i;
 }
 

@@ -12,10 +12,14 @@
 // point; lane r holds row r of G in registers (fully unrolled). Covariance
 // entries are spread evenly over the segment and exchanged through LDS; the
 // Cholesky broadcasts each new column through a double-buffered LDS vector and
-// pivots through cross-lane permutes. The VIF Gram U_S U_S' runs on MFMA with
-// the whole wavefront per point (FP64 16x16x4 MFMA, FP32 16x16x4 MFMA, or
-// split-BF16 16x16x32 MFMA with FP32 accumulation, 3 or 6 products).
+// pivots through cross-lane permutes. Plain Vecchia uses point_factor_kernel;
+// VIF uses vif_group_kernel, which shares the conditioning rows of a group of
+// spatially adjacent points through LDS and forms the Grams U_S U_S' on MFMA
+// (FP64 16x16x4, FP32 16x16x4, or split-BF16 16x16x32 with FP32 accumulation).
+#include <limits.h>
 #include <math.h>
+
+#include <type_traits>
 
 #include "internal.hpp"
 
@@ -32,190 +36,6 @@ template <> struct PrecT<0> { using T = double; using UT = double; };
 template <> struct PrecT<1> { using T = float; using UT = float; };
 template <> struct PrecT<2> { using T = float; using UT = float; };
 template <> struct PrecT<3> { using T = float; using UT = float; };
-
-// ---- Gram U_S U_S' on MFMA, whole wave, result (full symmetric) into G[ROWS*ROWS] ----
-template <int ROWS>
-__device__ void gram_mfma_f64(const double* __restrict__ U, int ldu, const int* sidx, double* G,
-                              int lane) {
-  constexpr int NT = ROWS / 16;
-  constexpr int NTT = NT * (NT + 1) / 2;
-  const int rr = lane & 15, kq = lane >> 4;
-  d4v acc[NTT];
-#pragma unroll
-  for (int t = 0; t < NTT; ++t) acc[t] = d4v{0.0, 0.0, 0.0, 0.0};
-  const double* rowp[NT];
-#pragma unroll
-  for (int ti = 0; ti < NT; ++ti) {
-    int s = sidx[ti * 16 + rr];
-    rowp[ti] = s >= 0 ? U + (int64_t)s * ldu + kq * 4 : nullptr;
-  }
-  for (int kb = 0; kb < ldu; kb += 16) {
-    double v[NT][4];
-#pragma unroll
-    for (int ti = 0; ti < NT; ++ti) {
-      if (rowp[ti]) {
-        const double2* p2 = reinterpret_cast<const double2*>(rowp[ti] + kb);
-        double2 x0 = p2[0], x1 = p2[1];
-        v[ti][0] = x0.x; v[ti][1] = x0.y; v[ti][2] = x1.x; v[ti][3] = x1.y;
-      } else {
-        v[ti][0] = v[ti][1] = v[ti][2] = v[ti][3] = 0.0;
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      int t = 0;
-#pragma unroll
-      for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-        for (int tj = 0; tj <= ti; ++tj) {
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[ti][c], v[tj][c], acc[t], 0, 0, 0);
-          ++t;
-        }
-    }
-  }
-  int t = 0;
-#pragma unroll
-  for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-    for (int tj = 0; tj <= ti; ++tj) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int row = ti * 16 + mfma16_row_f64(lane, e), col = tj * 16 + rr;
-        G[row * ROWS + col] = acc[t][e];
-        if (ti != tj) G[col * ROWS + row] = acc[t][e];
-      }
-      ++t;
-    }
-}
-
-template <int ROWS>
-__device__ void gram_mfma_f32(const float* __restrict__ U, int ldu, const int* sidx, float* G,
-                              int lane) {
-  constexpr int NT = ROWS / 16;
-  constexpr int NTT = NT * (NT + 1) / 2;
-  const int rr = lane & 15, kq = lane >> 4;
-  f4v acc[NTT];
-#pragma unroll
-  for (int t = 0; t < NTT; ++t) acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
-  const float* rowp[NT];
-#pragma unroll
-  for (int ti = 0; ti < NT; ++ti) {
-    int s = sidx[ti * 16 + rr];
-    rowp[ti] = s >= 0 ? U + (int64_t)s * ldu + kq * 4 : nullptr;
-  }
-  for (int kb = 0; kb < ldu; kb += 16) {
-    float v[NT][4];
-#pragma unroll
-    for (int ti = 0; ti < NT; ++ti) {
-      if (rowp[ti]) {
-        float4 x = *reinterpret_cast<const float4*>(rowp[ti] + kb);
-        v[ti][0] = x.x; v[ti][1] = x.y; v[ti][2] = x.z; v[ti][3] = x.w;
-      } else {
-        v[ti][0] = v[ti][1] = v[ti][2] = v[ti][3] = 0.f;
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      int t = 0;
-#pragma unroll
-      for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-        for (int tj = 0; tj <= ti; ++tj) {
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[ti][c], v[tj][c], acc[t], 0, 0, 0);
-          ++t;
-        }
-    }
-  }
-  int t = 0;
-#pragma unroll
-  for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-    for (int tj = 0; tj <= ti; ++tj) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int row = ti * 16 + mfma16_row_f32acc(lane, e), col = tj * 16 + rr;
-        G[row * ROWS + col] = acc[t][e];
-        if (ti != tj) G[col * ROWS + row] = acc[t][e];
-      }
-      ++t;
-    }
-}
-
-// Split-BF16 products with FP32 accumulation. NPROD = 3: x = h + l (two bf16
-// terms), products h*h + h*l + l*h (about 16 significant bits). NPROD = 6:
-// x = h + m + l (three terms), products down to the 2^-24 level:
-// h*h + (h*m + m*h) + (h*l + m*m + l*h), smallest issued first.
-template <int ROWS, int NPROD>
-__device__ void gram_mfma_bf16(const float* __restrict__ U, int ldu, const int* sidx, float* G,
-                               int lane) {
-  constexpr int NT = ROWS / 16;
-  constexpr int NTT = NT * (NT + 1) / 2;
-  constexpr int NS = NPROD == 3 ? 2 : 3;
-  const int rr = lane & 15, kq = lane >> 4;
-  f4v acc[NTT];
-#pragma unroll
-  for (int t = 0; t < NTT; ++t) acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
-  const float* rowp[NT];
-#pragma unroll
-  for (int ti = 0; ti < NT; ++ti) {
-    int s = sidx[ti * 16 + rr];
-    rowp[ti] = s >= 0 ? U + (int64_t)s * ldu + kq * 8 : nullptr;
-  }
-  for (int kb = 0; kb < ldu; kb += 32) {
-    bf8v part[NT][NS];
-#pragma unroll
-    for (int ti = 0; ti < NT; ++ti) {
-      float x[8];
-      if (rowp[ti]) {
-        const float4* p4 = reinterpret_cast<const float4*>(rowp[ti] + kb);
-        float4 a0 = p4[0], a1 = p4[1];
-        x[0] = a0.x; x[1] = a0.y; x[2] = a0.z; x[3] = a0.w;
-        x[4] = a1.x; x[5] = a1.y; x[6] = a1.z; x[7] = a1.w;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) x[e] = 0.f;
-      }
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        float r = x[e];
-#pragma unroll
-        for (int sp = 0; sp < NS; ++sp) {
-          const __bf16 h = (__bf16)r;
-          part[ti][sp][e] = h;
-          r -= (float)h;
-        }
-      }
-    }
-    int t = 0;
-#pragma unroll
-    for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-      for (int tj = 0; tj <= ti; ++tj) {
-        if constexpr (NPROD == 6) {
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][2], part[tj][0], acc[t], 0, 0, 0);
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][1], part[tj][1], acc[t], 0, 0, 0);
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][0], part[tj][2], acc[t], 0, 0, 0);
-        }
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][1], part[tj][0], acc[t], 0, 0, 0);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][0], part[tj][1], acc[t], 0, 0, 0);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][0], part[tj][0], acc[t], 0, 0, 0);
-        ++t;
-      }
-  }
-  int t = 0;
-#pragma unroll
-  for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-    for (int tj = 0; tj <= ti; ++tj) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int row = ti * 16 + mfma16_row_f32acc(lane, e), col = tj * 16 + rr;
-        G[row * ROWS + col] = acc[t][e];
-        if (ti != tj) G[col * ROWS + row] = acc[t][e];
-      }
-      ++t;
-    }
-}
 
 // Cholesky of the segment's ROWS x ROWS matrix, lane r holding row r in a[] (only
 // a[j], j <= r, meaningful), with the forward solve of y carried along.
@@ -256,8 +76,10 @@ __device__ __forceinline__ bool seg_cholesky(T (&a)[ROWS], T& yv, T& diag, const
 // point) at 32 KB in FP64.
 template <int ROWS> constexpr int wpb() { return ROWS == 16 ? 4 : (ROWS == 32 ? 2 : 1); }
 
-template <int ROWS, bool VIF, bool WANT_B, int PREC>
+// Plain Vecchia per-point factor (no low-rank part).
+template <int ROWS, bool WANT_B, int PREC>
 __global__ __launch_bounds__(64 * wpb<ROWS>()) void point_factor_kernel(FactorArgs A) {
+  constexpr bool VIF = false;
   constexpr int kWPB = wpb<ROWS>();
   using T = typename PrecT<PREC>::T;
   using UT = typename PrecT<PREC>::UT;
@@ -266,15 +88,22 @@ __global__ __launch_bounds__(64 * wpb<ROWS>()) void point_factor_kernel(FactorAr
   __shared__ T sCol[kWPB][PPW][4 * (ROWS + 1)];
   __shared__ double sX[kWPB][PPW][ROWS], sY[kWPB][PPW][ROWS], sT[kWPB][PPW][ROWS];
   __shared__ int sIdx[kWPB][PPW][ROWS];
-  __shared__ T sB[kWPB][PPW][ROWS];
 
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int seg = lane / ROWS;
   const int r = lane % ROWS;
   const int sb = seg * ROWS;
-  const int64_t i = ((int64_t)blockIdx.x * kWPB + wave) * PPW + seg;
-  const bool active = i < A.n;
+  // Blocks are dealt round-robin to the 8 XCDs; remap so that each XCD walks a
+  // contiguous range of the processing order (its L2 then holds the U rows
+  // that spatially adjacent points share).
+  const int64_t nblk = (A.n + (int64_t)kWPB * PPW - 1) / ((int64_t)kWPB * PPW);
+  const int64_t per = (nblk + 7) / 8;
+  const int64_t lb = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (lb >= nblk) return;  // whole block
+  const int64_t pos = (lb * kWPB + wave) * PPW + seg;
+  const bool active = pos < A.n;
+  const int64_t i = active ? (A.ord ? (int64_t)A.ord[pos] : pos) : A.n;
   const int m = A.m;
 
   int idx = -1;
@@ -308,23 +137,6 @@ __global__ __launch_bounds__(64 * wpb<ROWS>()) void point_factor_kernel(FactorAr
   wave_lds_sync();
 
   T* M = sM[wave][seg];
-  if constexpr (VIF) {
-    // Gram of the gathered U rows, one point at a time with the whole wave.
-#pragma unroll
-    for (int s2 = 0; s2 < PPW; ++s2) {
-      if (PREC == 0)
-        gram_mfma_f64<ROWS>(reinterpret_cast<const double*>(A.U), A.ldu, sIdx[wave][s2],
-                            reinterpret_cast<double*>(sM[wave][s2]), lane);
-      else if (PREC == 1)
-        gram_mfma_f32<ROWS>(reinterpret_cast<const float*>(A.U), A.ldu, sIdx[wave][s2],
-                            reinterpret_cast<float*>(sM[wave][s2]), lane);
-      else
-        gram_mfma_bf16<ROWS, PREC == 3 ? 6 : 3>(reinterpret_cast<const float*>(A.U), A.ldu,
-                                                 sIdx[wave][s2],
-                                                 reinterpret_cast<float*>(sM[wave][s2]), lane);
-    }
-    wave_lds_sync();
-  }
 
   // Strictly lower entries, balanced: lanes r and r + ROWS/2 share the row pair
   // (r', ROWS-1-r'), whose ROWS-1 entries they split by parity.
@@ -404,65 +216,457 @@ __global__ __launch_bounds__(64 * wpb<ROWS>()) void point_factor_kernel(FactorAr
     }
   }
 
-  if constexpr (VIF && !WANT_B) {
-    // b_r = -x_r / L_pp (r < p), b_p = 1 / L_pp;  W_i = sum_r b_r U_{S_r}.
-    const T inv = T(1) / Lpp_b;
-    sB[wave][seg][r] = (r < p) ? -x * inv : (r == p ? inv : T(0));
-    wave_lds_sync();
-    const UT* U = reinterpret_cast<const UT*>(A.U);
-    UT* W = reinterpret_cast<UT*>(A.W);
+}
+
+// ---------------------------------------------------------------------------
+// VIF per-point factor, grouped. A workgroup takes GP consecutive points of the
+// processing order (spatially adjacent points of one time slab). Their
+// conditioning rows are merged into one sorted union (bitonic sort in LDS, then
+// deduplicated); the union's rows of U are streamed through LDS in 128-byte
+// column chunks, each chunk feeding the MFMA Grams of all GP points and, in a
+// second pass, their W rows. Every U row is thus fetched once per group
+// instead of once per point that uses it.
+template <int ROWS, int PREC>
+struct GroupShape {
+  using T = typename PrecT<PREC>::T;
+  static constexpr int PPW = 64 / ROWS;
+  static constexpr int NW0 = (int)(65536 / (PPW * ROWS * ROWS * sizeof(T)));
+  static constexpr int NW = NW0 > 8 ? 8 : NW0;   // wavefronts per workgroup
+  static constexpr int GP = NW * PPW;            // points per workgroup
+  static constexpr int NSLOT = GP * ROWS;        // conditioning rows (union upper bound)
+};
+
+template <int ROWS, bool WANT_B, int PREC>
+__global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_kernel(FactorArgs A) {
+  using Sh = GroupShape<ROWS, PREC>;
+  using T = typename PrecT<PREC>::T;
+  using UT = typename PrecT<PREC>::UT;
+  constexpr int PPW = Sh::PPW, NW = Sh::NW, GP = Sh::GP, NSLOT = Sh::NSLOT;
+  constexpr int NTH = 64 * NW;
+  constexpr int KC = 128 / (int)sizeof(UT);   // columns per staged chunk
+  constexpr int VPE = 16 / (int)sizeof(UT);   // elements per 16-byte piece
+  constexpr int SLD = KC + VPE;               // LDS row stride (elements), 16-byte aligned
+  constexpr int NT = ROWS / 16;
+  constexpr int NTT = NT * (NT + 1) / 2;
+  constexpr size_t STAGE_B = (size_t)NSLOT * SLD * sizeof(UT);
+  constexpr size_t MAT_B = (size_t)GP * ROWS * ROWS * sizeof(T);
+  constexpr size_t BIG_B = STAGE_B > MAT_B ? STAGE_B : MAT_B;
+  __shared__ __attribute__((aligned(16))) unsigned char sBig[BIG_B];
+  __shared__ int sIdx[GP][ROWS];
+  __shared__ int sSlot[GP][ROWS];
+  __shared__ int sSort[NSLOT];
+  __shared__ int sUniq[NSLOT];
+  __shared__ int sNU;
+  __shared__ double sX[GP][ROWS], sY[GP][ROWS], sT[GP][ROWS];
+  __shared__ T sCol[GP][4 * (ROWS + 1)];
+  __shared__ T sBv[GP][ROWS];
+  __shared__ T sZ[GP];
+  __shared__ int64_t sI[GP];
+  UT* stage = reinterpret_cast<UT*>(sBig);
+  T* sM = reinterpret_cast<T*>(sBig);
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int seg = lane / ROWS;
+  const int r = lane % ROWS;
+  const int sb = seg * ROWS;
+  const int pl = wave * PPW + seg;  // point slot in the group
+  // Workgroups are dealt round-robin to the 8 XCDs; each XCD walks a
+  // contiguous range of groups so that its L2 holds the rows they share.
+  const int64_t ngrp = (A.n + GP - 1) / GP;
+  const int64_t per = (ngrp + 7) / 8;
+  const int64_t g = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (g >= ngrp) return;  // whole block, before any barrier
+  const int64_t pos = g * GP + pl;
+  const bool active = pos < A.n;
+  const int64_t i = active ? (A.ord ? (int64_t)A.ord[pos] : pos) : A.n;
+  const int m = A.m;
+  const UT* U = reinterpret_cast<const UT*>(A.U);
+
+  // ---- conditioning rows and neighbor-row validation (per segment) ----
+  int idx = -1;
+  if (active && r < m) idx = A.nbr[i * m + r];
+  const bool valid = active && r < m && idx >= 0 && (int64_t)idx < i;
+  const unsigned long long vb = __ballot(valid);
+  const unsigned long long mmask = (1ull << m) - 1ull;
+  const unsigned long long bits = (vb >> sb) & mmask;
+  const int p = (int)__builtin_ctzll(~bits);
+  const unsigned long long badb = __ballot(active && r < m && idx != -1 && !valid);
+  if (active && r == 0 && m > 0) {
+    const bool bad_entry = ((badb >> sb) & mmask) != 0ull;
+    if (bad_entry || (bits >> p) != 0ull) flag_fail(A.bad_nbr, i);
+  }
+  const int q = p + 1;
+  const int64_t srow = !active ? -1 : (r < p ? (int64_t)idx : (r == p ? i : -1));
+  double xr = 0.0, yr = 0.0, tr = 0.0;
+  T yv = T(0);
+  if (srow >= 0) {
+    xr = A.sx[srow];
+    yr = A.sy[srow];
+    tr = A.t[srow];
+    if (A.y) yv = (T)A.y[srow];
+  }
+  sX[pl][r] = xr;
+  sY[pl][r] = yr;
+  sT[pl][r] = tr;
+  sIdx[pl][r] = (int)srow;
+  sSort[pl * ROWS + r] = srow >= 0 ? (int)srow : INT_MAX;
+  if (r == 0) sI[pl] = active ? i : -1;
+  __syncthreads();
+
+  // ---- union of the group's conditioning rows: bitonic sort, dedup ----
+  for (int kk = 2; kk <= NSLOT; kk <<= 1) {
+    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+      for (int e = tid; e < NSLOT; e += NTH) {
+        const int ptn = e ^ jj;
+        if (ptn > e) {
+          const int a0 = sSort[e], a1 = sSort[ptn];
+          const bool up = (e & kk) == 0;
+          if ((a0 > a1) == up) {
+            sSort[e] = a1;
+            sSort[ptn] = a0;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (wave == 0) {
+    int base = 0;
+    for (int c0 = 0; c0 < NSLOT; c0 += 64) {
+      const int e = c0 + lane;
+      const int v = sSort[e];
+      const bool f = v != INT_MAX && (e == 0 || sSort[e - 1] != v);
+      const unsigned long long bm = __ballot(f);
+      const int at = base + __popcll(bm & ((1ull << lane) - 1ull));
+      if (f) sUniq[at] = v;
+      base += __popcll(bm);
+    }
+    if (lane == 0) sNU = base;
+  }
+  __syncthreads();
+  const int nu = sNU;
+  for (int e = tid; e < NSLOT; e += NTH) {
+    const int v = sIdx[e / ROWS][e % ROWS];
+    int slot = -1;
+    if (v >= 0) {
+      int lo = 0, hi = nu - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sUniq[mid] < v) lo = mid + 1; else hi = mid;
+      }
+      slot = lo;
+    }
+    sSlot[e / ROWS][e % ROWS] = slot;
+  }
+  __syncthreads();
+
+  // Staged chunk width: as many columns as the union size allows in the staging
+  // area (wider chunks mean fewer barriers), and a divisor of the row length.
+  constexpr int CAP = NSLOT * SLD;  // elements of UT in the staging area
+  int cw = KC;
+  if (nu * (4 * KC + VPE) <= CAP && A.ldu % (4 * KC) == 0) cw = 4 * KC;
+  else if (nu * (2 * KC + VPE) <= CAP && A.ldu % (2 * KC) == 0) cw = 2 * KC;
+  const int sld = cw + VPE;
+  const int lppr = __builtin_ctz(cw / VPE);  // log2 of the 16-byte pieces per row and chunk
+  const int npieces = nu << lppr;
+  constexpr int MAXP = (CAP / VPE + NTH - 1) / NTH;
+  f4v pre[MAXP];
+  // Next chunk into registers (in flight while the current chunk is used) ...
+  auto load_regs = [&](int kc) __attribute__((always_inline)) {
+#pragma unroll
+    for (int j = 0; j < MAXP; ++j) {
+      const int e = tid + j * NTH;
+      if (e < npieces) {
+        const int row = e >> lppr, piece = e & ((1 << lppr) - 1);
+        pre[j] = *reinterpret_cast<const f4v*>(U + (int64_t)sUniq[row] * A.ldu + kc +
+                                                  piece * VPE);
+      }
+    }
+  };
+  // ... and from registers into the staging area.
+  auto store_regs = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int j = 0; j < MAXP; ++j) {
+      const int e = tid + j * NTH;
+      if (e < npieces) {
+        const int row = e >> lppr, piece = e & ((1 << lppr) - 1);
+        *reinterpret_cast<f4v*>(stage + row * sld + piece * VPE) = pre[j];
+      }
+    }
+  };
+
+  // ---- Grams on MFMA from the staged union rows ----
+  using AccT = typename std::conditional<PREC == 0, d4v, f4v>::type;
+  AccT acc[PPW][NTT];
+#pragma unroll
+  for (int s2 = 0; s2 < PPW; ++s2)
+#pragma unroll
+    for (int t = 0; t < NTT; ++t) acc[s2][t] = AccT{0, 0, 0, 0};
+  const int rr16 = lane & 15, kq = lane >> 4;
+  load_regs(0);
+  store_regs();
+  __syncthreads();
+  for (int kc = 0; kc < A.ldu; kc += cw) {
+    const bool more = kc + cw < A.ldu;
+    if (more) load_regs(kc + cw);
+    for (int sub = 0; sub < cw; sub += KC) {
 #pragma unroll
     for (int s2 = 0; s2 < PPW; ++s2) {
-      const int64_t ip = ((int64_t)blockIdx.x * kWPB + wave) * PPW + s2;
-      if (ip >= A.n) break;
-      const int* S = sIdx[wave][s2];
-      const T* bb = sB[wave][s2];
-      const T zs = __shfl(zi, s2 * ROWS);
-      for (int c = lane; c < A.ldu; c += 64) {
-        T accw = T(0);
-#pragma unroll 4
-        for (int rr = 0; rr < ROWS; ++rr) {
-          const int srr = S[rr];
-          if (srr < 0) break;
-          accw += bb[rr] * (T)U[(int64_t)srr * A.ldu + c];
+      const int pp = wave * PPW + s2;
+      if constexpr (PREC == 0) {
+        // 16 doubles per step: lane group kq holds elements 4kq..4kq+3 (K = 4 per MFMA).
+        double v[NT][4];
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti) {
+          const int sl = sSlot[pp][ti * 16 + rr16];
+          if (sl >= 0) {
+            const double2* src = reinterpret_cast<const double2*>(stage + sl * sld + sub + kq * 4);
+            const double2 x0 = src[0], x1 = src[1];
+            v[ti][0] = x0.x; v[ti][1] = x0.y; v[ti][2] = x1.x; v[ti][3] = x1.y;
+          } else {
+            v[ti][0] = v[ti][1] = v[ti][2] = v[ti][3] = 0.0;
+          }
         }
-        W[ip * A.ldu + c] = (c == A.k) ? (UT)zs : (UT)accw;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          int t = 0;
+#pragma unroll
+          for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+            for (int tj = 0; tj <= ti; ++tj) {
+              acc[s2][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[ti][c], v[tj][c], acc[s2][t], 0, 0, 0);
+              ++t;
+            }
+        }
+      } else {
+        // 32 floats per step: lane group kq holds elements 8kq..8kq+7.
+        float x[NT][8];
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti) {
+          const int sl = sSlot[pp][ti * 16 + rr16];
+          if (sl >= 0) {
+            const float4* src = reinterpret_cast<const float4*>(stage + sl * sld + sub + kq * 8);
+            const float4 a0 = src[0], a1 = src[1];
+            x[ti][0] = a0.x; x[ti][1] = a0.y; x[ti][2] = a0.z; x[ti][3] = a0.w;
+            x[ti][4] = a1.x; x[ti][5] = a1.y; x[ti][6] = a1.z; x[ti][7] = a1.w;
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) x[ti][e] = 0.f;
+          }
+        }
+        if constexpr (PREC == 1) {
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            int t = 0;
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+              for (int tj = 0; tj <= ti; ++tj) {
+                acc[s2][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[ti][c], x[tj][c], acc[s2][t], 0, 0, 0);
+                ++t;
+              }
+          }
+        } else {
+          constexpr int NS = PREC == 3 ? 3 : 2;
+          bf8v part[NT][NS];
+#pragma unroll
+          for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              float rem = x[ti][e];
+#pragma unroll
+              for (int sp = 0; sp < NS; ++sp) {
+                const __bf16 h = (__bf16)rem;
+                part[ti][sp][e] = h;
+                rem -= (float)h;
+              }
+            }
+          int t = 0;
+#pragma unroll
+          for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+            for (int tj = 0; tj <= ti; ++tj) {
+              if constexpr (NS == 3) {
+                acc[s2][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][2], part[tj][0], acc[s2][t], 0, 0, 0);
+                acc[s2][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][1], part[tj][1], acc[s2][t], 0, 0, 0);
+                acc[s2][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][0], part[tj][2], acc[s2][t], 0, 0, 0);
+              }
+              acc[s2][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][1], part[tj][0], acc[s2][t], 0, 0, 0);
+              acc[s2][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][0], part[tj][1], acc[s2][t], 0, 0, 0);
+              acc[s2][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][0], part[tj][0], acc[s2][t], 0, 0, 0);
+              ++t;
+            }
+        }
+      }
+    }
+    }
+    __syncthreads();
+    if (more) {
+      store_regs();
+      __syncthreads();
+    }
+  }
+  // Grams into LDS (the staging area is free now), full symmetric matrices.
+#pragma unroll
+  for (int s2 = 0; s2 < PPW; ++s2) {
+    T* G = sM + (wave * PPW + s2) * ROWS * ROWS;
+    int t = 0;
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int tj = 0; tj <= ti; ++tj) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = ti * 16 + (PREC == 0 ? mfma16_row_f64(lane, e) : mfma16_row_f32acc(lane, e));
+          const int col = tj * 16 + rr16;
+          G[row * ROWS + col] = acc[s2][t][e];
+          if (ti != tj) G[col * ROWS + row] = acc[s2][t][e];
+        }
+        ++t;
+      }
+  }
+  __syncthreads();
+
+  // ---- per-point residual block, Cholesky, back-substitution (segment) ----
+  T* M = sM + pl * ROWS * ROWS;
+  {
+    const int h = (r >= ROWS / 2) ? 1 : 0;
+    const int rp = r - h * (ROWS / 2);
+    const int R = ROWS - 1 - rp;
+#pragma unroll 1
+    for (int tt = 0; tt < ROWS / 2; ++tt) {
+      const int e = h + 2 * tt;
+      if (e < ROWS - 1) {
+        const int row = (e < rp) ? rp : R;
+        const int col = (e < rp) ? e : e - rp;
+        T val = T(0);
+        if (row < q) {
+          const double dx = sX[pl][row] - sX[pl][col];
+          const double dy = sY[pl][row] - sY[pl][col];
+          const double dt = sT[pl][row] - sT[pl][col];
+          val = cov_eval<T>(A.K, (T)dx, (T)dy, (T)dt) - M[row * ROWS + col];
+        }
+        M[row * ROWS + col] = val;
+        M[col * ROWS + row] = val;
+      }
+    }
+    T dg = T(1);
+    if (r < q) dg = T(A.K.sigma2 + A.K.nugget) - M[r * ROWS + r];
+    M[r * ROWS + r] = dg;
+  }
+  wave_lds_sync();
+  T a[ROWS];
+#pragma unroll
+  for (int j = 0; j < ROWS; ++j) a[j] = M[j * ROWS + r];
+  T Ldiag = T(1);
+  const bool ok = seg_cholesky<ROWS, T>(a, yv, Ldiag, r, sb, sCol[pl]);
+  if (active && r == 0 && !ok) flag_fail(A.fail, i);
+  const T Lpp_b = __shfl(Ldiag, sb + p);
+  const T zi = __shfl(yv, sb + p);
+  T x = T(0);
+  {
+    wave_lds_sync();
+#pragma unroll
+    for (int j = 0; j < ROWS; ++j) M[r * ROWS + j] = (j <= r) ? a[j] : T(0);
+    wave_lds_sync();
+    T accb = (r < p) ? M[p * ROWS + r] : T(0);
+    const T inv_diag = T(1) / Ldiag;
+#pragma unroll
+    for (int rr = ROWS - 1; rr >= 0; --rr) {
+      const T xr_local = accb * inv_diag;
+      const T xb = __shfl(xr_local, sb + rr);
+      if (r == rr) x = xb;
+      if (r < rr) accb -= M[rr * ROWS + r] * xb;
+    }
+    if (r >= p) x = T(0);
+  }
+  if constexpr (WANT_B) {
+    if (active) {
+      if (r < m) A.B[i * m + r] = (r < p) ? -(double)x : 0.0;
+      if (r == 0) A.D[i] = (double)Lpp_b * (double)Lpp_b;
+    }
+    return;
+  } else {
+    if (active && r == 0) A.logD[i] = 2.0 * log((double)Lpp_b);
+    // b_r = -x_r / L_pp (r < p), b_p = 1 / L_pp;  W_i = sum_r b_r U_{S_r}.
+    const T inv = T(1) / Lpp_b;
+    sBv[pl][r] = (r < p) ? -x * inv : (r == p ? inv : T(0));
+    if (r == 0) sZ[pl] = zi;
+    __syncthreads();
+
+    // ---- W rows from the staged union rows ----
+    UT* W = reinterpret_cast<UT*>(A.W);
+    load_regs(0);
+    store_regs();
+    __syncthreads();
+    for (int kc = 0; kc < A.ldu; kc += cw) {
+      const bool more = kc + cw < A.ldu;
+      if (more) load_regs(kc + cw);
+      for (int o = tid; o < GP * cw; o += NTH) {
+        const int pp = o / cw, c = o - (o / cw) * cw;
+        const int64_t ip = sI[pp];
+        if (ip < 0) continue;
+        T accw = T(0);
+#pragma unroll 8
+        for (int rr = 0; rr < ROWS; ++rr) {
+          const int sl = sSlot[pp][rr];
+          if (sl < 0) break;
+          accw += sBv[pp][rr] * (T)stage[sl * sld + c];
+        }
+        W[ip * A.ldu + kc + c] = (kc + c == A.k) ? (UT)sZ[pp] : (UT)accw;
+      }
+      __syncthreads();
+      if (more) {
+        store_regs();
+        __syncthreads();
       }
     }
   }
 }
 
 template <int ROWS, int PREC>
-hipError_t launch_rows(const FactorArgs& a, int mode, bool vif, hipStream_t s) {
+hipError_t launch_group(const FactorArgs& a, int mode, hipStream_t s) {
+  using Sh = GroupShape<ROWS, PREC>;
+  const int64_t ngrp = (a.n + Sh::GP - 1) / Sh::GP;
+  const unsigned grid = (unsigned)(((ngrp + 7) / 8) * 8);
+  if (mode == 1)
+    hipLaunchKernelGGL((vif_group_kernel<ROWS, true, PREC>), dim3(grid), dim3(64 * Sh::NW), 0, s,
+                       a);
+  else
+    hipLaunchKernelGGL((vif_group_kernel<ROWS, false, PREC>), dim3(grid), dim3(64 * Sh::NW), 0,
+                       s, a);
+  return hipGetLastError();
+}
+
+template <int ROWS, int PREC>
+hipError_t launch_rows(const FactorArgs& a, int mode, hipStream_t s) {
   constexpr int PPW = 64 / ROWS;
   constexpr int kWPB = wpb<ROWS>();
   const int64_t per_block = (int64_t)kWPB * PPW;
-  const unsigned grid = (unsigned)((a.n + per_block - 1) / per_block);
-  if (vif) {
-    if (mode == 1)
-      hipLaunchKernelGGL((point_factor_kernel<ROWS, true, true, PREC>), dim3(grid),
-                         dim3(64 * kWPB), 0, s, a);
-    else
-      hipLaunchKernelGGL((point_factor_kernel<ROWS, true, false, PREC>), dim3(grid),
-                         dim3(64 * kWPB), 0, s, a);
-  } else {
-    if (mode == 1)
-      hipLaunchKernelGGL((point_factor_kernel<ROWS, false, true, PREC>), dim3(grid),
-                         dim3(64 * kWPB), 0, s, a);
-    else
-      hipLaunchKernelGGL((point_factor_kernel<ROWS, false, false, PREC>), dim3(grid),
-                         dim3(64 * kWPB), 0, s, a);
-  }
+  const int64_t nblk = (a.n + per_block - 1) / per_block;
+  const unsigned grid = (unsigned)(((nblk + 7) / 8) * 8);
+  if (mode == 1)
+    hipLaunchKernelGGL((point_factor_kernel<ROWS, true, PREC>), dim3(grid), dim3(64 * kWPB), 0, s,
+                       a);
+  else
+    hipLaunchKernelGGL((point_factor_kernel<ROWS, false, PREC>), dim3(grid), dim3(64 * kWPB), 0,
+                       s, a);
   return hipGetLastError();
 }
 
 template <int PREC>
 hipError_t launch_prec(const FactorArgs& a, int mode, hipStream_t s) {
-  const bool vif = a.k > 0;
   const int q = a.m + 1;
-  if (q <= 16) return launch_rows<16, PREC>(a, mode, vif, s);
-  if (q <= 32) return launch_rows<32, PREC>(a, mode, vif, s);
-  return launch_rows<64, PREC>(a, mode, vif, s);
+  if (a.k > 0) {
+    if (q <= 16) return launch_group<16, PREC>(a, mode, s);
+    if (q <= 32) return launch_group<32, PREC>(a, mode, s);
+    return launch_group<64, PREC>(a, mode, s);
+  }
+  if (q <= 16) return launch_rows<16, PREC>(a, mode, s);
+  if (q <= 32) return launch_rows<32, PREC>(a, mode, s);
+  return launch_rows<64, PREC>(a, mode, s);
 }
 
 }  // namespace
