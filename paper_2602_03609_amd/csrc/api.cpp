@@ -86,7 +86,7 @@ void prof_collect() {
 int kpad_of(int k) { return k > 0 ? ((k + 1 + 63) / 64) * 64 : 0; }
 
 struct Layout {
-  size_t flags = 0, out = 0, part = 0, sums = 0, logD = 0, z = 0, Sk = 0, P = 0, U = 0, W = 0,
+  size_t flags = 0, out = 0, part = 0, sums = 0, logD = 0, z = 0, Sk = 0, P = 0, Pb = 0, U = 0, W = 0,
          syrk = 0, M = 0, q = 0, dscr = 0, tab1 = 0, tab2 = 0, bnd = 0, bbox = 0, counts = 0,
          fill = 0, bsum = 0, key = 0, px = 0, py = 0, pidx = 0, total = 0;
   int kpad = 0, splits = 0;
@@ -144,13 +144,13 @@ Layout make_layout(int64_t n, int m, int k, int prec, int op) {
     const size_t kk = (size_t)L.kpad * L.kpad;
     L.Sk = take(sizeof(double) * kk);
     L.P = take(sizeof(double) * kk);
+    if (prec >= VIF_PREC_BF16X3) L.Pb = take(4 * kk);
     L.dscr = take(sizeof(double) * 64 * 64);
     L.U = take(es * (size_t)n * L.kpad);
     if (op == VIF_OP_NLL) {
       L.W = take(es * (size_t)n * L.kpad);
-      L.splits = vif::syrk_splits(n, L.kpad);
-      const int nt = L.kpad / 64;
-      L.syrk = take(sizeof(double) * (size_t)L.splits * (nt * (nt + 1) / 2) * 64 * 64);
+      L.splits = vif::syrk_chunks(n, L.kpad, prec);
+      L.syrk = take(vif::syrk_part_bytes(n, L.kpad, prec));
       L.M = take(sizeof(double) * kk);
       L.q = take(sizeof(double) * L.kpad);
     }
@@ -347,6 +347,13 @@ int32_t run_lowrank(const vif_points* p, const vif_points* ind, const vif_kernel
   HIPCHK(vif::launch_cholesky(L.kpad, Sk, reinterpret_cast<double*>(ws + L.dscr), fl + 1, s));
   HIPCHK(vif::launch_trinv(L.kpad, Sk, P, s));
   PROF(VIF_STAGE_SIGMA_K, true);
+  if (prec >= VIF_PREC_BF16X3 && vif::lowrank_fused_ok(L.kpad)) {
+    // Cross-covariance evaluated on chip inside the product.
+    PROF(VIF_STAGE_TRMM, false);
+    HIPCHK(vif::launch_lowrank_fused(a, P, ws + L.Pb, reinterpret_cast<float*>(ws + L.U), s));
+    PROF(VIF_STAGE_TRMM, true);
+    return VIF_OK;
+  }
   PROF(VIF_STAGE_CROSSCOV, false);
   HIPCHK(vif::launch_crosscov(a, ws + L.U, prec, s));
   PROF(VIF_STAGE_CROSSCOV, true);
@@ -407,14 +414,14 @@ int32_t nll_impl(const vif_points* p, const double* y, const vif_kernel* kern, i
     PROF(VIF_STAGE_POINT_FACTOR, false);
     HIPCHK(vif::launch_point_factor(fa, 0, prec, s));
     PROF(VIF_STAGE_POINT_FACTOR, true);
-    double* syrk = reinterpret_cast<double*>(ws + L.syrk);
+    void* syrk = ws + L.syrk;
     double* M = reinterpret_cast<double*>(ws + L.M);
     double* q = reinterpret_cast<double*>(ws + L.q);
     PROF(VIF_STAGE_SYRK, false);
     HIPCHK(vif::launch_syrk(p->n, L.kpad, ws + L.W, prec, syrk, L.splits, s));
     PROF(VIF_STAGE_SYRK, true);
     PROF(VIF_STAGE_ASSEMBLY, false);
-    HIPCHK(vif::launch_syrk_reduce(k, L.kpad, syrk, L.splits, M, q, sums + 1, s));
+    HIPCHK(vif::launch_syrk_reduce(k, L.kpad, syrk, prec, L.splits, M, q, sums + 1, s));
     HIPCHK(vif::launch_cholesky(L.kpad, M, reinterpret_cast<double*>(ws + L.dscr), fl + 2, s));
     HIPCHK(vif::launch_sum(p->n, fa.logD, 0, part, sums + 0, s));
     HIPCHK(vif::launch_finalize(p->n, k, L.kpad, M, q, sums + 0, sums + 1, out, s));

@@ -94,12 +94,21 @@ hipError_t launch_trinv(int N, const double* L, double* P, hipStream_t s);
 hipError_t launch_crosscov(const LowRankArgs& a, void* U, int prec, hipStream_t s);
 // In place: U[i, :] <- U[i, :] P^T with P lower triangular (U = C(X,Z) L_k^-T).
 hipError_t launch_trmm(const LowRankArgs& a, const double* P, void* U, int prec, hipStream_t s);
-// Partial Gram of W over row chunks: part[s][tile] = sum over rows of chunk s of W_I' W_J.
-int syrk_splits(int64_t n, int kpad);
-hipError_t launch_syrk(int64_t n, int kpad, const void* W, int prec, double* part, int splits,
+// Split-BF16 modes, kpad small enough for 32 rows of C in LDS (lowrank_fused_ok):
+// U = C(X, Z) P' in one pass, C evaluated on chip; Pb: 2 * kpad^2 bfloat16 scratch.
+bool lowrank_fused_ok(int kpad);
+hipError_t launch_lowrank_fused(const LowRankArgs& a, const double* P, void* Pb, float* U,
+                                hipStream_t s);
+// Partial Gram of W over row chunks: part[c][tile] = sum over the rows of chunk c
+// of W_I' W_J (FP64 64 x 64 tiles for prec 0/1, FP32 128 x 128 tiles for the
+// split-BF16 modes). syrk_chunks gives the chunk count, syrk_part_bytes the size
+// of part.
+int syrk_chunks(int64_t n, int kpad, int prec);
+size_t syrk_part_bytes(int64_t n, int kpad, int prec);
+hipError_t launch_syrk(int64_t n, int kpad, const void* W, int prec, void* part, int nchunk,
                        hipStream_t s);
-// M = I + (sum_s part[s])[0:k,0:k] with identity padding; q = column k; zz = entry (k,k).
-hipError_t launch_syrk_reduce(int k, int kpad, const double* part, int splits, double* M,
+// M = I + (sum_c part[c])[0:k,0:k] with identity padding; q = column k; zz = entry (k,k).
+hipError_t launch_syrk_reduce(int k, int kpad, const void* part, int prec, int nchunk, double* M,
                               double* q, double* zz, hipStream_t s);
 
 // ---- reductions and final assembly ------------------------------------------

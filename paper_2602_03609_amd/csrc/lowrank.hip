@@ -11,8 +11,10 @@
 //  * U: the cross-covariance is generated straight into U's buffer, then
 //    multiplied in place by P' = L_k^-T one 64-row tile per workgroup, column
 //    blocks right to left (block J needs C columns <= J only), on MFMA.
-//  * M: split-K Gram of [W | z] over row chunks into FP64 partial tiles (MFMA),
-//    reduced in a fixed order (deterministic; no floating-point atomics).
+//  * M: split-K Gram of [W | z] over row chunks into partial tiles on MFMA
+//    (FP64 tiles for the FP64/FP32 modes; for the split-BF16 modes, 128 x 128
+//    FP32 tiles over 4096-row chunks from operands split once at staging),
+//    reduced in FP64 in a fixed order (deterministic; no floating-point atomics).
 #include <math.h>
 
 #include <type_traits>
@@ -45,38 +47,66 @@ __global__ void cov_kk_kernel(LowRankArgs A, double* __restrict__ S) {
 }
 
 // ---------------------------------------------------------------- Cholesky ---
+// Solves T y = b (T lower triangular 64 x 64 in LDS) for 64 right-hand sides at
+// once, all in registers: lanes 4s..4s+3 hold right-hand side s, lane 4s + g
+// holding entries g, g + 4, ..., g + 60 in v[]. Column r of the elimination is
+// broadcast from its owner lane with a shuffle; no barriers.
+__device__ __forceinline__ void tri_solve_regs(double v[16], const double (*T)[NB + 1], int g,
+                                               int lane) {
+#pragma unroll
+  for (int r = 0; r < NB; ++r) {
+    const int go = r & 3, io = r >> 2;
+    double y = v[io] / T[r][r];
+    y = __shfl(y, (lane & ~3) | go);
+    if (g == go) v[io] = y;
+#pragma unroll
+    for (int i = io; i < 16; ++i) {
+      if (i > io || g > go) v[i] -= T[g + 4 * i][r] * y;
+    }
+  }
+}
+
 // Panel kernel: block w factors the diagonal block jb (redundantly) and, for
 // w > 0, solves row block jb + w of the panel against it.
 __global__ __launch_bounds__(256) void chol_panel_kernel(int N, double* __restrict__ A, int jb,
                                                          unsigned long long* fail,
                                                          double* __restrict__ dscr) {
   __shared__ double Ld[NB][NB + 1];
-  __shared__ double X[NB][NB + 1];
   __shared__ int bad;
   const int tid = threadIdx.x;
   const int w = blockIdx.x;
   const int64_t d0 = (int64_t)jb * NB;
+  const int lane = tid & 63, s = tid >> 2, g = tid & 3;
+  // Row s of the panel block (w > 0), entries g + 4i, loaded before the factorisation.
+  double v[16];
+  if (w > 0) {
+    const int64_t r0 = (int64_t)(jb + w) * NB;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = A[(r0 + s) * N + d0 + g + 4 * i];
+  }
   if (tid == 0) bad = -1;
   for (int e = tid; e < NB * NB; e += 256) {
-    int r = e / NB, c = e % NB;
+    const int r = e / NB, c = e % NB;
     Ld[r][c] = (c <= r) ? A[(d0 + r) * N + d0 + c] : 0.0;
   }
   __syncthreads();
+  // Right-looking factorisation of the diagonal block; thread (r = tid & 63)
+  // updates row r, columns c = kk + 1 + (tid >> 6) + 4j <= r.
+  const int ur = tid & 63, uc = tid >> 6;
   for (int kk = 0; kk < NB; ++kk) {
+    double d = Ld[kk][kk];
+    const bool okp = d > 0.0 && d < INFINITY;
+    const double piv = okp ? sqrt(d) : 1.0;
+    __syncthreads();
     if (tid == 0) {
-      double d = Ld[kk][kk];
-      if (!(d > 0.0) || !(d < INFINITY)) {
-        if (bad < 0) bad = kk;
-        d = 1.0;
-      }
-      Ld[kk][kk] = sqrt(d);
+      if (!okp && bad < 0) bad = kk;
+      Ld[kk][kk] = piv;
     }
+    if (tid > kk && tid < NB) Ld[tid][kk] /= piv;
     __syncthreads();
-    if (tid > kk && tid < NB) Ld[tid][kk] /= Ld[kk][kk];
-    __syncthreads();
-    for (int e = tid; e < NB * NB; e += 256) {
-      int r = e / NB, c = e % NB;
-      if (c > kk && r >= c) Ld[r][c] -= Ld[r][kk] * Ld[c][kk];
+    if (ur > kk) {
+      const double lr = Ld[ur][kk];
+      for (int c = kk + 1 + uc; c <= ur; c += 4) Ld[ur][c] -= lr * Ld[c][kk];
     }
     __syncthreads();
   }
@@ -85,31 +115,16 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(int N, double* __restri
     // so the factor goes to scratch; the update launch copies it into place.
     if (tid == 0 && bad >= 0) atomicMin(fail, (unsigned long long)(d0 + bad));
     for (int e = tid; e < NB * NB; e += 256) {
-      int r = e / NB, c = e % NB;
+      const int r = e / NB, c = e % NB;
       dscr[e] = (c <= r) ? Ld[r][c] : 0.0;
     }
     return;
   }
+  // X L' = A_panel, i.e. L x = a for each row a of the panel block.
+  tri_solve_regs(v, Ld, g, lane);
   const int64_t r0 = (int64_t)(jb + w) * NB;
-  for (int e = tid; e < NB * NB; e += 256) {
-    int r = e / NB, c = e % NB;
-    X[r][c] = A[(r0 + r) * N + d0 + c];
-  }
-  __syncthreads();
-  // X L' = A_panel: row r independent; column c sequential.
-  if (tid < NB) {
-    const int r = tid;
-    for (int c = 0; c < NB; ++c) {
-      double s = X[r][c];
-      for (int cp = 0; cp < c; ++cp) s -= X[r][cp] * Ld[c][cp];
-      X[r][c] = s / Ld[c][c];
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < NB * NB; e += 256) {
-    int r = e / NB, c = e % NB;
-    A[(r0 + r) * N + d0 + c] = X[r][c];
-  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) A[(r0 + s) * N + d0 + g + 4 * i] = v[i];
 }
 
 // Trailing update of tile (IB, JB), jb < JB <= IB: A_IJ -= L_I,jb L_J,jb'.
@@ -208,19 +223,15 @@ __global__ __launch_bounds__(256) void trinv_kernel(int N, const double* __restr
       Ta[r][c] = L[(r0 + r) * N + r0 + c];  // diagonal block
     }
     __syncthreads();
-    // Forward substitution, one column per thread.
-    if (tid < NB) {
-      const int c = tid;
-      for (int r = 0; r < NB; ++r) {
-        double s = R[r][c];
-        for (int rp = 0; rp < r; ++rp) s -= Ta[r][rp] * R[rp][c];
-        R[r][c] = s / Ta[r][r];
-      }
-    }
-    __syncthreads();
-    for (int e = tid; e < NB * NB; e += 256) {
-      int r = e / NB, c = e % NB;
-      P[(r0 + r) * N + c0 + c] = R[r][c];
+    // Forward substitution of the 64 columns of R, in registers.
+    {
+      const int lane = tid & 63, sc = tid >> 2, g = tid & 3;
+      double v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = R[g + 4 * i][sc];
+      tri_solve_regs(v, Ta, g, lane);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) P[(r0 + g + 4 * i) * N + c0 + sc] = v[i];
     }
   }
 }
@@ -405,6 +416,125 @@ __global__ __launch_bounds__(256) void trmm_f32_kernel(int64_t n, int kpad, floa
   }
 }
 
+// ------------------------------------------- U = C(X, Z) P' fused (split-BF16) ----
+// P = L_k^-1 in FP32-rounded bfloat16 pairs (h, l): P ~ h + l.
+__global__ __launch_bounds__(256) void split_p_kernel(int64_t total, const double* __restrict__ P,
+                                                      __bf16* __restrict__ Ph,
+                                                      __bf16* __restrict__ Pl) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const float x = (float)P[e];
+  const __bf16 h = (__bf16)x;
+  Ph[e] = h;
+  Pl[e] = (__bf16)(x - (float)h);
+}
+
+// One block per 32 rows of X: the rows' cross-covariances C(x_i, z_l), l < kpad,
+// are evaluated once into LDS as bfloat16 pairs, then U_i,j = sum_{l <= j} C_i,l
+// P_j,l for all j on MFMA (3 products: hh, hl, lh), P streamed from L2. C never
+// goes to HBM; U is written once.
+constexpr int URB = 32;
+constexpr int UPAD = 8;
+
+__global__ __launch_bounds__(512) void lowrank_u_kernel(LowRankArgs A, const __bf16* __restrict__ Ph,
+                                                        const __bf16* __restrict__ Pl,
+                                                        float* __restrict__ U) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int kpad = A.kpad;
+  const int ldc = kpad + UPAD;
+  __bf16* Ch = reinterpret_cast<__bf16*>(smem);
+  __bf16* Cl = Ch + URB * ldc;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * URB;
+
+  // ---- C rows into LDS: thread -> 8 consecutive columns x 8 rows ----
+  {
+    const int ncg = kpad / 8;  // column groups
+    for (int task = tid; task < ncg * (URB / 8); task += 512) {
+      const int cg = task % ncg, rg = task / ncg;
+      double zx[8], zy[8], zt[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int l = cg * 8 + c;
+        const bool ok = l < A.k;
+        zx[c] = ok ? A.zx[l] : 0.0;
+        zy[c] = ok ? A.zy[l] : 0.0;
+        zt[c] = ok ? A.zt[l] : 0.0;
+      }
+#pragma unroll 1
+      for (int rr = 0; rr < 8; ++rr) {
+        const int row = rg * 8 + rr;
+        const int64_t i = i0 + row;
+        bf8v h8, l8;
+        if (i < A.n) {
+          const double xi = A.sx[i], yi = A.sy[i], ti = A.t[i];
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            const int l = cg * 8 + c;
+            float v = 0.f;
+            if (l < A.k)
+              v = cov_eval<float>(A.K, (float)(xi - zx[c]), (float)(yi - zy[c]), (float)(ti - zt[c]));
+            const __bf16 h = (__bf16)v;
+            h8[c] = h;
+            l8[c] = (__bf16)(v - (float)h);
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            h8[c] = (__bf16)0.f;
+            l8[c] = (__bf16)0.f;
+          }
+        }
+        *reinterpret_cast<bf8v*>(Ch + row * ldc + cg * 8) = h8;
+        *reinterpret_cast<bf8v*>(Cl + row * ldc + cg * 8) = l8;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- U = C P' on MFMA: wave -> column blocks of 16 (snake order for balance) ----
+  const int ncb = kpad / 16;
+  const int g = lane >> 4, j = lane & 15;
+  for (int pass = 0; pass * 8 < ncb; ++pass) {
+    const int cb = pass * 8 + ((pass & 1) ? 7 - wave : wave);
+    if (cb >= ncb) continue;
+    const int jrow = cb * 16 + j;  // output column = row of P
+    const __bf16* ph = Ph + (int64_t)jrow * kpad + 8 * g;
+    const __bf16* pl = Pl + (int64_t)jrow * kpad + 8 * g;
+    const int kend = cb * 16 + 16;  // P_j,l = 0 for l > j
+    f4v acc0 = f4v{0.f, 0.f, 0.f, 0.f}, acc1 = f4v{0.f, 0.f, 0.f, 0.f};
+    bf8v bh = *reinterpret_cast<const bf8v*>(ph);
+    bf8v bl = *reinterpret_cast<const bf8v*>(pl);
+    for (int k0 = 0; k0 < kend; k0 += 32) {
+      bf8v nh = bh, nl = bl;
+      if (k0 + 32 < kend) {
+        nh = *reinterpret_cast<const bf8v*>(ph + k0 + 32);
+        nl = *reinterpret_cast<const bf8v*>(pl + k0 + 32);
+      }
+      const int ko = k0 + 8 * g;
+      const bf8v a0h = *reinterpret_cast<const bf8v*>(Ch + j * ldc + ko);
+      const bf8v a0l = *reinterpret_cast<const bf8v*>(Cl + j * ldc + ko);
+      const bf8v a1h = *reinterpret_cast<const bf8v*>(Ch + (16 + j) * ldc + ko);
+      const bf8v a1l = *reinterpret_cast<const bf8v*>(Cl + (16 + j) * ldc + ko);
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0l, bh, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1l, bh, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0h, bl, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1h, bl, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0h, bh, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1h, bh, acc1, 0, 0, 0);
+      bh = nh;
+      bl = nl;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = mfma16_row_f32acc(lane, e);
+      const int64_t ia = i0 + r, ib = i0 + 16 + r;
+      if (ia < A.n) U[ia * kpad + jrow] = acc0[e];
+      if (ib < A.n) U[ib * kpad + jrow] = acc1[e];
+    }
+  }
+}
+
 // ------------------------------------------------------------------- SYRK ----
 __device__ __forceinline__ void tile_of(int t, int& TI, int& TJ) {
   TI = 0;
@@ -585,6 +715,165 @@ __global__ __launch_bounds__(256) void syrk_kernel(int64_t n, int kpad, const vo
       }
 }
 
+// Split-BF16 Gram of W over 4096-row chunks, FP32 partial tiles of 128 x 128.
+//
+// W (FP32) is split once, when staged, into NS bfloat16 terms (x = h + m [+ l]);
+// LDS holds each term transposed to [8-row group][column][8 rows], so that one
+// 16-byte read is one lane's MFMA operand (the K order inside a 32-row step is
+// the same for both operands, which is all a Gram needs). Products of the terms
+// (3 for NS = 2, 6 for NS = 3), smallest first, accumulate in FP32 over the
+// chunk; the partials are summed in FP64 by syrk_split_reduce_kernel.
+// Blocks are dealt to the 8 XCDs round-robin; XCD x runs the tiles of chunks
+// x, x + 8, ... one chunk after the other, so that the tiles sharing a chunk's
+// rows run together and find them in that XCD's L2.
+constexpr int TB = 128;    // output tile
+constexpr int CHR = 4096;  // rows per chunk (one FP32 accumulation)
+constexpr int SBK = 32;    // rows per step (the bf16 MFMA K)
+
+template <int NS>
+__global__ __launch_bounds__(256) void syrk_split_kernel(int64_t n, int kpad,
+                                                         const float* __restrict__ W,
+                                                         float* __restrict__ part, int nchunk,
+                                                         int ntile) {
+  __shared__ bf8v sP[2][2][NS][SBK / 8][TB];
+  const int x = blockIdx.x & 7;
+  const int l = blockIdx.x >> 3;
+  const int c = (l / ntile) * 8 + x;
+  const int t = l - (l / ntile) * ntile;
+  if (c >= nchunk) return;  // whole block, before any barrier
+  int TI, TJ;
+  tile_of(t, TI, TJ);
+  const bool diag = TI == TJ;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  // On a diagonal tile the upper-right quarter is the transpose of the lower-left.
+  const bool skip = diag && wr < wc;
+  const int64_t rbeg = (int64_t)c * CHR;
+  const int64_t rend = rbeg + CHR < n ? rbeg + CHR : n;
+  const int lc = tid & (TB - 1);
+  const int lg = (tid >> 7) * 2;
+  const int colA = TI * TB + lc, colB = TJ * TB + lc;
+  const bool okA = colA < kpad, okB = !diag && colB < kpad;
+  float ra[16], rb[16];
+  auto load = [&](int64_t r0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int64_t row = r0 + lg * 8 + e;
+      ra[e] = (row < rend && okA) ? W[row * kpad + colA] : 0.f;
+      rb[e] = (row < rend && okB) ? W[row * kpad + colB] : 0.f;
+    }
+  };
+  auto split_store = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      bf8v pa[NS], pb[NS];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        float xa = ra[h * 8 + e], xb = rb[h * 8 + e];
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) {
+          const __bf16 ha = (__bf16)xa, hb = (__bf16)xb;
+          pa[sp][e] = ha;
+          pb[sp][e] = hb;
+          xa -= (float)ha;
+          xb -= (float)hb;
+        }
+      }
+#pragma unroll
+      for (int sp = 0; sp < NS; ++sp) {
+        sP[buf][0][sp][lg + h][lc] = pa[sp];
+        if (!diag) sP[buf][1][sp][lg + h][lc] = pb[sp];
+      }
+    }
+  };
+
+  f4v acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f4v{0.f, 0.f, 0.f, 0.f};
+  const int g = lane >> 4, j = lane & 15;
+  const int sb = diag ? 0 : 1;
+  const int nsteps = (int)((rend - rbeg + SBK - 1) / SBK);
+  if (nsteps > 0) {
+    load(rbeg);
+    split_store(0);
+  }
+  __syncthreads();
+  for (int st = 0; st < nsteps; ++st) {
+    const int buf = st & 1;
+    const bool more = st + 1 < nsteps;
+    if (more) load(rbeg + (int64_t)(st + 1) * SBK);
+    if (!skip) {
+      bf8v av[4][NS], bv[4][NS];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) av[a][sp] = sP[buf][0][sp][g][wr * 64 + a * 16 + j];
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) bv[b][sp] = sP[buf][sb][sp][g][wc * 64 + b * 16 + j];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          if constexpr (NS == 3) {
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a][2], bv[b][0], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a][1], bv[b][1], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a][0], bv[b][2], acc[a][b], 0, 0, 0);
+          }
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a][1], bv[b][0], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a][0], bv[b][1], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a][0], bv[b][0], acc[a][b], 0, 0, 0);
+        }
+    }
+    if (more) split_store(buf ^ 1);
+    __syncthreads();
+  }
+  if (skip) return;
+  float* out = part + ((int64_t)c * ntile + t) * (TB * TB);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = wr * 64 + a * 16 + mfma16_row_f32acc(lane, e);
+        const int col = wc * 64 + b * 16 + j;
+        out[row * TB + col] = acc[a][b][e];
+      }
+}
+
+// M = I + sum over chunks (FP64, fixed order) of the lower tiles, q = row k, zz = (k, k).
+__global__ __launch_bounds__(256) void syrk_split_reduce_kernel(int k, int kpad,
+                                                                const float* __restrict__ part,
+                                                                int nchunk, int ntile,
+                                                                double* __restrict__ M,
+                                                                double* __restrict__ q,
+                                                                double* __restrict__ zz) {
+  constexpr int PER = TB * TB / 256;  // blocks per tile
+  const int t = blockIdx.x / PER;
+  const int e = (blockIdx.x - t * PER) * 256 + threadIdx.x;
+  int TI, TJ;
+  tile_of(t, TI, TJ);
+  const int er = e / TB, ec = e - (e / TB) * TB;
+  const int es = (TI == TJ && er < ec) ? ec * TB + er : e;
+  const float* src = part + (int64_t)t * (TB * TB) + es;
+  const int64_t stride = (int64_t)ntile * (TB * TB);
+  double s = 0.0;
+#pragma unroll 8
+  for (int cc = 0; cc < nchunk; ++cc) s += (double)src[cc * stride];
+  const int r = TI * TB + er, col = TJ * TB + ec;
+  if (r < kpad && col < kpad) {
+    double v = (r == col) ? 1.0 : 0.0;
+    if (r < k && col < k) v += s;
+    M[(int64_t)r * kpad + col] = v;
+  }
+  if (r == k && col < k) q[col] = s;
+  if (r == k && col == k) *zz = s;
+}
+
 __global__ void syrk_reduce_kernel(int k, int kpad, const double* __restrict__ part, int splits,
                                    int ntile, double* __restrict__ M, double* __restrict__ q,
                                    double* __restrict__ zz) {
@@ -637,6 +926,27 @@ hipError_t launch_crosscov(const LowRankArgs& a, void* U, int prec, hipStream_t 
   return hipGetLastError();
 }
 
+size_t lowrank_fused_lds(int kpad) { return (size_t)2 * URB * (kpad + UPAD) * sizeof(__bf16); }
+
+bool lowrank_fused_ok(int kpad) { return lowrank_fused_lds(kpad) <= 160 * 1024; }
+
+hipError_t launch_lowrank_fused(const LowRankArgs& a, const double* P, void* Pb, float* U,
+                                hipStream_t s) {
+  const int64_t kk = (int64_t)a.kpad * a.kpad;
+  __bf16* Ph = reinterpret_cast<__bf16*>(Pb);
+  __bf16* Pl = Ph + kk;
+  hipLaunchKernelGGL(split_p_kernel, dim3((unsigned)((kk + 255) / 256)), dim3(256), 0, s, kk, P,
+                     Ph, Pl);
+  const size_t lds = lowrank_fused_lds(a.kpad);
+  hipError_t e = hipFuncSetAttribute((const void*)lowrank_u_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const unsigned grid = (unsigned)((a.n + URB - 1) / URB);
+  hipLaunchKernelGGL(lowrank_u_kernel, dim3(grid), dim3(512), lds, s, a, (const __bf16*)Ph,
+                     (const __bf16*)Pl, U);
+  return hipGetLastError();
+}
+
 hipError_t launch_trmm(const LowRankArgs& a, const double* P, void* U, int prec, hipStream_t s) {
   const unsigned g2 = (unsigned)((a.n + 63) / 64);
   if (prec == 0)
@@ -650,30 +960,59 @@ hipError_t launch_trmm(const LowRankArgs& a, const double* P, void* U, int prec,
   return hipGetLastError();
 }
 
-int syrk_splits(int64_t, int) { return 8; }
+namespace {
+int syrk_ntile(int kpad, int tb) {
+  const int nt = (kpad + tb - 1) / tb;
+  return nt * (nt + 1) / 2;
+}
+}  // namespace
 
-hipError_t launch_syrk(int64_t n, int kpad, const void* W, int prec, double* part, int splits,
+int syrk_chunks(int64_t n, int, int prec) {
+  if (prec <= 1) return 8;
+  const int64_t c = (n + CHR - 1) / CHR;
+  return (int)(((c + 7) / 8) * 8);
+}
+
+size_t syrk_part_bytes(int64_t n, int kpad, int prec) {
+  const size_t c = (size_t)syrk_chunks(n, kpad, prec);
+  if (prec <= 1) return sizeof(double) * c * syrk_ntile(kpad, NB) * NB * NB;
+  return sizeof(float) * c * syrk_ntile(kpad, TB) * TB * TB;
+}
+
+hipError_t launch_syrk(int64_t n, int kpad, const void* W, int prec, void* part, int nchunk,
                        hipStream_t s) {
-  const int nt = kpad / NB;
-  const int ntile = nt * (nt + 1) / 2;
-  dim3 grid(ntile * splits);
+  if (prec >= 2) {
+    const int ntile = syrk_ntile(kpad, TB);
+    dim3 grid((unsigned)(ntile * nchunk));
+    if (prec == 2)
+      hipLaunchKernelGGL(syrk_split_kernel<2>, grid, dim3(256), 0, s, n, kpad,
+                         (const float*)W, (float*)part, nchunk, ntile);
+    else
+      hipLaunchKernelGGL(syrk_split_kernel<3>, grid, dim3(256), 0, s, n, kpad,
+                         (const float*)W, (float*)part, nchunk, ntile);
+    return hipGetLastError();
+  }
+  const int ntile = syrk_ntile(kpad, NB);
+  dim3 grid(ntile * nchunk);
+  double* pd = (double*)part;
   if (prec == 0)
-    hipLaunchKernelGGL(syrk_kernel<0>, grid, dim3(256), 0, s, n, kpad, W, part, splits, ntile);
-  else if (prec == 1)
-    hipLaunchKernelGGL(syrk_kernel<1>, grid, dim3(256), 0, s, n, kpad, W, part, splits, ntile);
-  else if (prec == 2)
-    hipLaunchKernelGGL(syrk_kernel<2>, grid, dim3(256), 0, s, n, kpad, W, part, splits, ntile);
+    hipLaunchKernelGGL(syrk_kernel<0>, grid, dim3(256), 0, s, n, kpad, W, pd, nchunk, ntile);
   else
-    hipLaunchKernelGGL(syrk_kernel<3>, grid, dim3(256), 0, s, n, kpad, W, part, splits, ntile);
+    hipLaunchKernelGGL(syrk_kernel<1>, grid, dim3(256), 0, s, n, kpad, W, pd, nchunk, ntile);
   return hipGetLastError();
 }
 
-hipError_t launch_syrk_reduce(int k, int kpad, const double* part, int splits, double* M,
+hipError_t launch_syrk_reduce(int k, int kpad, const void* part, int prec, int nchunk, double* M,
                               double* q, double* zz, hipStream_t s) {
-  const int nt = kpad / NB;
-  const int ntile = nt * (nt + 1) / 2;
-  hipLaunchKernelGGL(syrk_reduce_kernel, dim3(ntile), dim3(256), 0, s, k, kpad, part, splits,
-                     ntile, M, q, zz);
+  if (prec >= 2) {
+    const int ntile = syrk_ntile(kpad, TB);
+    hipLaunchKernelGGL(syrk_split_reduce_kernel, dim3((unsigned)(ntile * (TB * TB / 256))),
+                       dim3(256), 0, s, k, kpad, (const float*)part, nchunk, ntile, M, q, zz);
+    return hipGetLastError();
+  }
+  const int ntile = syrk_ntile(kpad, NB);
+  hipLaunchKernelGGL(syrk_reduce_kernel, dim3(ntile), dim3(256), 0, s, k, kpad,
+                     (const double*)part, nchunk, ntile, M, q, zz);
   return hipGetLastError();
 }
 

@@ -231,7 +231,9 @@ struct GroupShape {
   using T = typename PrecT<PREC>::T;
   static constexpr int PPW = 64 / ROWS;
   static constexpr int NW0 = (int)(65536 / (PPW * ROWS * ROWS * sizeof(T)));
-  static constexpr int NW = NW0 > 8 ? 8 : NW0;   // wavefronts per workgroup
+  static constexpr int NW1 = NW0 > 8 ? 8 : NW0;
+  // At most 16 points: the W product runs the group as the 16 rows of an MFMA tile.
+  static constexpr int NW = NW1 * PPW > 16 ? 16 / PPW : NW1;  // wavefronts per workgroup
   static constexpr int GP = NW * PPW;            // points per workgroup
   static constexpr int NSLOT = GP * ROWS;        // conditioning rows (union upper bound)
 };
@@ -248,9 +250,12 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
   constexpr int SLD = KC + VPE;               // LDS row stride (elements), 16-byte aligned
   constexpr int NT = ROWS / 16;
   constexpr int NTT = NT * (NT + 1) / 2;
+  // Shared area: union-row staging (Gram and W passes), the per-point matrices, and
+  // in the W pass the 16 x union selection matrix beside the staged rows.
   constexpr size_t STAGE_B = (size_t)NSLOT * SLD * sizeof(UT);
   constexpr size_t MAT_B = (size_t)GP * ROWS * ROWS * sizeof(T);
-  constexpr size_t BIG_B = STAGE_B > MAT_B ? STAGE_B : MAT_B;
+  constexpr size_t SEL_B = (size_t)16 * (NSLOT + 8) * sizeof(UT);
+  constexpr size_t BIG_B = STAGE_B + SEL_B > MAT_B ? STAGE_B + SEL_B : MAT_B;
   __shared__ __attribute__((aligned(16))) unsigned char sBig[BIG_B];
   __shared__ int sIdx[GP][ROWS];
   __shared__ int sSlot[GP][ROWS];
@@ -364,14 +369,18 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
 
   // Staged chunk width: as many columns as the union size allows in the staging
   // area (wider chunks mean fewer barriers), and a divisor of the row length.
-  constexpr int CAP = NSLOT * SLD;  // elements of UT in the staging area
-  int cw = KC;
-  if (nu * (4 * KC + VPE) <= CAP && A.ldu % (4 * KC) == 0) cw = 4 * KC;
-  else if (nu * (2 * KC + VPE) <= CAP && A.ldu % (2 * KC) == 0) cw = 2 * KC;
-  const int sld = cw + VPE;
-  const int lppr = __builtin_ctz(cw / VPE);  // log2 of the 16-byte pieces per row and chunk
-  const int npieces = nu << lppr;
-  constexpr int MAXP = (CAP / VPE + NTH - 1) / NTH;
+  constexpr int CAPB = (int)(BIG_B / sizeof(UT));          // elements of UT in sBig
+  constexpr int MAXP = (CAPB / VPE + NTH - 1) / NTH;        // 16-byte pieces per thread
+  auto pick_width = [&](int cap) {
+    cap = min(cap, MAXP * NTH * VPE);
+    if (nu * (4 * KC + VPE) <= cap && A.ldu % (4 * KC) == 0) return 4 * KC;
+    if (nu * (2 * KC + VPE) <= cap && A.ldu % (2 * KC) == 0) return 2 * KC;
+    return KC;  // nu <= NSLOT always fits
+  };
+  int cw = pick_width(CAPB);
+  int sld = cw + VPE;
+  int lppr = __builtin_ctz(cw / VPE);  // log2 of the 16-byte pieces per row and chunk
+  int npieces = nu << lppr;
   f4v pre[MAXP];
   // Next chunk into registers (in flight while the current chunk is used) ...
   auto load_regs = [&](int kc) __attribute__((always_inline)) {
@@ -596,7 +605,20 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
     if (r == 0) sZ[pl] = zi;
     __syncthreads();
 
-    // ---- W rows from the staged union rows ----
+    // ---- W rows: W_group = S * U_union on MFMA ----
+    // S (16 x nu, zero beyond the group's points and the rows they use) holds each
+    // point's b_r at its rows' union slots; its row stride is odd against LDS banks.
+    const int nup = (nu + 3) & ~3;
+    const int sst = nup + 1;
+    UT* sel = reinterpret_cast<UT*>(sBig);
+    stage = sel + ((16 * sst + VPE - 1) / VPE) * VPE;
+    for (int e = tid; e < 16 * sst; e += NTH) sel[e] = UT(0);
+    cw = pick_width(CAPB - (int)(stage - sel));
+    sld = cw + VPE;
+    lppr = __builtin_ctz(cw / VPE);
+    npieces = nu << lppr;
+    __syncthreads();
+    if (active && r < q) sel[pl * sst + sSlot[pl][r]] = (UT)sBv[pl][r];
     UT* W = reinterpret_cast<UT*>(A.W);
     load_regs(0);
     store_regs();
@@ -604,18 +626,27 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
     for (int kc = 0; kc < A.ldu; kc += cw) {
       const bool more = kc + cw < A.ldu;
       if (more) load_regs(kc + cw);
-      for (int o = tid; o < GP * cw; o += NTH) {
-        const int pp = o / cw, c = o - (o / cw) * cw;
-        const int64_t ip = sI[pp];
-        if (ip < 0) continue;
-        T accw = T(0);
-#pragma unroll 8
-        for (int rr = 0; rr < ROWS; ++rr) {
-          const int sl = sSlot[pp][rr];
-          if (sl < 0) break;
-          accw += sBv[pp][rr] * (T)stage[sl * sld + c];
+      const int ncb = cw >> 4;
+      for (int cb = wave; cb < ncb; cb += NW) {
+        AccT aw = AccT{0, 0, 0, 0};
+        const int col = cb * 16 + rr16;
+        for (int u0 = 0; u0 < nup; u0 += 4) {
+          const int u = u0 + kq;
+          const UT av = sel[rr16 * sst + u];
+          const UT bv = u < nu ? stage[u * sld + col] : UT(0);
+          if constexpr (PREC == 0)
+            aw = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, aw, 0, 0, 0);
+          else
+            aw = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, aw, 0, 0, 0);
         }
-        W[ip * A.ldu + kc + c] = (kc + c == A.k) ? (UT)sZ[pp] : (UT)accw;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int pp = PREC == 0 ? mfma16_row_f64(lane, e) : mfma16_row_f32acc(lane, e);
+          if (pp < GP) {
+            const int64_t ip = sI[pp];
+            if (ip >= 0) W[ip * A.ldu + kc + col] = (kc + col == A.k) ? (UT)sZ[pp] : (UT)aw[e];
+          }
+        }
       }
       __syncthreads();
       if (more) {
