@@ -30,6 +30,7 @@ namespace {
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
 
 template <int PREC> struct PrecT;
 template <> struct PrecT<0> { using T = double; using UT = double; };
@@ -255,7 +256,13 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
   constexpr size_t STAGE_B = (size_t)NSLOT * SLD * sizeof(UT);
   constexpr size_t MAT_B = (size_t)GP * ROWS * ROWS * sizeof(T);
   constexpr size_t SEL_B = (size_t)16 * (NSLOT + 8) * sizeof(UT);
-  constexpr size_t BIG_B = STAGE_B + SEL_B > MAT_B ? STAGE_B + SEL_B : MAT_B;
+  // Split-BF16 modes stage the Gram pass as NSP bfloat16 terms per value.
+  constexpr bool SPLIT = PREC >= 2;
+  constexpr int NSP = PREC == 3 ? 3 : 2;
+  constexpr int BPAD = 8;  // bf16 row padding (16 bytes)
+  constexpr size_t SPL_B = SPLIT ? (size_t)NSLOT * NSP * (KC + BPAD) * 2 : 0;
+  constexpr size_t B1 = STAGE_B + SEL_B > MAT_B ? STAGE_B + SEL_B : MAT_B;
+  constexpr size_t BIG_B = SPL_B > B1 ? SPL_B : B1;
   __shared__ __attribute__((aligned(16))) unsigned char sBig[BIG_B];
   __shared__ int sIdx[GP][ROWS];
   __shared__ int sSlot[GP][ROWS];
@@ -370,38 +377,89 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
   // Staged chunk width: as many columns as the union size allows in the staging
   // area (wider chunks mean fewer barriers), and a divisor of the row length.
   constexpr int CAPB = (int)(BIG_B / sizeof(UT));          // elements of UT in sBig
-  constexpr int MAXP = (CAPB / VPE + NTH - 1) / NTH;        // 16-byte pieces per thread
+  constexpr int MAXP0 = (CAPB / VPE + NTH - 1) / NTH;
+  constexpr int MAXP = MAXP0 < 12 ? MAXP0 : 12;             // 16-byte pieces per thread
+  // FP32/FP64 staging: nu rows of (width + VPE) elements.
   auto pick_width = [&](int cap) {
     cap = min(cap, MAXP * NTH * VPE);
     if (nu * (4 * KC + VPE) <= cap && A.ldu % (4 * KC) == 0) return 4 * KC;
     if (nu * (2 * KC + VPE) <= cap && A.ldu % (2 * KC) == 0) return 2 * KC;
     return KC;  // nu <= NSLOT always fits
   };
-  int cw = pick_width(CAPB);
-  int sld = cw + VPE;
+  // Split staging: nu rows of NSP planes of (width + BPAD) bfloat16.
+  auto pick_width_split = [&]() {
+    const int capb = (int)(BIG_B / 2);
+    const int capp = MAXP * NTH * VPE;
+    for (int w = 4 * KC; w > KC; w >>= 1)
+      if (nu * NSP * (w + BPAD) <= capb && nu * w <= capp && A.ldu % w == 0) return w;
+    return KC;
+  };
+  bool split_stage = SPLIT;            // Gram pass; the W pass stages FP32
+  int cw = SPLIT ? pick_width_split() : pick_width(CAPB);
+  int sld = SPLIT ? cw + BPAD : cw + VPE;  // row stride (bf16 per plane, or UT)
   int lppr = __builtin_ctz(cw / VPE);  // log2 of the 16-byte pieces per row and chunk
   int npieces = nu << lppr;
-  f4v pre[MAXP];
-  // Next chunk into registers (in flight while the current chunk is used) ...
-  auto load_regs = [&](int kc) __attribute__((always_inline)) {
+  __bf16* splane = reinterpret_cast<__bf16*>(sBig);
+  // Two register sets of staged pieces: the loads of a chunk are issued two chunk
+  // periods before its data go to LDS.
+  f4v preA[MAXP], preB[MAXP];
+  // Loads are unconditional (surplus lanes re-read the last piece) so that the
+  // compiler can count them exactly and wait for one register set only.
+  auto load_into = [&](f4v (&pre)[MAXP], int kc) __attribute__((always_inline)) {
+#pragma unroll
+    for (int j = 0; j < MAXP; ++j) {
+      const int e = min(tid + j * NTH, npieces - 1);
+      const int row = e >> lppr, piece = e & ((1 << lppr) - 1);
+      pre[j] = *reinterpret_cast<const f4v*>(U + (int64_t)sUniq[row] * A.ldu + kc + piece * VPE);
+    }
+  };
+  auto store_from = [&](f4v (&pre)[MAXP]) __attribute__((always_inline)) {
 #pragma unroll
     for (int j = 0; j < MAXP; ++j) {
       const int e = tid + j * NTH;
       if (e < npieces) {
         const int row = e >> lppr, piece = e & ((1 << lppr) - 1);
-        pre[j] = *reinterpret_cast<const f4v*>(U + (int64_t)sUniq[row] * A.ldu + kc +
-                                                  piece * VPE);
+        if (SPLIT && split_stage) {
+          // x = t_0 + t_1 (+ t_2), each term the bfloat16 rounding of the remainder.
+          f4v rem = pre[j];
+#pragma unroll
+          for (int sp = 0; sp < NSP; ++sp) {
+            bf4v hv;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const __bf16 h = (__bf16)rem[c];
+              hv[c] = h;
+              rem[c] -= (float)h;
+            }
+            *reinterpret_cast<bf4v*>(splane + (row * NSP + sp) * sld + piece * 4) = hv;
+          }
+        } else {
+          *reinterpret_cast<f4v*>(stage + row * sld + piece * VPE) = pre[j];
+        }
       }
     }
   };
-  // ... and from registers into the staging area.
-  auto store_regs = [&]() __attribute__((always_inline)) {
-#pragma unroll
-    for (int j = 0; j < MAXP; ++j) {
-      const int e = tid + j * NTH;
-      if (e < npieces) {
-        const int row = e >> lppr, piece = e & ((1 << lppr) - 1);
-        *reinterpret_cast<f4v*>(stage + row * sld + piece * VPE) = pre[j];
+  // One pass over the row in chunks of cw columns; compute(kc) consumes the staged
+  // chunk kc. With first_issued, preA already holds the loads of chunk 0.
+  auto run_pass = [&](auto&& compute, bool first_issued) __attribute__((always_inline)) {
+    if (!first_issued) load_into(preA, 0);
+    if (cw < A.ldu) load_into(preB, cw);
+    store_from(preA);
+    __syncthreads();
+    for (int kc = 0; kc < A.ldu; kc += 2 * cw) {
+      if (kc + 2 * cw < A.ldu) load_into(preA, kc + 2 * cw);
+      compute(kc);
+      __syncthreads();
+      if (kc + cw < A.ldu) {
+        store_from(preB);
+        __syncthreads();
+        if (kc + 3 * cw < A.ldu) load_into(preB, kc + 3 * cw);
+        compute(kc + cw);
+        __syncthreads();
+        if (kc + 2 * cw < A.ldu) {
+          store_from(preA);
+          __syncthreads();
+        }
       }
     }
   };
@@ -414,12 +472,7 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
 #pragma unroll
     for (int t = 0; t < NTT; ++t) acc[s2][t] = AccT{0, 0, 0, 0};
   const int rr16 = lane & 15, kq = lane >> 4;
-  load_regs(0);
-  store_regs();
-  __syncthreads();
-  for (int kc = 0; kc < A.ldu; kc += cw) {
-    const bool more = kc + cw < A.ldu;
-    if (more) load_regs(kc + cw);
+  auto gram_chunk = [&](int) __attribute__((always_inline)) {
     for (int sub = 0; sub < cw; sub += KC) {
 #pragma unroll
     for (int s2 = 0; s2 < PPW; ++s2) {
@@ -450,22 +503,22 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
             }
         }
       } else {
-        // 32 floats per step: lane group kq holds elements 8kq..8kq+7.
-        float x[NT][8];
-#pragma unroll
-        for (int ti = 0; ti < NT; ++ti) {
-          const int sl = sSlot[pp][ti * 16 + rr16];
-          if (sl >= 0) {
-            const float4* src = reinterpret_cast<const float4*>(stage + sl * sld + sub + kq * 8);
-            const float4 a0 = src[0], a1 = src[1];
-            x[ti][0] = a0.x; x[ti][1] = a0.y; x[ti][2] = a0.z; x[ti][3] = a0.w;
-            x[ti][4] = a1.x; x[ti][5] = a1.y; x[ti][6] = a1.z; x[ti][7] = a1.w;
-          } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) x[ti][e] = 0.f;
-          }
-        }
         if constexpr (PREC == 1) {
+          // 32 floats per step: lane group kq holds elements 8kq..8kq+7.
+          float x[NT][8];
+#pragma unroll
+          for (int ti = 0; ti < NT; ++ti) {
+            const int sl = sSlot[pp][ti * 16 + rr16];
+            if (sl >= 0) {
+              const float4* src = reinterpret_cast<const float4*>(stage + sl * sld + sub + kq * 8);
+              const float4 a0 = src[0], a1 = src[1];
+              x[ti][0] = a0.x; x[ti][1] = a0.y; x[ti][2] = a0.z; x[ti][3] = a0.w;
+              x[ti][4] = a1.x; x[ti][5] = a1.y; x[ti][6] = a1.z; x[ti][7] = a1.w;
+            } else {
+#pragma unroll
+              for (int e = 0; e < 8; ++e) x[ti][e] = 0.f;
+            }
+          }
 #pragma unroll
           for (int c = 0; c < 8; ++c) {
             int t = 0;
@@ -478,20 +531,20 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
               }
           }
         } else {
-          constexpr int NS = PREC == 3 ? 3 : 2;
+          // Pre-split terms: lane group kq holds elements 8kq..8kq+7 of each plane.
+          constexpr int NS = NSP;
           bf8v part[NT][NS];
 #pragma unroll
-          for (int ti = 0; ti < NT; ++ti)
+          for (int ti = 0; ti < NT; ++ti) {
+            const int sl = sSlot[pp][ti * 16 + rr16];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              float rem = x[ti][e];
-#pragma unroll
-              for (int sp = 0; sp < NS; ++sp) {
-                const __bf16 h = (__bf16)rem;
-                part[ti][sp][e] = h;
-                rem -= (float)h;
-              }
+            for (int sp = 0; sp < NS; ++sp) {
+              if (sl >= 0)
+                part[ti][sp] = *reinterpret_cast<const bf8v*>(splane + (sl * NS + sp) * sld + sub + kq * 8);
+              else
+                part[ti][sp] = bf8v{};
             }
+          }
           int t = 0;
 #pragma unroll
           for (int ti = 0; ti < NT; ++ti)
@@ -511,12 +564,8 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
       }
     }
     }
-    __syncthreads();
-    if (more) {
-      store_regs();
-      __syncthreads();
-    }
-  }
+  };
+  run_pass(gram_chunk, false);
   // Grams into LDS (the staging area is free now), full symmetric matrices.
 #pragma unroll
   for (int s2 = 0; s2 < PPW; ++s2) {
@@ -537,6 +586,21 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
       }
   }
   __syncthreads();
+
+  // W-pass geometry (FP32 staging after the selection matrix S) and the loads of
+  // its first chunk, in flight during the per-point phase.
+  const int nup = (nu + 3) & ~3;
+  const int sst = nup + 1;
+  UT* sel = reinterpret_cast<UT*>(sBig);
+  if constexpr (!WANT_B) {
+    split_stage = false;
+    stage = sel + ((16 * sst + VPE - 1) / VPE) * VPE;
+    cw = pick_width(CAPB - (int)(stage - sel));
+    sld = cw + VPE;
+    lppr = __builtin_ctz(cw / VPE);
+    npieces = nu << lppr;
+    load_into(preA, 0);
+  }
 
   // ---- per-point residual block, Cholesky, back-substitution (segment) ----
   T* M = sM + pl * ROWS * ROWS;
@@ -608,24 +672,11 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
     // ---- W rows: W_group = S * U_union on MFMA ----
     // S (16 x nu, zero beyond the group's points and the rows they use) holds each
     // point's b_r at its rows' union slots; its row stride is odd against LDS banks.
-    const int nup = (nu + 3) & ~3;
-    const int sst = nup + 1;
-    UT* sel = reinterpret_cast<UT*>(sBig);
-    stage = sel + ((16 * sst + VPE - 1) / VPE) * VPE;
     for (int e = tid; e < 16 * sst; e += NTH) sel[e] = UT(0);
-    cw = pick_width(CAPB - (int)(stage - sel));
-    sld = cw + VPE;
-    lppr = __builtin_ctz(cw / VPE);
-    npieces = nu << lppr;
     __syncthreads();
     if (active && r < q) sel[pl * sst + sSlot[pl][r]] = (UT)sBv[pl][r];
     UT* W = reinterpret_cast<UT*>(A.W);
-    load_regs(0);
-    store_regs();
-    __syncthreads();
-    for (int kc = 0; kc < A.ldu; kc += cw) {
-      const bool more = kc + cw < A.ldu;
-      if (more) load_regs(kc + cw);
+    auto w_chunk = [&](int kc) __attribute__((always_inline)) {
       const int ncb = cw >> 4;
       for (int cb = wave; cb < ncb; cb += NW) {
         AccT aw = AccT{0, 0, 0, 0};
@@ -648,12 +699,8 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
           }
         }
       }
-      __syncthreads();
-      if (more) {
-        store_regs();
-        __syncthreads();
-      }
-    }
+    };
+    run_pass(w_chunk, true);
   }
 }
 
