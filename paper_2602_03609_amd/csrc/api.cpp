@@ -130,7 +130,7 @@ Layout make_layout(int64_t n, int m, int k, int prec, int op) {
   L.sums = take(sizeof(double) * 8);
   if (op == VIF_OP_NLL) {
     L.logD = take(sizeof(double) * (size_t)n);
-    if (k == 0) L.z = take(sizeof(double) * (size_t)n);
+    L.z = take(sizeof(double) * (size_t)n);
   }
   if (k > 0) {
     // processing order of the per-point kernel (Z order of a fine grid per time slab)
@@ -148,9 +148,18 @@ Layout make_layout(int64_t n, int m, int k, int prec, int op) {
     L.dscr = take(sizeof(double) * 64 * 64);
     L.U = take(es * (size_t)n * L.kpad);
     if (op == VIF_OP_NLL) {
-      L.W = take(es * (size_t)n * L.kpad);
-      L.splits = vif::syrk_chunks(n, L.kpad, prec);
-      L.syrk = take(vif::syrk_part_bytes(n, L.kpad, prec));
+      if (prec >= VIF_PREC_BF16X3) {
+        // bfloat16 term planes of W (2 or 3), rows padded to a multiple of 16.
+        const int64_t wr = vif::w_plane_rows(n);
+        const size_t nsp = prec == VIF_PREC_BF16X6 ? 3 : 2;
+        L.W = take(2 * nsp * (size_t)wr * L.kpad);
+        L.splits = vif::syrk_chunks(wr, L.kpad, prec);
+        L.syrk = take(vif::syrk_part_bytes(wr, L.kpad, prec));
+      } else {
+        L.W = take(es * (size_t)n * L.kpad);
+        L.splits = vif::syrk_chunks(n, L.kpad, prec);
+        L.syrk = take(vif::syrk_part_bytes(n, L.kpad, prec));
+      }
       L.M = take(sizeof(double) * kk);
       L.q = take(sizeof(double) * L.kpad);
     }
@@ -411,6 +420,8 @@ int32_t nll_impl(const vif_points* p, const double* y, const vif_kernel* kern, i
     if ((st = run_lowrank(p, ind, kern, prec, ws, L, s))) return st;
     fa.U = ws + L.U;
     fa.W = ws + L.W;
+    fa.z = reinterpret_cast<double*>(ws + L.z);
+    fa.wrb = vif::w_plane_rows(p->n) / 8;
     PROF(VIF_STAGE_POINT_FACTOR, false);
     HIPCHK(vif::launch_point_factor(fa, 0, prec, s));
     PROF(VIF_STAGE_POINT_FACTOR, true);
@@ -418,12 +429,16 @@ int32_t nll_impl(const vif_points* p, const double* y, const vif_kernel* kern, i
     double* M = reinterpret_cast<double*>(ws + L.M);
     double* q = reinterpret_cast<double*>(ws + L.q);
     PROF(VIF_STAGE_SYRK, false);
-    HIPCHK(vif::launch_syrk(p->n, L.kpad, ws + L.W, prec, syrk, L.splits, s));
+    const int64_t wrows = prec >= VIF_PREC_BF16X3 ? vif::w_plane_rows(p->n) : p->n;
+    HIPCHK(vif::launch_syrk(wrows, L.kpad, ws + L.W, prec, syrk, L.splits, s));
     PROF(VIF_STAGE_SYRK, true);
     PROF(VIF_STAGE_ASSEMBLY, false);
-    HIPCHK(vif::launch_syrk_reduce(k, L.kpad, syrk, prec, L.splits, M, q, sums + 1, s));
+    // z'z is summed in FP64 from the per-point z (sums[1]); the Gram's own (k, k)
+    // entry goes to sums[2] unused.
+    HIPCHK(vif::launch_syrk_reduce(k, L.kpad, syrk, prec, L.splits, M, q, sums + 2, s));
     HIPCHK(vif::launch_cholesky(L.kpad, M, reinterpret_cast<double*>(ws + L.dscr), fl + 2, s));
     HIPCHK(vif::launch_sum(p->n, fa.logD, 0, part, sums + 0, s));
+    HIPCHK(vif::launch_sum(p->n, fa.z, 1, part, sums + 1, s));
     HIPCHK(vif::launch_finalize(p->n, k, L.kpad, M, q, sums + 0, sums + 1, out, s));
     PROF(VIF_STAGE_ASSEMBLY, true);
   } else {

@@ -61,7 +61,11 @@ struct FactorArgs {
   const double *sx, *sy, *t, *y;
   const int32_t* nbr;
   const void* U;  // [n, ldu], FP64 or FP32 by precision
-  void* W;        // [n, ldu]; column k receives z_i
+  void* W;        // [n, ldu]; column k receives z_i. Split-BF16 modes: see w_planes below.
+  // Split-BF16 modes (prec 2, 3): W is written as its bfloat16 terms (2 or 3 planes),
+  // rows in processing order, padded to wrb * 8 rows, in 8-row blocks: the term sp of
+  // W[row][col] sits at ((sp * wrb + row / 8) * ldu + col) * 8 + row % 8.
+  int64_t wrb;
   double *B, *D;  // factor outputs
   double *logD, *z;  // NLL outputs (per point)
   const int32_t* ord;           // processing order (a permutation of 0..n-1) or NULL
@@ -103,10 +107,13 @@ hipError_t launch_lowrank_fused(const LowRankArgs& a, const double* P, void* Pb,
 // of W_I' W_J (FP64 64 x 64 tiles for prec 0/1, FP32 128 x 128 tiles for the
 // split-BF16 modes). syrk_chunks gives the chunk count, syrk_part_bytes the size
 // of part.
+// For the split-BF16 modes, n is the padded row count of the W planes (wrb * 8).
 int syrk_chunks(int64_t n, int kpad, int prec);
 size_t syrk_part_bytes(int64_t n, int kpad, int prec);
 hipError_t launch_syrk(int64_t n, int kpad, const void* W, int prec, void* part, int nchunk,
                        hipStream_t s);
+// Rows of W (processing order, padded) in the split-BF16 plane layout.
+inline int64_t w_plane_rows(int64_t n) { return (n + 15) / 16 * 16; }
 // M = I + (sum_c part[c])[0:k,0:k] with identity padding; q = column k; zz = entry (k,k).
 hipError_t launch_syrk_reduce(int k, int kpad, const void* part, int prec, int nchunk, double* M,
                               double* q, double* zz, hipStream_t s);

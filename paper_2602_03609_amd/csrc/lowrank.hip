@@ -717,25 +717,26 @@ __global__ __launch_bounds__(256) void syrk_kernel(int64_t n, int kpad, const vo
 
 // Split-BF16 Gram of W over 4096-row chunks, FP32 partial tiles of 128 x 128.
 //
-// W (FP32) is split once, when staged, into NS bfloat16 terms (x = h + m [+ l]);
-// LDS holds each term transposed to [8-row group][column][8 rows], so that one
-// 16-byte read is one lane's MFMA operand (the K order inside a 32-row step is
-// the same for both operands, which is all a Gram needs). Products of the terms
-// (3 for NS = 2, 6 for NS = 3), smallest first, accumulate in FP32 over the
-// chunk; the partials are summed in FP64 by syrk_split_reduce_kernel.
-// Blocks are dealt to the 8 XCDs round-robin; XCD x runs the tiles of chunks
-// x, x + 8, ... one chunk after the other, so that the tiles sharing a chunk's
-// rows run together and find them in that XCD's L2.
+// W arrives as its bfloat16 terms (x = h + m [+ l]) in 8-row blocks, so that one
+// 16-byte piece is one lane's MFMA operand (8 consecutive rows of one column; the
+// K order inside a 32-row step is the same for both operands, which is all a
+// Gram needs). Pieces are copied to LDS unchanged, loads one step ahead in
+// registers; one 48 KB buffer, so that two workgroups share a CU. Products of the terms (3 for NS = 2, 6 for NS = 3), smallest
+// first, accumulate in FP32 over the chunk; the partials are summed in FP64 by
+// syrk_split_reduce_kernel. Blocks are dealt to the 8 XCDs round-robin; XCD x
+// runs the tiles of chunks x, x + 8, ... one chunk after the other, so that the
+// tiles sharing a chunk's rows run together and find them in that XCD's L2.
 constexpr int TB = 128;    // output tile
 constexpr int CHR = 4096;  // rows per chunk (one FP32 accumulation)
 constexpr int SBK = 32;    // rows per step (the bf16 MFMA K)
 
 template <int NS>
-__global__ __launch_bounds__(256) void syrk_split_kernel(int64_t n, int kpad,
-                                                         const float* __restrict__ W,
+__global__ __launch_bounds__(256, 2) void syrk_split_kernel(int64_t nrows, int kpad,
+                                                         const __bf16* __restrict__ Wp,
                                                          float* __restrict__ part, int nchunk,
                                                          int ntile) {
-  __shared__ bf8v sP[2][2][NS][SBK / 8][TB];
+  constexpr int PPS = NS * (SBK / 8) * TB / 256;  // 16-byte pieces per thread and strip
+  __shared__ bf8v sP[1][2][NS][SBK / 8][TB];
   const int x = blockIdx.x & 7;
   const int l = blockIdx.x >> 3;
   const int c = (l / ntile) * 8 + x;
@@ -748,42 +749,32 @@ __global__ __launch_bounds__(256) void syrk_split_kernel(int64_t n, int kpad,
   const int wr = wave >> 1, wc = wave & 1;
   // On a diagonal tile the upper-right quarter is the transpose of the lower-left.
   const bool skip = diag && wr < wc;
-  const int64_t rbeg = (int64_t)c * CHR;
-  const int64_t rend = rbeg + CHR < n ? rbeg + CHR : n;
-  const int lc = tid & (TB - 1);
-  const int lg = (tid >> 7) * 2;
-  const int colA = TI * TB + lc, colB = TJ * TB + lc;
-  const bool okA = colA < kpad, okB = !diag && colB < kpad;
-  float ra[16], rb[16];
-  auto load = [&](int64_t r0) __attribute__((always_inline)) {
+  const int64_t wrb = nrows / 8;
+  const int64_t bbeg = (int64_t)c * (CHR / 8);
+  const int64_t bend = bbeg + CHR / 8 < wrb ? bbeg + CHR / 8 : wrb;
+  bf8v ra[PPS], rb[PPS];
+  // Unconditional loads (out-of-range pieces re-read a valid one and are zeroed
+  // at the store), so that each store waits for its own loads only.
+  auto load = [&](int64_t b0) __attribute__((always_inline)) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int64_t row = r0 + lg * 8 + e;
-      ra[e] = (row < rend && okA) ? W[row * kpad + colA] : 0.f;
-      rb[e] = (row < rend && okB) ? W[row * kpad + colB] : 0.f;
+    for (int i = 0; i < PPS; ++i) {
+      const int pc = tid + 256 * i;
+      const int col = pc & (TB - 1), gq = (pc / TB) & 3, sp = pc / (TB * 4);
+      int64_t blk = b0 + gq;
+      blk = blk < bend ? blk : bend - 1;
+      const int ca = min(TI * TB + col, kpad - 1), cb = min(TJ * TB + col, kpad - 1);
+      ra[i] = *reinterpret_cast<const bf8v*>(Wp + ((sp * wrb + blk) * kpad + ca) * 8);
+      rb[i] = *reinterpret_cast<const bf8v*>(Wp + ((sp * wrb + blk) * kpad + cb) * 8);
     }
   };
-  auto split_store = [&](int buf) __attribute__((always_inline)) {
+  auto store = [&](int buf, int64_t b0) __attribute__((always_inline)) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      bf8v pa[NS], pb[NS];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        float xa = ra[h * 8 + e], xb = rb[h * 8 + e];
-#pragma unroll
-        for (int sp = 0; sp < NS; ++sp) {
-          const __bf16 ha = (__bf16)xa, hb = (__bf16)xb;
-          pa[sp][e] = ha;
-          pb[sp][e] = hb;
-          xa -= (float)ha;
-          xb -= (float)hb;
-        }
-      }
-#pragma unroll
-      for (int sp = 0; sp < NS; ++sp) {
-        sP[buf][0][sp][lg + h][lc] = pa[sp];
-        if (!diag) sP[buf][1][sp][lg + h][lc] = pb[sp];
-      }
+    for (int i = 0; i < PPS; ++i) {
+      const int pc = tid + 256 * i;
+      const int col = pc & (TB - 1), gq = (pc / TB) & 3, sp = pc / (TB * 4);
+      const bool okr = b0 + gq < bend;
+      sP[buf][0][sp][gq][col] = (okr && TI * TB + col < kpad) ? ra[i] : bf8v{};
+      sP[buf][1][sp][gq][col] = (okr && TJ * TB + col < kpad) ? rb[i] : bf8v{};
     }
   };
 
@@ -793,17 +784,17 @@ __global__ __launch_bounds__(256) void syrk_split_kernel(int64_t n, int kpad,
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f4v{0.f, 0.f, 0.f, 0.f};
   const int g = lane >> 4, j = lane & 15;
-  const int sb = diag ? 0 : 1;
-  const int nsteps = (int)((rend - rbeg + SBK - 1) / SBK);
+  const int nsteps = bend > bbeg ? (int)((bend - bbeg + 3) / 4) : 0;
   if (nsteps > 0) {
-    load(rbeg);
-    split_store(0);
+    load(bbeg);
+    store(0, bbeg);
   }
   __syncthreads();
   for (int st = 0; st < nsteps; ++st) {
-    const int buf = st & 1;
+    const int buf = 0;
     const bool more = st + 1 < nsteps;
-    if (more) load(rbeg + (int64_t)(st + 1) * SBK);
+    const int64_t bnext = bbeg + (int64_t)(st + 1) * 4;
+    if (more) load(bnext);
     if (!skip) {
       bf8v av[4][NS], bv[4][NS];
 #pragma unroll
@@ -813,7 +804,7 @@ __global__ __launch_bounds__(256) void syrk_split_kernel(int64_t n, int kpad,
 #pragma unroll
       for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int sp = 0; sp < NS; ++sp) bv[b][sp] = sP[buf][sb][sp][g][wc * 64 + b * 16 + j];
+        for (int sp = 0; sp < NS; ++sp) bv[b][sp] = sP[buf][1][sp][g][wc * 64 + b * 16 + j];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -828,8 +819,11 @@ __global__ __launch_bounds__(256) void syrk_split_kernel(int64_t n, int kpad,
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a][0], bv[b][0], acc[a][b], 0, 0, 0);
         }
     }
-    if (more) split_store(buf ^ 1);
     __syncthreads();
+    if (more) {
+      store(0, bnext);
+      __syncthreads();
+    }
   }
   if (skip) return;
   float* out = part + ((int64_t)c * ntile + t) * (TB * TB);
@@ -986,10 +980,10 @@ hipError_t launch_syrk(int64_t n, int kpad, const void* W, int prec, void* part,
     dim3 grid((unsigned)(ntile * nchunk));
     if (prec == 2)
       hipLaunchKernelGGL(syrk_split_kernel<2>, grid, dim3(256), 0, s, n, kpad,
-                         (const float*)W, (float*)part, nchunk, ntile);
+                         (const __bf16*)W, (float*)part, nchunk, ntile);
     else
       hipLaunchKernelGGL(syrk_split_kernel<3>, grid, dim3(256), 0, s, n, kpad,
-                         (const float*)W, (float*)part, nchunk, ntile);
+                         (const __bf16*)W, (float*)part, nchunk, ntile);
     return hipGetLastError();
   }
   const int ntile = syrk_ntile(kpad, NB);

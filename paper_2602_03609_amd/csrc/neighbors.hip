@@ -164,11 +164,61 @@ __global__ void grid_scatter_kernel(int64_t n, const double* __restrict__ sx,
   if (i >= n) return;
   const int k = key[i];
   const int pos = off[k] + atomicAdd(&fill[k], 1);
-  if (px) {
-    px[pos] = sx[i];
-    py[pos] = sy[i];
-  }
   pidx[pos] = (int32_t)i;
+}
+
+// The scatter leaves each cell's points in arrival order; sorting every cell by
+// point index makes the layout (and the processing order built from it)
+// independent of scheduling. One thread per cell: insertion sort for short
+// cells, heapsort otherwise.
+__global__ void cell_sort_kernel(int64_t ncells, const int32_t* __restrict__ off,
+                                 int32_t* __restrict__ pidx) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  int32_t* a = pidx + off[c];
+  const int len = off[c + 1] - off[c];
+  if (len < 2) return;
+  if (len <= 32) {
+    for (int q = 1; q < len; ++q) {
+      const int32_t v = a[q];
+      int r = q - 1;
+      while (r >= 0 && a[r] > v) {
+        a[r + 1] = a[r];
+        --r;
+      }
+      a[r + 1] = v;
+    }
+    return;
+  }
+  auto sift = [&](int root, int end) {
+    while (2 * root + 1 < end) {
+      int child = 2 * root + 1;
+      if (child + 1 < end && a[child] < a[child + 1]) ++child;
+      if (a[root] >= a[child]) return;
+      const int32_t tmp = a[root];
+      a[root] = a[child];
+      a[child] = tmp;
+      root = child;
+    }
+  };
+  for (int st = len / 2 - 1; st >= 0; --st) sift(st, len);
+  for (int end = len - 1; end > 0; --end) {
+    const int32_t tmp = a[0];
+    a[0] = a[end];
+    a[end] = tmp;
+    sift(0, end);
+  }
+}
+
+__global__ void grid_gather_kernel(int64_t n, const double* __restrict__ sx,
+                                   const double* __restrict__ sy,
+                                   const int32_t* __restrict__ pidx, double* __restrict__ px,
+                                   double* __restrict__ py) {
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= n) return;
+  const int32_t i = pidx[pos];
+  px[pos] = sx[i];
+  py[pos] = sy[i];
 }
 
 // Ranking keys. Fixed operation order and no contraction, so that any IEEE FP64
@@ -413,6 +463,12 @@ hipError_t launch_grid_build(int64_t n, const double* sx, const double* sy, cons
                      (const int32_t*)bsum);
   hipLaunchKernelGGL(grid_scatter_kernel, dim3(gn), dim3(256), 0, s, n, sx, sy,
                      (const int32_t*)key, (const int32_t*)counts, fill, px, py, pidx);
+  const int64_t ncells = len - 1;
+  hipLaunchKernelGGL(cell_sort_kernel, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, s,
+                     ncells, (const int32_t*)counts, pidx);
+  if (px)
+    hipLaunchKernelGGL(grid_gather_kernel, dim3(gn), dim3(256), 0, s, n, sx, sy,
+                       (const int32_t*)pidx, px, py);
   return hipGetLastError();
 }
 

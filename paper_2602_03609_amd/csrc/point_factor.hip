@@ -286,10 +286,26 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
   const int pl = wave * PPW + seg;  // point slot in the group
   // Workgroups are dealt round-robin to the 8 XCDs; each XCD walks a
   // contiguous range of groups so that its L2 holds the rows they share.
-  const int64_t ngrp = (A.n + GP - 1) / GP;
+  // In the split-BF16 NLL modes the groups also cover the zero padding rows of
+  // the W planes; those groups only write zeros.
+  const int64_t ngrp = (SPLIT && !WANT_B) ? A.wrb * 8 / GP : (A.n + GP - 1) / GP;
   const int64_t per = (ngrp + 7) / 8;
   const int64_t g = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (g >= ngrp) return;  // whole block, before any barrier
+  if constexpr (SPLIT && !WANT_B) {
+    if (g * GP >= A.n) {
+      __bf16* Wp = reinterpret_cast<__bf16*>(A.W);
+      const bf4v zero = bf4v{};
+      for (int e = tid; e < NSP * A.ldu * (GP / 4); e += NTH) {
+        const int quad = e % (GP / 4), rest = e / (GP / 4);
+        const int col = rest % A.ldu, sp = rest / A.ldu;
+        const int64_t row0 = g * GP + 4 * quad;
+        *reinterpret_cast<bf4v*>(Wp + ((sp * A.wrb + (row0 >> 3)) * A.ldu + col) * 8 +
+                                 (row0 & 7)) = zero;
+      }
+      return;
+    }
+  }
   const int64_t pos = g * GP + pl;
   const bool active = pos < A.n;
   const int64_t i = active ? (A.ord ? (int64_t)A.ord[pos] : pos) : A.n;
@@ -378,20 +394,20 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
   // area (wider chunks mean fewer barriers), and a divisor of the row length.
   constexpr int CAPB = (int)(BIG_B / sizeof(UT));          // elements of UT in sBig
   constexpr int MAXP0 = (CAPB / VPE + NTH - 1) / NTH;
-  constexpr int MAXP = MAXP0 < 12 ? MAXP0 : 12;             // 16-byte pieces per thread
+  constexpr int MAXP = MAXP0 < 10 ? MAXP0 : 10;             // 16-byte pieces per thread
   // FP32/FP64 staging: nu rows of (width + VPE) elements.
   auto pick_width = [&](int cap) {
     cap = min(cap, MAXP * NTH * VPE);
-    if (nu * (4 * KC + VPE) <= cap && A.ldu % (4 * KC) == 0) return 4 * KC;
-    if (nu * (2 * KC + VPE) <= cap && A.ldu % (2 * KC) == 0) return 2 * KC;
-    return KC;  // nu <= NSLOT always fits
+    if (nu * (4 * KC + VPE) <= cap && A.ldu % (8 * KC) == 0) return 4 * KC;
+    if (nu * (2 * KC + VPE) <= cap && A.ldu % (4 * KC) == 0) return 2 * KC;
+    return KC;  // nu <= NSLOT always fits; ldu is a multiple of 64 >= 2 KC
   };
   // Split staging: nu rows of NSP planes of (width + BPAD) bfloat16.
   auto pick_width_split = [&]() {
     const int capb = (int)(BIG_B / 2);
     const int capp = MAXP * NTH * VPE;
     for (int w = 4 * KC; w > KC; w >>= 1)
-      if (nu * NSP * (w + BPAD) <= capb && nu * w <= capp && A.ldu % w == 0) return w;
+      if (nu * NSP * (w + BPAD) <= capb && nu * w <= capp && A.ldu % (2 * w) == 0) return w;
     return KC;
   };
   bool split_stage = SPLIT;            // Gram pass; the W pass stages FP32
@@ -439,29 +455,34 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
       }
     }
   };
-  // One pass over the row in chunks of cw columns; compute(kc) consumes the staged
-  // chunk kc. With first_issued, preA already holds the loads of chunk 0.
+  // One pass over the row in chunks of cw columns (an even number of them);
+  // compute(kc) consumes the staged chunk kc. With first_issued, preA already
+  // holds the loads of chunk 0. The loop body is free of conditional loads, so
+  // each store waits for exactly the register set it writes out.
   auto run_pass = [&](auto&& compute, bool first_issued) __attribute__((always_inline)) {
     if (!first_issued) load_into(preA, 0);
-    if (cw < A.ldu) load_into(preB, cw);
+    load_into(preB, cw);
     store_from(preA);
     __syncthreads();
-    for (int kc = 0; kc < A.ldu; kc += 2 * cw) {
-      if (kc + 2 * cw < A.ldu) load_into(preA, kc + 2 * cw);
+    int kc = 0;
+    for (; kc + 2 * cw < A.ldu; kc += 2 * cw) {
+      load_into(preA, kc + 2 * cw);
       compute(kc);
       __syncthreads();
-      if (kc + cw < A.ldu) {
-        store_from(preB);
-        __syncthreads();
-        if (kc + 3 * cw < A.ldu) load_into(preB, kc + 3 * cw);
-        compute(kc + cw);
-        __syncthreads();
-        if (kc + 2 * cw < A.ldu) {
-          store_from(preA);
-          __syncthreads();
-        }
-      }
+      store_from(preB);
+      __syncthreads();
+      load_into(preB, kc + 3 * cw);
+      compute(kc + cw);
+      __syncthreads();
+      store_from(preA);
+      __syncthreads();
     }
+    compute(kc);
+    __syncthreads();
+    store_from(preB);
+    __syncthreads();
+    compute(kc + cw);
+    __syncthreads();
   };
 
   // ---- Grams on MFMA from the staged union rows ----
@@ -662,11 +683,14 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
     }
     return;
   } else {
-    if (active && r == 0) A.logD[i] = 2.0 * log((double)Lpp_b);
+    if (active && r == 0) {
+      A.logD[i] = 2.0 * log((double)Lpp_b);
+      A.z[i] = (double)zi;
+    }
     // b_r = -x_r / L_pp (r < p), b_p = 1 / L_pp;  W_i = sum_r b_r U_{S_r}.
     const T inv = T(1) / Lpp_b;
     sBv[pl][r] = (r < p) ? -x * inv : (r == p ? inv : T(0));
-    if (r == 0) sZ[pl] = zi;
+    if (r == 0) sZ[pl] = active ? zi : T(0);
     __syncthreads();
 
     // ---- W rows: W_group = S * U_union on MFMA ----
@@ -690,12 +714,36 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
           else
             aw = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, aw, 0, 0, 0);
         }
+        if constexpr (SPLIT) {
+          // Lane holds rows 4kq..4kq+3 of column col: one 8-byte piece per term plane.
+          if (4 * kq < GP) {
+            const int64_t row0 = g * GP + 4 * kq;
+            f4v v;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int pp = PREC == 0 ? mfma16_row_f64(lane, e) : mfma16_row_f32acc(lane, e);
-          if (pp < GP) {
-            const int64_t ip = sI[pp];
-            if (ip >= 0) W[ip * A.ldu + kc + col] = (kc + col == A.k) ? (UT)sZ[pp] : (UT)aw[e];
+            for (int e = 0; e < 4; ++e)
+              v[e] = (kc + col == A.k) ? (float)sZ[4 * kq + e] : (float)aw[e];
+            __bf16* Wp = reinterpret_cast<__bf16*>(A.W);
+#pragma unroll
+            for (int sp = 0; sp < NSP; ++sp) {
+              bf4v hv;
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const __bf16 h = (__bf16)v[e];
+                hv[e] = h;
+                v[e] -= (float)h;
+              }
+              *reinterpret_cast<bf4v*>(
+                  Wp + ((sp * A.wrb + (row0 >> 3)) * A.ldu + kc + col) * 8 + (row0 & 7)) = hv;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int pp = PREC == 0 ? mfma16_row_f64(lane, e) : mfma16_row_f32acc(lane, e);
+            if (pp < GP) {
+              const int64_t ip = sI[pp];
+              if (ip >= 0) W[ip * A.ldu + kc + col] = (kc + col == A.k) ? (UT)sZ[pp] : (UT)aw[e];
+            }
           }
         }
       }
@@ -707,7 +755,8 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
 template <int ROWS, int PREC>
 hipError_t launch_group(const FactorArgs& a, int mode, hipStream_t s) {
   using Sh = GroupShape<ROWS, PREC>;
-  const int64_t ngrp = (a.n + Sh::GP - 1) / Sh::GP;
+  const int64_t ngrp =
+      (PREC >= 2 && mode != 1) ? a.wrb * 8 / Sh::GP : (a.n + Sh::GP - 1) / Sh::GP;
   const unsigned grid = (unsigned)(((ngrp + 7) / 8) * 8);
   if (mode == 1)
     hipLaunchKernelGGL((vif_group_kernel<ROWS, true, PREC>), dim3(grid), dim3(64 * Sh::NW), 0, s,
