@@ -53,22 +53,31 @@ def parse():
     return ap.parse_args()
 
 
-def stage_work(n, m, k, kpad, es):
+def stage_work(n, m, k, kpad, es, prec):
     """Algorithmic flops and HBM bytes per launch of each timed stage."""
     q = m + 1
+    split = prec in ("bf16x3", "bf16x6")
+    # W is stored as 2 or 3 bfloat16 terms per value in the split modes
+    ew = (3 if prec == "bf16x6" else 2) * 2 if split else es
+    if split:
+        # cross-covariance evaluated on chip: coordinates in, U written once, P's terms in
+        trmm_bytes = n * kpad * es + n * 3 * 8 + 4 * kpad * kpad
+    else:
+        # U (holding the cross-covariance) read and written once, P in
+        trmm_bytes = 2 * n * kpad * es + kpad * kpad * 8
     return {
         # exact key evaluations are counted from the kernel's own scan; bytes: coordinates in,
         # neighbor rows out
         "neighbors": {"bytes": n * (3 * 8 + 4 * m), "flops": None},
         "crosscov": {"bytes": n * kpad * es, "flops": None},
-        # U = C L_k^-T, triangular: sum_j 2(j+1) flops per row; U read and written once
-        "trmm": {"bytes": 2 * n * kpad * es + kpad * kpad * 8, "flops": n * k * (k + 1)},
+        # U = C L_k^-T, triangular: sum_j 2(j+1) flops per row
+        "trmm": {"bytes": trmm_bytes, "flops": n * k * (k + 1)},
         # Gram of the q gathered rows (lower triangle incl. diagonal) + W row; U read once
-        # (cache-ideal gathers), W written, nbr/coords/y in, logD out
-        "point_factor": {"bytes": 2 * n * kpad * es + n * (4 * m + 4 * 8 + 8),
+        # (cache-ideal gathers), W written, nbr/coords/y in, logD and z out
+        "point_factor": {"bytes": n * kpad * (es + ew) + n * (4 * m + 4 * 8 + 16),
                          "flops": n * (q * (q + 1) // 2 * 2 * k + 2 * q * k)},
         # [W z]'[W z], lower triangle incl. diagonal
-        "syrk": {"bytes": n * kpad * es, "flops": n * (k + 1) * (k + 2)},
+        "syrk": {"bytes": n * kpad * ew, "flops": n * (k + 1) * (k + 2)},
     }
 
 
@@ -85,11 +94,13 @@ def kernel_name(stage, prec, m):
     c = PREC_CODE[prec]
     rows = 16 if m + 1 <= 16 else (32 if m + 1 <= 32 else 64)
     if stage == "point_factor":
-        return f"point_factor_kernel<{rows}, true, false, {c}>"
+        return f"vif_group_kernel<{rows}, false, {c}>"
     if stage == "syrk":
-        return f"syrk_kernel<{c}>"
+        return f"syrk_split_kernel<{3 if c == 3 else 2}>" if c >= 2 else f"syrk_kernel<{c}>"
     if stage == "trmm":
-        return "trmm_f64_kernel" if c == 0 else f"trmm_f32_kernel<{'true' if c >= 2 else 'false'}>"
+        if c >= 2:
+            return "lowrank_u_kernel"
+        return "trmm_f64_kernel" if c == 0 else "trmm_f32_kernel<false>"
     if stage == "crosscov":
         return f"crosscov_kernel<{'double' if c == 0 else 'float'}>"
     return "neighbors_grid_kernel<0>"
@@ -123,8 +134,8 @@ def mfma_peak(prec):
     return PEAK["bf16_TFs"]
 
 
-def cpu_baseline(d, m, budget_s=20.0):
-    """The FP64 oracle, timed on a bounded sample of the same workload."""
+def cpu_baseline(d, m, n_query=6000, n_point=24000):
+    """The FP64 oracle, timed on a bounded sample of the same workload (about 15 s)."""
     import numpy as np
     from oracle import likelihood as LK
     from oracle import neighbors as NB
@@ -138,7 +149,7 @@ def cpu_baseline(d, m, budget_s=20.0):
     Z = (d["zx"], d["zy"], d["zt"])
     rng = np.random.default_rng(123)
     # neighbor search: exact lag-pruned oracle on sampled queries
-    q_rows = rng.choice(n, 1500, replace=False)
+    q_rows = rng.choice(n, n_query, replace=False)
     t0 = time.perf_counter()
     nb_rows = NB.lag_pruned(d["kern"], *X, m, rows=q_rows)
     t_q = (time.perf_counter() - t0) / q_rows.shape[0]
@@ -146,7 +157,7 @@ def cpu_baseline(d, m, budget_s=20.0):
     t0 = time.perf_counter()
     Lk = LK.low_rank_factor(d["kern"], Z)
     t_lk = time.perf_counter() - t0
-    s_rows = np.sort(rng.choice(np.arange(m, n), 6000, replace=False))
+    s_rows = np.sort(rng.choice(np.arange(m, n), n_point, replace=False))
     nb_s = NB.lag_pruned(d["kern"], *X, m, rows=s_rows)
     nbr_full = np.full((n, m), -1, dtype=np.int32)
     nbr_full[s_rows] = nb_s
@@ -167,9 +178,10 @@ def cpu_baseline(d, m, budget_s=20.0):
         "unit": "evals/s",
         "cores": int(blas_threads),
         "kind": "oracle",
-        "sample": (f"FP64 NumPy/SciPy oracle: lag-pruned exact neighbor search on 1500 sampled "
-                   f"queries and the VIF per-point factor (U rows by triangular solve, residual "
-                   f"block solves, W rows) plus W'W on 6000 sampled points, scaled to n={n}; "
+        "sample": (f"FP64 NumPy/SciPy oracle: lag-pruned exact neighbor search on {n_query} "
+                   f"sampled queries and the VIF per-point factor (U rows by triangular solve, "
+                   f"residual block solves, W rows) plus W'W on {n_point} sampled points, scaled "
+                   f"to n={n}; "
                    f"plus L_k and chol(M) once; step = search + NLL = {t_step:.1f} s"),
         "neighbor_pts_per_s": 1.0 / t_q,
         "nll_evals_per_s": 1.0 / (n * (t_pt + t_syrk) + t_lk + t_chol),
@@ -256,9 +268,10 @@ def main():
 
     kpad = ((k + 1 + 63) // 64) * 64
     es = PREC_ES[args.prec]
-    work = stage_work(n, m, k, kpad, es)
+    work = stage_work(n, m, k, kpad, es, args.prec)
     # dominant kernel among the single-kernel stages
-    cand = {s: stage_ms[s] for s in ("trmm", "point_factor", "syrk", "neighbors", "crosscov")}
+    cand = {s: stage_ms[s] for s in ("trmm", "point_factor", "syrk", "neighbors", "crosscov")
+            if stage_ms.get(s, 0.0) > 0.0}
     dom = max(cand, key=cand.get)
     t_dom = stage_ms[dom] / 1000.0
     wk = work[dom]

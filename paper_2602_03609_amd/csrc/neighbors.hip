@@ -164,30 +164,39 @@ __global__ void grid_scatter_kernel(int64_t n, const double* __restrict__ sx,
   if (i >= n) return;
   const int k = key[i];
   const int pos = off[k] + atomicAdd(&fill[k], 1);
+  if (px) {
+    px[pos] = sx[i];
+    py[pos] = sy[i];
+  }
   pidx[pos] = (int32_t)i;
 }
 
 // The scatter leaves each cell's points in arrival order; sorting every cell by
-// point index makes the layout (and the processing order built from it)
-// independent of scheduling. One thread per cell: insertion sort for short
-// cells, heapsort otherwise.
-__global__ void cell_sort_kernel(int64_t ncells, const int32_t* __restrict__ off,
-                                 int32_t* __restrict__ pidx) {
+// point index makes the processing order built from the grid independent of
+// scheduling (the neighbor search itself does not depend on the order inside a
+// cell). One thread per cell: insertion sort for short cells, heapsort otherwise.
+__global__ __launch_bounds__(256) void cell_sort_kernel(int64_t ncells,
+                                                        const int32_t* __restrict__ off,
+                                                        int32_t* __restrict__ pidx) {
+  __shared__ int32_t buf[32][257];  // column per thread: short cells sort in LDS
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncells) return;
   int32_t* a = pidx + off[c];
   const int len = off[c + 1] - off[c];
   if (len < 2) return;
   if (len <= 32) {
+    const int tx = threadIdx.x;
+    for (int q = 0; q < len; ++q) buf[q][tx] = a[q];
     for (int q = 1; q < len; ++q) {
-      const int32_t v = a[q];
+      const int32_t v = buf[q][tx];
       int r = q - 1;
-      while (r >= 0 && a[r] > v) {
-        a[r + 1] = a[r];
+      while (r >= 0 && buf[r][tx] > v) {
+        buf[r + 1][tx] = buf[r][tx];
         --r;
       }
-      a[r + 1] = v;
+      buf[r + 1][tx] = v;
     }
+    for (int q = 0; q < len; ++q) a[q] = buf[q][tx];
     return;
   }
   auto sift = [&](int root, int end) {
@@ -210,16 +219,6 @@ __global__ void cell_sort_kernel(int64_t ncells, const int32_t* __restrict__ off
   }
 }
 
-__global__ void grid_gather_kernel(int64_t n, const double* __restrict__ sx,
-                                   const double* __restrict__ sy,
-                                   const int32_t* __restrict__ pidx, double* __restrict__ px,
-                                   double* __restrict__ py) {
-  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (pos >= n) return;
-  const int32_t i = pidx[pos];
-  px[pos] = sx[i];
-  py[pos] = sy[i];
-}
 
 // Ranking keys. Fixed operation order and no contraction, so that any IEEE FP64
 // implementation of the same sequence returns the same bits.
@@ -463,12 +462,12 @@ hipError_t launch_grid_build(int64_t n, const double* sx, const double* sy, cons
                      (const int32_t*)bsum);
   hipLaunchKernelGGL(grid_scatter_kernel, dim3(gn), dim3(256), 0, s, n, sx, sy,
                      (const int32_t*)key, (const int32_t*)counts, fill, px, py, pidx);
-  const int64_t ncells = len - 1;
-  hipLaunchKernelGGL(cell_sort_kernel, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, s,
-                     ncells, (const int32_t*)counts, pidx);
-  if (px)
-    hipLaunchKernelGGL(grid_gather_kernel, dim3(gn), dim3(256), 0, s, n, sx, sy,
-                       (const int32_t*)pidx, px, py);
+  if (!px) {
+    // processing order: made independent of scheduling
+    const int64_t ncells = len - 1;
+    hipLaunchKernelGGL(cell_sort_kernel, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0,
+                       s, ncells, (const int32_t*)counts, pidx);
+  }
   return hipGetLastError();
 }
 
