@@ -19,10 +19,17 @@ from ._lib import (  # noqa: F401
     load,
     release_workspaces,
     vif_factor,
+    vif_mlp_adam,
+    vif_mlp_backward,
+    vif_mlp_batch,
+    vif_mlp_features,
+    vif_mlp_forward,
+    vif_mlp_pair_loss,
     vif_neighbors,
     vif_nll,
     vif_nll_terms,
     vif_profile,
     vif_profile_read,
+    vif_propose_neighbors,
     vif_workspace_bytes,
 )

@@ -22,7 +22,11 @@ PREC_NAMES = {"fp64": VIF_PREC_FP64, "fp32": VIF_PREC_FP32, "bf16x3": VIF_PREC_B
               "bf16x6": VIF_PREC_BF16X6}
 
 EXPORTS = ("vif_workspace_bytes", "vif_neighbors", "vif_factor", "vif_nll", "vif_nll_terms",
-           "vif_last_error", "vif_profile", "vif_profile_read")
+           "vif_last_error", "vif_profile", "vif_profile_read",
+           "vif_mlp_features", "vif_mlp_forward", "vif_mlp_backward_ws", "vif_mlp_backward",
+           "vif_mlp_pair_loss", "vif_mlp_adam", "vif_mlp_batch", "vif_propose_ws",
+           "vif_propose_neighbors")
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 8, 64, 16, 9936
 STAGES = ("neighbors", "sigma_k", "crosscov", "trmm", "point_factor", "syrk", "assembly")
 
 
@@ -76,6 +80,26 @@ def load(path=LIB_PATH):
         lib.vif_profile.restype = i32
         lib.vif_profile_read.argtypes = [pd, ctypes.POINTER(i32), i32]
         lib.vif_profile_read.restype = i32
+        f32 = ctypes.c_float
+        lib.vif_mlp_features.argtypes = [pP, pK, pd, vp, vp]
+        lib.vif_mlp_features.restype = i32
+        lib.vif_mlp_forward.argtypes = [vp, vp, i64, vp, vp, vp]
+        lib.vif_mlp_forward.restype = i32
+        lib.vif_mlp_backward_ws.argtypes = [i64]
+        lib.vif_mlp_backward_ws.restype = sz
+        lib.vif_mlp_backward.argtypes = [vp, vp, vp, vp, i64, vp, vp, sz, vp]
+        lib.vif_mlp_backward.restype = i32
+        lib.vif_mlp_pair_loss.argtypes = [vp, i64, i32, i32, f32, vp, vp, vp]
+        lib.vif_mlp_pair_loss.restype = i32
+        lib.vif_mlp_adam.argtypes = [vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp]
+        lib.vif_mlp_adam.restype = i32
+        lib.vif_mlp_batch.argtypes = [vp, vp, i64, vp, i32, i32, i32, i32, vp, i32, vp, vp]
+        lib.vif_mlp_batch.restype = i32
+        lib.vif_propose_ws.argtypes = [i64]
+        lib.vif_propose_ws.restype = sz
+        lib.vif_propose_neighbors.argtypes = [pP, pK, i32, vp, i32, ctypes.c_double, i32, i32, vp,
+                                              ctypes.POINTER(i64), vp, sz, vp]
+        lib.vif_propose_neighbors.restype = i32
         _lib = lib
         return lib
 
@@ -249,3 +273,119 @@ def vif_profile_read():
     calls = (ctypes.c_int32 * n)()
     _check(load().vif_profile_read(ms, calls, n))
     return {STAGES[i]: (ms[i], calls[i]) for i in range(n)}
+
+
+# ------------------------------------------------------------ learned proposal ----
+def _scratch(key, nbytes, device):
+    torch = _torch()
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        _ws_cache.pop(key, None)
+        buf = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
+def vif_mlp_features(sx, sy, t, kern, centre, stream=None):
+    """Network inputs [n, 8] (float32) for the points under kernel `kern`."""
+    torch = _torch()
+    lib = load()
+    n = sx.shape[0]
+    X = torch.empty((n, MLP_IN), dtype=torch.float32, device=sx.device)
+    c = (ctypes.c_double * 10)(*[float(v) for v in centre])
+    p = make_points(sx, sy, t)
+    K = make_kernel(kern)
+    _check(lib.vif_mlp_features(ctypes.byref(p), ctypes.byref(K), c, X.data_ptr(),
+                                _stream(stream)))
+    return X
+
+
+def vif_mlp_forward(params, X, want_hidden=False, stream=None):
+    """(E [rows, 16], H [rows, 3, 64] or None)."""
+    torch = _torch()
+    lib = load()
+    rows = X.shape[0]
+    E = torch.empty((rows, MLP_OUT), dtype=torch.float32, device=X.device)
+    H = (torch.empty((rows, 3, MLP_HIDDEN), dtype=torch.float32, device=X.device)
+         if want_hidden else None)
+    _check(lib.vif_mlp_forward(_dev_ptr(params, torch.float32, "params"),
+                               _dev_ptr(X, torch.float32, "X"), int(rows), E.data_ptr(),
+                               H.data_ptr() if H is not None else None, _stream(stream)))
+    return E, H
+
+
+def vif_mlp_backward(params, X, H, dE, stream=None):
+    """Gradient [9936] of sum(dE * E) with respect to the parameters."""
+    torch = _torch()
+    lib = load()
+    rows = X.shape[0]
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
+    nb = int(lib.vif_mlp_backward_ws(int(rows)))
+    ws = _scratch(("mlp_bwd", str(X.device)), nb, X.device)
+    _check(lib.vif_mlp_backward(_dev_ptr(params, torch.float32, "params"),
+                                _dev_ptr(X, torch.float32, "X"), _dev_ptr(H, torch.float32, "H"),
+                                _dev_ptr(dE, torch.float32, "dE"), int(rows), grad.data_ptr(),
+                                ws.data_ptr(), ws.numel(), _stream(stream)))
+    return grad
+
+
+def vif_mlp_pair_loss(E, npos, nneg, tau, stream=None):
+    """(loss [groups], dE [rows, 16]) for groups of 1 + npos + nneg rows."""
+    torch = _torch()
+    lib = load()
+    G = 1 + npos + nneg
+    groups = E.shape[0] // G
+    loss = torch.empty(groups, dtype=torch.float32, device=E.device)
+    dE = torch.zeros_like(E)
+    _check(lib.vif_mlp_pair_loss(_dev_ptr(E, torch.float32, "E"), int(groups), int(npos),
+                                 int(nneg), float(tau), dE.data_ptr(), loss.data_ptr(),
+                                 _stream(stream)))
+    return loss, dE
+
+
+def vif_mlp_adam(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    """One in-place Adam step (step counts from 1)."""
+    torch = _torch()
+    lib = load()
+    _check(lib.vif_mlp_adam(_dev_ptr(params, torch.float32, "params"),
+                            _dev_ptr(grad, torch.float32, "grad"), _dev_ptr(m, torch.float32, "m"),
+                            _dev_ptr(v, torch.float32, "v"), int(params.numel()), int(step),
+                            float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))
+
+
+def vif_mlp_batch(X, queries, nbr_ext, npos, nhard, nrand, rnd, rand_window, stream=None):
+    """Training rows [nq * (1 + npos + nhard + nrand), 8]."""
+    torch = _torch()
+    lib = load()
+    nq = queries.shape[0]
+    G = 1 + npos + nhard + nrand
+    Xb = torch.empty((nq * G, MLP_IN), dtype=torch.float32, device=X.device)
+    _check(lib.vif_mlp_batch(_dev_ptr(X, torch.float32, "X"),
+                             _dev_ptr(queries, torch.int32, "queries"), int(nq),
+                             _dev_ptr(nbr_ext, torch.int32, "nbr_ext"), int(nbr_ext.shape[1]),
+                             int(npos), int(nhard), int(nrand),
+                             _dev_ptr(rnd, torch.int32, "rnd") if nrand > 0 else None,
+                             int(rand_window), Xb.data_ptr(), _stream(stream)))
+    return Xb
+
+
+def vif_propose_neighbors(sx, sy, t, kern, m, E, ncand, cell, lags, cmax=1024, nbr=None,
+                          stream=None):
+    """Proposal search (embedding or, with E=None, spatial candidates + exact rerank).
+    Returns (nbr int32 [n, m], number of rows that took the exact search)."""
+    torch = _torch()
+    lib = load()
+    n = sx.shape[0]
+    if nbr is None:
+        nbr = torch.empty((n, m), dtype=torch.int32, device=sx.device)
+    p = make_points(sx, sy, t)
+    K = make_kernel(kern)
+    ws = _scratch(("propose", str(sx.device)), int(lib.vif_propose_ws(int(n))), sx.device)
+    nfb = ctypes.c_int64(0)
+    _check(lib.vif_propose_neighbors(ctypes.byref(p), ctypes.byref(K), int(m),
+                                     _dev_ptr(E, torch.float32, "E") if E is not None else None,
+                                     int(ncand), float(cell), int(lags), int(cmax),
+                                     _dev_ptr(nbr, torch.int32, "nbr") if m > 0 else None,
+                                     ctypes.byref(nfb), ws.data_ptr(), ws.numel(),
+                                     _stream(stream)))
+    return nbr, int(nfb.value)

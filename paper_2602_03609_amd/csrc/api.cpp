@@ -12,6 +12,7 @@
 
 #include "internal.hpp"
 #include "vif.h"
+#include "vif_learn.h"
 
 namespace {
 
@@ -86,6 +87,8 @@ void prof_collect() {
 int kpad_of(int k) { return k > 0 ? ((k + 1 + 63) / 64) * 64 : 0; }
 
 struct Layout {
+  size_t c2 = 0, f2 = 0, b2 = 0, k2 = 0, px2 = 0, py2 = 0, pi2 = 0, pflag = 0, plist = 0,
+         pcount = 0;  // proposal search
   size_t flags = 0, out = 0, part = 0, sums = 0, logD = 0, z = 0, Sk = 0, P = 0, Pb = 0, U = 0, W = 0,
          syrk = 0, M = 0, q = 0, dscr = 0, tab1 = 0, tab2 = 0, bnd = 0, bbox = 0, counts = 0,
          fill = 0, bsum = 0, key = 0, px = 0, py = 0, pidx = 0, total = 0;
@@ -164,6 +167,29 @@ Layout make_layout(int64_t n, int m, int k, int prec, int op) {
       L.q = take(sizeof(double) * L.kpad);
     }
   }
+  L.total = off;
+  return L;
+}
+
+// Exact-search layout plus the proposal grid, fallback flags and list.
+Layout make_propose_layout(int64_t n) {
+  Layout L = make_layout(n, 1, 0, VIF_PREC_FP64, VIF_OP_NEIGHBORS);
+  size_t off = L.total;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off += align256(bytes);
+    return at;
+  };
+  L.c2 = take(sizeof(int32_t) * ((size_t)vif::kMaxCells + 1));
+  L.f2 = take(sizeof(int32_t) * ((size_t)vif::kMaxCells + 1));
+  L.b2 = take(sizeof(int32_t) * ((size_t)vif::kMaxCells / 1024 + 2));
+  L.k2 = take(sizeof(int32_t) * (size_t)n);
+  L.px2 = take(sizeof(double) * (size_t)n);
+  L.py2 = take(sizeof(double) * (size_t)n);
+  L.pi2 = take(sizeof(int32_t) * (size_t)n);
+  L.pflag = take(sizeof(int32_t) * (size_t)n);
+  L.plist = take(sizeof(int32_t) * (size_t)n);
+  L.pcount = take(256);
   L.total = off;
   return L;
 }
@@ -469,73 +495,45 @@ int32_t nll_impl(const vif_points* p, const double* y, const vif_kernel* kern, i
 
 }  // namespace
 
-extern "C" {
+// Shared by the exact and the proposal search: validates times, reads the
+// bounding box, uploads the per-lag tables and fills the search arguments.
+struct SearchSetup {
+  double tt[2], bb[4];
+  int Lmax = 0;
+  int mode = 0;
+  std::vector<double> tab;  // host tables; must outlive the copies (caller syncs)
+  vif::NbrArgs a{};
+};
 
-size_t vif_workspace_bytes(int64_t n, int32_t m, int32_t k, int32_t prec, int32_t op) {
-  if (n < 1 || m < 0 || m > VIF_MAX_M || k < 0 || k > VIF_MAX_K) return 0;
-  if (prec < VIF_PREC_FP64 || prec > VIF_PREC_BF16X6) return 0;
-  if (op < VIF_OP_NEIGHBORS || op > VIF_OP_NLL) return 0;
-  return make_layout(n, m, k, prec, op).total;
-}
-
-const char* vif_last_error(void) { return g_err.c_str(); }
-
-int32_t vif_profile(int32_t enable) {
-  g_prof.on = enable != 0;
-  for (int st = 0; st < VIF_NSTAGES; ++st) {
-    g_prof.total_ms[st] = 0.0;
-    g_prof.calls[st] = 0;
-    g_prof.used[st] = false;
-  }
-  return ok();
-}
-
-int32_t vif_profile_read(double* total_ms, int32_t* calls, int32_t cap) {
-  if (!total_ms || !calls || cap < 0) return fail(VIF_E_ARG, "NULL output or negative cap");
-  const int nst = cap < VIF_NSTAGES ? cap : VIF_NSTAGES;
-  for (int st = 0; st < nst; ++st) {
-    total_ms[st] = g_prof.total_ms[st];
-    calls[st] = g_prof.calls[st];
-  }
-  return ok();
-}
-
-int32_t vif_neighbors(const vif_points* p, const vif_kernel* kern, int32_t m, int32_t* nbr,
-                      void* wsv, size_t ws_bytes, void* hip_stream) {
-  if (!p) return fail(VIF_E_ARG, "points is NULL");
-  const Layout L = make_layout(p->n, m, 0, VIF_PREC_FP64, VIF_OP_NEIGHBORS);
-  int32_t st = check_common(p, kern, m, wsv, ws_bytes, L.total);
-  if (st) return st;
-  if (m > 0 && !nbr) return fail(VIF_E_ARG, "nbr is NULL");
-  if (m == 0) return ok();
-  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-  char* ws = reinterpret_cast<char*>(wsv);
+int32_t search_setup(const vif_points* p, const vif_kernel* kern, int32_t m, int32_t* nbr,
+                     char* ws, const Layout& L, hipStream_t s, SearchSetup* S) {
+  int32_t st;
   if ((st = init_flags(ws, L, s))) return st;
   Flags* dflags = reinterpret_cast<Flags*>(ws + L.flags);
   double* bbox = reinterpret_cast<double*>(ws + L.bbox);
   HIPCHK(vif::launch_validate_times(p->n, p->t, &dflags->tflag, s));
   HIPCHK(vif::launch_bbox(p->n, p->sx, p->sy, bbox, bbox + 4 * 256, s));
   Flags f;
-  double tt[2], bb[4];
   HIPCHK(hipMemcpyAsync(&f, ws + L.flags, sizeof(f), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&tt[0], p->t, sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&tt[1], p->t + (p->n - 1), sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(bb, bbox + 4 * 256, sizeof(bb), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&S->tt[0], p->t, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&S->tt[1], p->t + (p->n - 1), sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(S->bb, bbox + 4 * 256, sizeof(S->bb), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (!isfinite(bb[0]) || !isfinite(bb[1]) || !isfinite(bb[2]) || !isfinite(bb[3]))
+  if (!isfinite(S->bb[0]) || !isfinite(S->bb[1]) || !isfinite(S->bb[2]) || !isfinite(S->bb[3]))
     return fail(VIF_E_ARG, "coordinates must be finite");
   if (f.tflag & 1u) return fail(VIF_E_ARG, "times must be finite");
   if (f.tflag & 2u) return fail(VIF_E_UNSUPPORTED, "neighbor search requires integer-valued times");
   if (f.tflag & 4u) return fail(VIF_E_ARG, "times must be nondecreasing in index");
-  const double span = tt[1] - tt[0];
+  const double span = S->tt[1] - S->tt[0];
   if (!(span >= 0) || span >= (double)VIF_MAX_LAGS)
     return fail(VIF_E_UNSUPPORTED, "time span %g exceeds VIF_MAX_LAGS - 1", span);
   const int Lmax = (int)span;
+  S->Lmax = Lmax;
 
   // Per-lag factors from the host C math library, in the operation order the
   // ranking key specifies; bnd is the suffix maximum of -tab1.
-  std::vector<double> tab((size_t)3 * (Lmax + 1), 0.0);
-  double* tab1 = tab.data();
+  S->tab.assign((size_t)3 * (Lmax + 1), 0.0);
+  double* tab1 = S->tab.data();
   double* tab2 = tab1 + (Lmax + 1);
   double* bnd = tab2 + (Lmax + 1);
   int mode;
@@ -574,7 +572,29 @@ int32_t vif_neighbors(const vif_points* p, const vif_kernel* kern, int32_t m, in
   HIPCHK(hipMemcpyAsync(ws + L.tab1, tab1, sizeof(double) * (Lmax + 1), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ws + L.tab2, tab2, sizeof(double) * (Lmax + 1), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ws + L.bnd, bnd, sizeof(double) * (Lmax + 1), hipMemcpyHostToDevice, s));
-  // Spatial grid: about kCellTarget points of one time slab per cell.
+  S->mode = mode;
+  vif::NbrArgs& a = S->a;
+  a.n = p->n;
+  a.m = m;
+  a.mode = mode;
+  a.nu_code = kd.nu_code;
+  a.ir_s = kern->kind == VIF_KERNEL_MATERN_ANISO ? 1.0 / kern->range_s : 0.0;
+  a.gamma = kern->gamma;
+  a.t0 = S->tt[0];
+  a.sx = p->sx; a.sy = p->sy; a.t = p->t;
+  a.tab1 = reinterpret_cast<const double*>(ws + L.tab1);
+  a.tab2 = reinterpret_cast<const double*>(ws + L.tab2);
+  a.bnd = reinterpret_cast<const double*>(ws + L.bnd);
+  a.nbr = nbr;
+  return VIF_OK;
+}
+
+// The exact search's grid: about kCellTarget points of one time slab per cell.
+int32_t exact_grid(const vif_points* p, char* ws, const Layout& L, hipStream_t s,
+                   const SearchSetup& S, vif::GridArgs* out) {
+  const int Lmax = S.Lmax;
+  const double* bb = S.bb;
+  const double* tt = S.tt;
   vif::GridArgs g{};
   {
     const int nslab = Lmax + 1;
@@ -616,7 +636,6 @@ int32_t vif_neighbors(const vif_points* p, const vif_kernel* kern, int32_t m, in
     g.py = reinterpret_cast<const double*>(ws + L.py);
     g.pidx = reinterpret_cast<const int32_t*>(ws + L.pidx);
   }
-  PROF(VIF_STAGE_NEIGHBORS, false);
   HIPCHK(vif::launch_grid_build(p->n, p->sx, p->sy, p->t, tt[0], g,
                                 reinterpret_cast<int32_t*>(ws + L.counts),
                                 reinterpret_cast<int32_t*>(ws + L.fill),
@@ -625,20 +644,57 @@ int32_t vif_neighbors(const vif_points* p, const vif_kernel* kern, int32_t m, in
                                 reinterpret_cast<double*>(ws + L.px),
                                 reinterpret_cast<double*>(ws + L.py),
                                 reinterpret_cast<int32_t*>(ws + L.pidx), s));
-  vif::NbrArgs a{};
-  a.n = p->n;
-  a.m = m;
-  a.mode = mode;
-  a.nu_code = kd.nu_code;
-  a.ir_s = kern->kind == VIF_KERNEL_MATERN_ANISO ? 1.0 / kern->range_s : 0.0;
-  a.gamma = kern->gamma;
-  a.t0 = tt[0];
-  a.sx = p->sx; a.sy = p->sy; a.t = p->t;
-  a.tab1 = reinterpret_cast<const double*>(ws + L.tab1);
-  a.tab2 = reinterpret_cast<const double*>(ws + L.tab2);
-  a.bnd = reinterpret_cast<const double*>(ws + L.bnd);
-  a.nbr = nbr;
-  HIPCHK(vif::launch_neighbors(a, g, s));
+  *out = g;
+  return VIF_OK;
+}
+
+extern "C" {
+
+size_t vif_workspace_bytes(int64_t n, int32_t m, int32_t k, int32_t prec, int32_t op) {
+  if (n < 1 || m < 0 || m > VIF_MAX_M || k < 0 || k > VIF_MAX_K) return 0;
+  if (prec < VIF_PREC_FP64 || prec > VIF_PREC_BF16X6) return 0;
+  if (op < VIF_OP_NEIGHBORS || op > VIF_OP_NLL) return 0;
+  return make_layout(n, m, k, prec, op).total;
+}
+
+const char* vif_last_error(void) { return g_err.c_str(); }
+
+int32_t vif_profile(int32_t enable) {
+  g_prof.on = enable != 0;
+  for (int st = 0; st < VIF_NSTAGES; ++st) {
+    g_prof.total_ms[st] = 0.0;
+    g_prof.calls[st] = 0;
+    g_prof.used[st] = false;
+  }
+  return ok();
+}
+
+int32_t vif_profile_read(double* total_ms, int32_t* calls, int32_t cap) {
+  if (!total_ms || !calls || cap < 0) return fail(VIF_E_ARG, "NULL output or negative cap");
+  const int nst = cap < VIF_NSTAGES ? cap : VIF_NSTAGES;
+  for (int st = 0; st < nst; ++st) {
+    total_ms[st] = g_prof.total_ms[st];
+    calls[st] = g_prof.calls[st];
+  }
+  return ok();
+}
+
+int32_t vif_neighbors(const vif_points* p, const vif_kernel* kern, int32_t m, int32_t* nbr,
+                      void* wsv, size_t ws_bytes, void* hip_stream) {
+  if (!p) return fail(VIF_E_ARG, "points is NULL");
+  const Layout L = make_layout(p->n, m, 0, VIF_PREC_FP64, VIF_OP_NEIGHBORS);
+  int32_t st = check_common(p, kern, m, wsv, ws_bytes, L.total);
+  if (st) return st;
+  if (m > 0 && !nbr) return fail(VIF_E_ARG, "nbr is NULL");
+  if (m == 0) return ok();
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  char* ws = reinterpret_cast<char*>(wsv);
+  SearchSetup S;
+  if ((st = search_setup(p, kern, m, nbr, ws, L, s, &S))) return st;
+  PROF(VIF_STAGE_NEIGHBORS, false);
+  vif::GridArgs g{};
+  if ((st = exact_grid(p, ws, L, s, S, &g))) return st;
+  HIPCHK(vif::launch_neighbors(S.a, g, s));
   PROF(VIF_STAGE_NEIGHBORS, true);
   // The host tables must outlive the copies above.
   HIPCHK(hipStreamSynchronize(s));
@@ -700,6 +756,181 @@ int32_t vif_nll_terms(const vif_points* p, const double* y, const vif_kernel* ke
                       const int32_t* nbr, const vif_points* ind, int32_t prec, double* nll,
                       double* terms, void* ws, size_t ws_bytes, void* hip_stream) {
   return nll_impl(p, y, kern, m, nbr, ind, prec, nll, terms, ws, ws_bytes, hip_stream);
+}
+
+
+// ---------------------------------------------------------- learned proposal ----
+int32_t vif_mlp_features(const vif_points* p, const vif_kernel* kern, const double* centre,
+                         float* X, void* hip_stream) {
+  if (!p || !kern || !centre || !X) return fail(VIF_E_ARG, "NULL argument");
+  int32_t st = check_points(p, "points");
+  if (st) return st;
+  if (kern->kind != VIF_KERNEL_GNEITING)
+    return fail(VIF_E_UNSUPPORTED, "features need the Gneiting kernel (log a, c, alpha, beta, gamma)");
+  if (!(kern->a > 0) || !(kern->c > 0) || !(kern->alpha > 0) || !(kern->beta > 0) ||
+      !(kern->gamma > 0))
+    return fail(VIF_E_ARG, "a, c, alpha, beta, gamma must be positive");
+  if (!(centre[3] > 0) || !(centre[4] > 0)) return fail(VIF_E_ARG, "scales must be positive");
+  vif::FeatArgs f{};
+  f.cx = centre[0]; f.cy = centre[1]; f.ct = centre[2]; f.ss = centre[3]; f.st = centre[4];
+  const double hp[5] = {kern->a, kern->c, kern->alpha, kern->beta, kern->gamma};
+  for (int c = 0; c < 5; ++c) f.hyper[c] = log(hp[c]) - centre[5 + c];
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  HIPCHK(vif::launch_features(p->n, p->sx, p->sy, p->t, f, X, s));
+  return ok();
+}
+
+int32_t vif_mlp_forward(const float* params, const float* X, int64_t rows, float* E, float* H,
+                        void* hip_stream) {
+  if (rows < 0) return fail(VIF_E_ARG, "rows < 0");
+  if (rows > 0 && (!params || !X || !E)) return fail(VIF_E_ARG, "NULL argument");
+  if (rows > ((int64_t)1 << 31) / 192) return fail(VIF_E_UNSUPPORTED, "too many rows");
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  HIPCHK(vif::launch_mlp_forward(rows, params, X, E, H, s));
+  return ok();
+}
+
+size_t vif_mlp_backward_ws(int64_t rows) {
+  if (rows < 0) return 0;
+  return align256(sizeof(float) * (size_t)(vif::mlp_backward_blocks(rows) + 1) * VIF_MLP_PARAMS);
+}
+
+int32_t vif_mlp_backward(const float* params, const float* X, const float* H, const float* dE,
+                         int64_t rows, float* grad, void* ws, size_t ws_bytes, void* hip_stream) {
+  if (rows < 0) return fail(VIF_E_ARG, "rows < 0");
+  if (!params || !grad || (rows > 0 && (!X || !H || !dE))) return fail(VIF_E_ARG, "NULL argument");
+  if (rows > ((int64_t)1 << 31) / 192) return fail(VIF_E_UNSUPPORTED, "too many rows");
+  if (!ws || ws_bytes < vif_mlp_backward_ws(rows))
+    return fail(VIF_E_WORKSPACE, "workspace too small: %zu < %zu", ws_bytes,
+                vif_mlp_backward_ws(rows));
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  HIPCHK(vif::launch_mlp_backward(rows, params, X, H, dE, reinterpret_cast<float*>(ws), grad, s));
+  return ok();
+}
+
+int32_t vif_mlp_pair_loss(const float* E, int64_t groups, int32_t npos, int32_t nneg, float tau,
+                          float* dE, float* loss, void* hip_stream) {
+  if (groups < 0 || npos < 1 || nneg < 1 || npos + nneg > 128 || !(tau > 0))
+    return fail(VIF_E_ARG, "need groups >= 0, npos, nneg >= 1, npos + nneg <= 128, tau > 0");
+  if (groups > 0 && (!E || !dE || !loss)) return fail(VIF_E_ARG, "NULL argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  HIPCHK(vif::launch_pair_loss(groups, npos, nneg, tau, E, dE, loss, s));
+  return ok();
+}
+
+int32_t vif_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t count,
+                     int32_t step, float lr, float beta1, float beta2, float eps,
+                     void* hip_stream) {
+  if (count < 0 || step < 1) return fail(VIF_E_ARG, "need count >= 0 and step >= 1");
+  if (count > 0 && (!params || !grad || !m || !v)) return fail(VIF_E_ARG, "NULL argument");
+  if (!(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return fail(VIF_E_ARG, "bad Adam constants");
+  const float c1 = (float)(1.0 - pow((double)beta1, (double)step));
+  const float c2 = (float)(1.0 - pow((double)beta2, (double)step));
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  HIPCHK(vif::launch_adam(count, params, grad, m, v, lr, beta1, beta2, eps, c1, c2, s));
+  return ok();
+}
+
+int32_t vif_mlp_batch(const float* X, const int32_t* queries, int64_t nq, const int32_t* nbr_ext,
+                      int32_t m_ext, int32_t npos, int32_t nhard, int32_t nrand,
+                      const uint32_t* rnd, int32_t rand_window, float* Xb, void* hip_stream) {
+  if (nq < 0 || npos < 1 || nhard < 0 || nrand < 0 || m_ext < npos + nhard || rand_window < 1)
+    return fail(VIF_E_ARG, "bad batch sizes");
+  if (nhard == 0 && nrand > 0)
+    return fail(VIF_E_ARG, "random negatives need at least one hard negative");
+  if (nq > 0 && (!X || !queries || !nbr_ext || !Xb || (nrand > 0 && !rnd)))
+    return fail(VIF_E_ARG, "NULL argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  HIPCHK(vif::launch_batch(nq, queries, nbr_ext, m_ext, npos, nhard, nrand, rnd, rand_window, X,
+                           Xb, s));
+  return ok();
+}
+
+size_t vif_propose_ws(int64_t n) {
+  if (n < 1) return 0;
+  return make_propose_layout(n).total;
+}
+
+int32_t vif_propose_neighbors(const vif_points* p, const vif_kernel* kern, int32_t m,
+                              const float* E, int32_t ncand, double cell, int32_t lags,
+                              int32_t cmax, int32_t* nbr, int64_t* n_fallback, void* wsv,
+                              size_t ws_bytes, void* hip_stream) {
+  if (!p) return fail(VIF_E_ARG, "points is NULL");
+  const Layout L = make_propose_layout(p->n);
+  int32_t st = check_common(p, kern, m, wsv, ws_bytes, L.total);
+  if (st) return st;
+  if (m > 0 && !nbr) return fail(VIF_E_ARG, "nbr is NULL");
+  if (ncand < m || ncand > 128) return fail(VIF_E_ARG, "need m <= ncand <= 128");
+  if (!(cell > 0) || !isfinite(cell)) return fail(VIF_E_ARG, "cell must be positive");
+  if (lags < 0) return fail(VIF_E_ARG, "lags < 0");
+  if (cmax < 1 || cmax > vif::kProposeCmax)
+    return fail(VIF_E_ARG, "cmax must be in 1..%d", vif::kProposeCmax);
+  if (n_fallback) *n_fallback = 0;
+  if (m == 0) return ok();
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  char* ws = reinterpret_cast<char*>(wsv);
+  SearchSetup S;
+  if ((st = search_setup(p, kern, m, nbr, ws, L, s, &S))) return st;
+  // proposal grid: square cells of side `cell`
+  const double ih = 1.0 / cell;
+  const double gxd = (S.bb[1] - S.bb[0]) * ih + 1.0, gyd = (S.bb[3] - S.bb[2]) * ih + 1.0;
+  const int nslab = S.Lmax + 1;
+  if (gxd * gyd * nslab > (double)vif::kMaxCells)
+    return fail(VIF_E_UNSUPPORTED, "cell too small: %.0f cells exceed %d", gxd * gyd * nslab,
+                vif::kMaxCells);
+  vif::GridArgs g2{};
+  g2.gx = (int)((S.bb[1] - S.bb[0]) * ih) + 1;
+  g2.gy = (int)((S.bb[3] - S.bb[2]) * ih) + 1;
+  g2.ncell = g2.gx * g2.gy;
+  g2.nslab = nslab;
+  g2.morton = 0;
+  g2.xmin = S.bb[0];
+  g2.ymin = S.bb[2];
+  g2.cw = cell;
+  g2.ch = cell;
+  g2.icw = ih;
+  g2.ich = ih;
+  g2.off = reinterpret_cast<const int32_t*>(ws + L.c2);
+  g2.px = reinterpret_cast<const double*>(ws + L.px2);
+  g2.py = reinterpret_cast<const double*>(ws + L.py2);
+  g2.pidx = reinterpret_cast<const int32_t*>(ws + L.pi2);
+  HIPCHK(vif::launch_grid_build(p->n, p->sx, p->sy, p->t, S.tt[0], g2,
+                                reinterpret_cast<int32_t*>(ws + L.c2),
+                                reinterpret_cast<int32_t*>(ws + L.f2),
+                                reinterpret_cast<int32_t*>(ws + L.b2),
+                                reinterpret_cast<int32_t*>(ws + L.k2),
+                                reinterpret_cast<double*>(ws + L.px2),
+                                reinterpret_cast<double*>(ws + L.py2),
+                                reinterpret_cast<int32_t*>(ws + L.pi2), s));
+  vif::ProposeArgs pa{};
+  pa.ncand = ncand;
+  pa.lags = lags;
+  pa.cmax = cmax;
+  pa.E = E;
+  pa.fallback = reinterpret_cast<int32_t*>(ws + L.pflag);
+  int32_t* count = reinterpret_cast<int32_t*>(ws + L.pcount);
+  PROF(VIF_STAGE_NEIGHBORS, false);
+  HIPCHK(vif::launch_propose(S.a, g2, pa, s));
+  HIPCHK(vif::launch_zero_i32(count, 1, s));
+  HIPCHK(vif::launch_compact(p->n, pa.fallback, reinterpret_cast<int32_t*>(ws + L.plist), count,
+                             s));
+  int32_t nfb = 0;
+  HIPCHK(hipMemcpyAsync(&nfb, count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (nfb > 0) {
+    vif::GridArgs g{};
+    if ((st = exact_grid(p, ws, L, s, S, &g))) return st;
+    vif::NbrArgs a = S.a;
+    a.qlist = reinterpret_cast<const int32_t*>(ws + L.plist);
+    a.n = nfb;
+    HIPCHK(vif::launch_neighbors(a, g, s));
+  }
+  PROF(VIF_STAGE_NEIGHBORS, true);
+  HIPCHK(hipStreamSynchronize(s));
+  prof_collect();
+  if (n_fallback) *n_fallback = nfb;
+  return ok();
 }
 
 }  // extern "C"

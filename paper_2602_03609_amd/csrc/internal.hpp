@@ -22,6 +22,7 @@ struct NbrArgs {
   const double *sx, *sy, *t;
   const double *tab1, *tab2, *bnd;
   int32_t* nbr;
+  const int32_t* qlist;  // when set, query w of the launch is point qlist[w] (n = list length)
 };
 
 // Uniform spatial grid shared by all time slabs; cell (cx, cy) of slab l holds
@@ -38,6 +39,43 @@ struct GridArgs {
 };
 
 constexpr int kMaxCells = 1 << 22;  // nslab * ncell
+
+// Candidate proposal (learned embedding or spatial distance) + exact rerank.
+struct ProposeArgs {
+  int ncand;            // candidates kept for the exact rerank (<= 128)
+  int lags;             // window: slabs t_i - lags .. t_i
+  int cmax;             // larger windows fall back to the exact search (<= kProposeCmax)
+  const float* E;       // [n, 16] embeddings, or NULL: spatial distance
+  int32_t* fallback;    // [n] 1 where the row must come from the exact search
+};
+constexpr int kProposeCmax = 1024;
+hipError_t launch_propose(const NbrArgs& a, const GridArgs& g, const ProposeArgs& pa,
+                          hipStream_t s);
+// p[0 .. cnt) = 0.
+hipError_t launch_zero_i32(int32_t* p, int64_t cnt, hipStream_t s);
+// Compacts i with flag[i] != 0 into list, count into *count (device, zeroed first).
+hipError_t launch_compact(int64_t n, const int32_t* flag, int32_t* list, int32_t* count,
+                          hipStream_t s);
+
+// ---- learned proposal network (learn.hip) -------------------------------------
+struct FeatArgs {
+  double cx, cy, ct, ss, st;  // coordinate centre and scales
+  double hyper[5];            // log a, log c, log alpha, log beta, log gamma minus centres
+};
+hipError_t launch_features(int64_t n, const double* sx, const double* sy, const double* t,
+                           const FeatArgs& f, float* X, hipStream_t s);
+hipError_t launch_mlp_forward(int64_t rows, const float* params, const float* X, float* E,
+                              float* H, hipStream_t s);
+int64_t mlp_backward_blocks(int64_t rows);
+hipError_t launch_mlp_backward(int64_t rows, const float* params, const float* X, const float* H,
+                               const float* dE, float* part, float* grad, hipStream_t s);
+hipError_t launch_pair_loss(int64_t groups, int npos, int nneg, float tau, const float* E,
+                            float* dE, float* loss, hipStream_t s);
+hipError_t launch_adam(int64_t count, float* p, const float* g, float* m, float* v, float lr,
+                       float b1, float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t launch_batch(int64_t nq, const int32_t* queries, const int32_t* nbr_ext, int m_ext,
+                        int npos, int nhard, int nrand, const uint32_t* rnd, int rand_window,
+                        const float* X, float* Xb, hipStream_t s);
 
 // Checks finite, integer-valued, nondecreasing times; sets bits in *flag.
 hipError_t launch_validate_times(int64_t n, const double* t, uint32_t* flag, hipStream_t s);

@@ -370,8 +370,9 @@ __device__ __forceinline__ void scan_run(const NbrArgs& A, const GridArgs& G, co
 template <int MODE>
 __global__ __launch_bounds__(256) void neighbors_grid_kernel(NbrArgs A, GridArgs G) {
   const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= A.n) return;  // uniform per wave
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= A.n) return;  // uniform per wave
+  const int64_t i = A.qlist ? (int64_t)A.qlist[w] : w;
   const int m = A.m;
   const double qx = A.sx[i], qy = A.sy[i];
   const int ti = (int)(A.t[i] - A.t0);
@@ -471,6 +472,182 @@ hipError_t launch_grid_build(int64_t n, const double* sx, const double* sy, cons
   return hipGetLastError();
 }
 
+// ------------------------------------------------------- candidate proposal ----
+// One wavefront per query. The window (earlier points of slabs t_i - lags .. t_i
+// in the 3 x 3 grid cells around the query) is scored -- squared embedding
+// distance in FP32 (dimension order, no contraction) or squared spatial distance
+// in FP64 -- into LDS; a bitonic sort on (score, index) picks the ncand best;
+// their exact ranking keys (the key of the exact search) are sorted on
+// (key descending, index ascending) and the first m written. Windows smaller
+// than min(i, m) or larger than cmax set the row's fallback flag instead.
+__device__ __forceinline__ float emb_dist(const float* __restrict__ ei,
+                                          const float* __restrict__ ej) {
+#pragma clang fp contract(off)
+  float acc = 0.f;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const float d = ei[k] - ej[k];
+    const float d2 = d * d;
+    acc = acc + d2;
+  }
+  return acc;
+}
+
+__device__ __forceinline__ double spatial_dist(double dx, double dy) {
+#pragma clang fp contract(off)
+  const double a = dx * dx;
+  const double b = dy * dy;
+  return a + b;
+}
+
+// (ka, ia) before (kb, ib) in ascending score order, ties to the lower index.
+__device__ __forceinline__ bool asc_before(uint64_t ka, int ia, uint64_t kb, int ib) {
+  return ka < kb || (ka == kb && ia < ib);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void propose_kernel(NbrArgs A, GridArgs G, ProposeArgs P) {
+  constexpr int CM = kProposeCmax;
+  __shared__ uint64_t sk[4][CM];
+  __shared__ int32_t si[4][CM];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wv;
+  if (i >= A.n) return;  // uniform per wave
+  uint64_t* K = sk[wv];
+  int32_t* I = si[wv];
+  const int m = A.m;
+  const double qx = A.sx[i], qy = A.sy[i];
+  const int ti = (int)(A.t[i] - A.t0);
+  const int qcx = cell_of(qx, G.xmin, G.icw, G.gx);
+  const int qcy = cell_of(qy, G.ymin, G.ich, G.gy);
+  float ei[16];
+  if (P.E) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) ei[k] = P.E[i * 16 + k];
+  }
+  int cnt = 0;
+  const int lmax = P.lags < ti ? P.lags : ti;
+  for (int lag = 0; lag <= lmax; ++lag) {
+    const int slab = ti - lag;
+    const int32_t* off = G.off + (int64_t)slab * G.ncell;
+    for (int cy = qcy - 1; cy <= qcy + 1; ++cy) {
+      if (cy < 0 || cy >= G.gy) continue;
+      const int cx0 = qcx - 1 < 0 ? 0 : qcx - 1;
+      const int cx1 = qcx + 1 >= G.gx ? G.gx - 1 : qcx + 1;
+      // cells cx0..cx1 of one row are contiguous in the CSR order
+      const int beg = off[cy * G.gx + cx0], end = off[cy * G.gx + cx1 + 1];
+      for (int b0 = beg; b0 < end; b0 += 64) {
+        const int pos = b0 + lane;
+        bool ok = pos < end;
+        int j = 0;
+        uint64_t key = 0;
+        if (ok) {
+          j = G.pidx[pos];
+          ok = lag > 0 || (int64_t)j < i;
+        }
+        if (ok) {
+          if (P.E) {
+            const float d = emb_dist(ei, P.E + (int64_t)j * 16);
+            key = (uint64_t)__float_as_uint(d);
+          } else {
+            key = (uint64_t)__double_as_longlong(spatial_dist(G.px[pos] - qx, G.py[pos] - qy));
+          }
+        }
+        const unsigned long long bal = __ballot(ok);
+        const int at = cnt + __popcll(bal & ((1ull << lane) - 1ull));
+        if (ok && at < CM) {
+          K[at] = key;
+          I[at] = j;
+        }
+        cnt += __popcll(bal);
+      }
+    }
+  }
+  const int need = (int64_t)m < i ? m : (int)i;
+  if (cnt < need || cnt > P.cmax) {
+    if (lane == 0) P.fallback[i] = 1;
+    return;
+  }
+  if (lane == 0) P.fallback[i] = 0;
+  // pad to a power of two and sort ascending on (score, index)
+  int L2 = 1;
+  while (L2 < cnt) L2 <<= 1;
+  for (int e = cnt + lane; e < L2; e += 64) {
+    K[e] = ~0ull;
+    I[e] = INT_MAX;
+  }
+  wave_lds_sync();
+  for (int kk = 2; kk <= L2; kk <<= 1) {
+    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+      for (int e = lane; e < L2; e += 64) {
+        const int pt = e ^ jj;
+        if (pt > e) {
+          const uint64_t ka = K[e], kb = K[pt];
+          const int ia = I[e], ib = I[pt];
+          const bool up = (e & kk) == 0;
+          if (asc_before(kb, ib, ka, ia) == up) {
+            K[e] = kb; I[e] = ib;
+            K[pt] = ka; I[pt] = ia;
+          }
+        }
+      }
+      wave_lds_sync();
+    }
+  }
+  // exact keys of the first nc candidates, two per lane
+  const int nc = cnt < P.ncand ? cnt : P.ncand;
+  double kx[2];
+  int jx[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = lane + 64 * h;
+    kx[h] = -INFINITY;
+    jx[h] = INT_MAX;
+    if (e < nc) {
+      const int j = I[e];
+      const int lj = ti - (int)(A.t[j] - A.t0);
+      kx[h] = rank_key<MODE>(A.sx[j] - qx, A.sy[j] - qy, A.tab1[lj], A.tab2[lj], A);
+      jx[h] = j;
+    }
+  }
+  wave_lds_sync();
+  // sort the 128 (key, index) pairs on (key descending, index ascending) in LDS
+  double* DK = reinterpret_cast<double*>(K);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    DK[lane + 64 * h] = kx[h];
+    I[lane + 64 * h] = jx[h];
+  }
+  wave_lds_sync();
+  for (int kk = 2; kk <= 128; kk <<= 1) {
+    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int e = lane + 64 * h;
+        const int pt = e ^ jj;
+        if (pt > e) {
+          const double ka = DK[e], kb = DK[pt];
+          const int ia = I[e], ib = I[pt];
+          const bool up = (e & kk) == 0;
+          if (ranks_before(kb, ib, ka, ia) == up) {
+            DK[e] = kb; I[e] = ib;
+            DK[pt] = ka; I[pt] = ia;
+          }
+        }
+      }
+      wave_lds_sync();
+    }
+  }
+  if (lane < m) A.nbr[i * m + lane] = lane < nc ? I[lane] : -1;
+}
+
+__global__ void compact_kernel(int64_t n, const int32_t* __restrict__ flag,
+                               int32_t* __restrict__ list, int32_t* __restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !flag[i]) return;
+  list[atomicAdd(count, 1)] = (int32_t)i;
+}
+
 hipError_t launch_neighbors(const NbrArgs& a, const GridArgs& g, hipStream_t s) {
   if (a.n <= 0 || a.m <= 0) return hipSuccess;
   unsigned grid = (unsigned)((a.n + 3) / 4);
@@ -480,6 +657,33 @@ hipError_t launch_neighbors(const NbrArgs& a, const GridArgs& g, hipStream_t s) 
     case 2: hipLaunchKernelGGL(neighbors_grid_kernel<2>, dim3(grid), dim3(256), 0, s, a, g); break;
     default: hipLaunchKernelGGL(neighbors_grid_kernel<3>, dim3(grid), dim3(256), 0, s, a, g); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_propose(const NbrArgs& a, const GridArgs& g, const ProposeArgs& pa,
+                          hipStream_t s) {
+  if (a.n <= 0 || a.m <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((a.n + 3) / 4);
+  switch (a.mode) {
+    case 0: hipLaunchKernelGGL(propose_kernel<0>, dim3(grid), dim3(256), 0, s, a, g, pa); break;
+    case 1: hipLaunchKernelGGL(propose_kernel<1>, dim3(grid), dim3(256), 0, s, a, g, pa); break;
+    case 2: hipLaunchKernelGGL(propose_kernel<2>, dim3(grid), dim3(256), 0, s, a, g, pa); break;
+    default: hipLaunchKernelGGL(propose_kernel<3>, dim3(grid), dim3(256), 0, s, a, g, pa); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(int64_t n, const int32_t* flag, int32_t* list, int32_t* count,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(compact_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, flag,
+                     list, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_i32(int32_t* p, int64_t cnt, hipStream_t s) {
+  if (cnt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, p, cnt);
   return hipGetLastError();
 }
 

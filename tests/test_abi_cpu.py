@@ -1,5 +1,6 @@
 """CPU-side checks of the C ABI: the library loads and exports every function
-that include/vif.h declares, and the workspace query behaves (no GPU work)."""
+that the headers in include/ declare, and the workspace query behaves (no GPU
+work)."""
 import ctypes
 import os
 import re
@@ -7,19 +8,24 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "vif.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def declared_functions():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(vif_\w+)\s*\(", src, flags=re.M)))
+    fns = set()
+    for h in HEADERS:
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        fns |= set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(vif_\w+)\s*\(", src, flags=re.M))
+    return sorted(fns)
 
 
 def test_header_declares_expected_api():
     fns = declared_functions()
     for f in ("vif_workspace_bytes", "vif_neighbors", "vif_factor", "vif_nll", "vif_nll_terms",
-              "vif_last_error"):
+              "vif_last_error", "vif_mlp_forward", "vif_mlp_backward", "vif_mlp_pair_loss",
+              "vif_mlp_adam", "vif_mlp_batch", "vif_mlp_features", "vif_propose_neighbors"):
         assert f in fns
 
 
@@ -80,3 +86,27 @@ def test_argument_errors_before_any_launch():
                      ctypes.c_void_p(0x1000), None, 0, ctypes.byref(ctypes.c_double()),
                      ctypes.c_void_p(0x100000), 1 << 30, None)
     assert st == L.VIF_E_UNSUPPORTED
+
+
+def test_learned_proposal_argument_errors():
+    import paper_2602_03609_amd._lib as L
+    lib = L.load()
+    assert lib.vif_mlp_pair_loss(None, 4, 0, 3, 1.0, None, None, None) == L.VIF_E_ARG
+    assert lib.vif_mlp_pair_loss(None, 4, 100, 30, 1.0, None, None, None) == L.VIF_E_ARG
+    assert lib.vif_mlp_adam(None, None, None, None, 10, 0, 1e-3, 0.9, 0.999, 1e-8, None) == L.VIF_E_ARG
+    assert lib.vif_mlp_forward(None, None, 5, None, None, None) == L.VIF_E_ARG
+    assert lib.vif_mlp_backward_ws(1000) >= 16 * 9936 * 4
+    assert lib.vif_propose_ws(0) == 0 and lib.vif_propose_ws(1000) > 0
+    K = L.make_kernel({"kind": 1, "sigma2": 1.0, "nugget": 0.1, "a": 0.5, "c": 20.0, "alpha": 0.75,
+                       "beta": 0.5, "gamma": 0.5, "tau": 1.0})
+    P = L.Points()
+    P.n = 10
+    P.sx = P.sy = P.t = ctypes.c_void_p(0x1000)
+    nfb = ctypes.c_int64(0)
+    # ncand above 128 and a NULL workspace are host-side errors
+    st = lib.vif_propose_neighbors(ctypes.byref(P), ctypes.byref(K), 5, None, 200, 1.0, 1, 64,
+                                   ctypes.c_void_p(0x1000), ctypes.byref(nfb), None, 0, None)
+    assert st == L.VIF_E_ARG
+    centre = (ctypes.c_double * 10)(*([0.0] * 10))
+    st = lib.vif_mlp_features(ctypes.byref(P), ctypes.byref(K), centre, ctypes.c_void_p(0x1000), None)
+    assert st == L.VIF_E_ARG and b"scale" in lib.vif_last_error()
