@@ -89,7 +89,9 @@ size_t vif_propose_ws(int64_t n);
 /* Proposal search. For point i, the window is every earlier point of the time
  * slabs t_i - lags .. t_i whose grid cell (square side `cell`, origin at the
  * minimum coordinates, cell index = trunc((x - min) / cell) clamped) is within
- * one cell of the query's in x and in y. The ncand (<= 128) window points of
+ * r cells of the query's in x and in y, r the smallest radius in 1..rmax whose
+ * cells hold at least wmin points of those slabs (the query's whole slab
+ * counted), else rmax. The ncand (<= 128) window points of
  * smallest |e_i - e_j|^2 (FP32, summed in dimension order, no fused
  * multiply-add), or of smallest squared spatial distance (FP64) when E is
  * NULL, ties to the lower index, are reranked by the exact key of
@@ -100,8 +102,8 @@ size_t vif_propose_ws(int64_t n);
  * stream. */
 int32_t vif_propose_neighbors(const vif_points* points, const vif_kernel* kern, int32_t m,
                               const float* E, int32_t ncand, double cell, int32_t lags,
-                              int32_t cmax, int32_t* nbr, int64_t* n_fallback, void* ws,
-                              size_t ws_bytes, void* hip_stream);
+                              int32_t wmin, int32_t rmax, int32_t cmax, int32_t* nbr,
+                              int64_t* n_fallback, void* ws, size_t ws_bytes, void* hip_stream);
 
 #ifdef __cplusplus
 }

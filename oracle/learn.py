@@ -17,12 +17,15 @@ This module is the FP64 reference for a learned shortcut to that search:
     softplus((d_p - d_n) / tau);
   * Adam;
   * the proposal search: for query i, the window is every earlier point of the
-    last L+1 time slabs whose grid cell (side h) is within one cell of the
-    query's in x and y; the ncand window points of smallest embedding distance
-    (FP32, fixed order, ties to the lower index) -- or, without a network, of
-    smallest spatial distance (FP64) -- are reranked by the exact key of the
-    correlation search and the best m kept. A row whose window holds fewer
-    than min(i, m) points or more than cmax points takes the exact search.
+    last L+1 time slabs whose grid cell (side h) is within r cells of the
+    query's in x and in y, r the smallest radius in 1..rmax at which those
+    cells hold at least wmin points of the L+1 slabs (all of them, later points
+    of the query's own slab included), else rmax. The ncand window points of
+    smallest embedding distance (FP32, fixed order, ties to the lower index)
+    -- or, without a network, of smallest spatial distance (FP64) -- are
+    reranked by the exact key of the correlation search and the best m kept.
+    A row whose window holds fewer than min(i, m) points or more than cmax
+    points takes the exact search.
 
 Nothing here is from the paper's text beyond the neighbor definition it
 reranks to; the network, loss and window are this library's design.
@@ -151,12 +154,26 @@ def grid_cells(sx, sy, h):
     return cx, cy
 
 
-def window(t, cx, cy, i, L):
-    """Earlier points of the last L+1 slabs within one cell of the query (sorted)."""
+def radius(t, cx, cy, i, L, wmin, rmax):
+    """Smallest r in 1..rmax whose cells hold at least wmin points of the slabs
+    t_i - L .. t_i (counting whole slabs), else rmax."""
+    lo = int(np.searchsorted(t, t[i] - L, side="left"))
+    hi = int(np.searchsorted(t, t[i], side="right"))
+    dx = np.abs(cx[lo:hi] - cx[i])
+    dy = np.abs(cy[lo:hi] - cy[i])
+    cheb = np.maximum(dx, dy)
+    for r in range(1, rmax + 1):
+        if int((cheb <= r).sum()) >= wmin:
+            return r
+    return rmax
+
+
+def window(t, cx, cy, i, L, r=1):
+    """Earlier points of the last L+1 slabs within r cells of the query (sorted)."""
     t0 = t[i] - L
     lo = int(np.searchsorted(t, t0, side="left"))
     js = np.arange(lo, i)
-    ok = (np.abs(cx[js] - cx[i]) <= 1) & (np.abs(cy[js] - cy[i]) <= 1)
+    ok = (np.abs(cx[js] - cx[i]) <= r) & (np.abs(cy[js] - cy[i]) <= r)
     return js[ok]
 
 
@@ -170,7 +187,7 @@ def emb_dist32(E, i, js):
     return acc
 
 
-def propose(kern, sx, sy, t, m, E, ncand, h, L, cmax, rows=None):
+def propose(kern, sx, sy, t, m, E, ncand, h, L, cmax, rows=None, wmin=0, rmax=1):
     """Proposal neighbor rows [len(rows), m] (-1 padded) and the fallback mask."""
     n = sx.shape[0]
     rows = np.arange(n) if rows is None else np.asarray(rows)
@@ -180,7 +197,8 @@ def propose(kern, sx, sy, t, m, E, ncand, h, L, cmax, rows=None):
     out = np.full((rows.shape[0], m), -1, dtype=np.int32)
     fb = np.zeros(rows.shape[0], dtype=bool)
     for r, i in enumerate(rows):
-        js = window(t, cx, cy, i, L)
+        rad = radius(t, cx, cy, i, L, wmin, rmax)
+        js = window(t, cx, cy, i, L, rad)
         if js.shape[0] < min(i, m) or js.shape[0] > cmax:
             fb[r] = True
             ex = NB.brute_force(kern, sx, sy, t, m, rows=[i])[0]

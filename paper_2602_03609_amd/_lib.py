@@ -97,8 +97,8 @@ def load(path=LIB_PATH):
         lib.vif_mlp_batch.restype = i32
         lib.vif_propose_ws.argtypes = [i64]
         lib.vif_propose_ws.restype = sz
-        lib.vif_propose_neighbors.argtypes = [pP, pK, i32, vp, i32, ctypes.c_double, i32, i32, vp,
-                                              ctypes.POINTER(i64), vp, sz, vp]
+        lib.vif_propose_neighbors.argtypes = [pP, pK, i32, vp, i32, ctypes.c_double, i32, i32,
+                                              i32, i32, vp, ctypes.POINTER(i64), vp, sz, vp]
         lib.vif_propose_neighbors.restype = i32
         _lib = lib
         return lib
@@ -370,7 +370,7 @@ def vif_mlp_batch(X, queries, nbr_ext, npos, nhard, nrand, rnd, rand_window, str
 
 
 def vif_propose_neighbors(sx, sy, t, kern, m, E, ncand, cell, lags, cmax=1024, nbr=None,
-                          stream=None):
+                          stream=None, wmin=0, rmax=1):
     """Proposal search (embedding or, with E=None, spatial candidates + exact rerank).
     Returns (nbr int32 [n, m], number of rows that took the exact search)."""
     torch = _torch()
@@ -384,7 +384,8 @@ def vif_propose_neighbors(sx, sy, t, kern, m, E, ncand, cell, lags, cmax=1024, n
     nfb = ctypes.c_int64(0)
     _check(lib.vif_propose_neighbors(ctypes.byref(p), ctypes.byref(K), int(m),
                                      _dev_ptr(E, torch.float32, "E") if E is not None else None,
-                                     int(ncand), float(cell), int(lags), int(cmax),
+                                     int(ncand), float(cell), int(lags), int(wmin), int(rmax),
+                                     int(cmax),
                                      _dev_ptr(nbr, torch.int32, "nbr") if m > 0 else None,
                                      ctypes.byref(nfb), ws.data_ptr(), ws.numel(),
                                      _stream(stream)))

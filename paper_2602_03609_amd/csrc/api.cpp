@@ -854,8 +854,9 @@ size_t vif_propose_ws(int64_t n) {
 
 int32_t vif_propose_neighbors(const vif_points* p, const vif_kernel* kern, int32_t m,
                               const float* E, int32_t ncand, double cell, int32_t lags,
-                              int32_t cmax, int32_t* nbr, int64_t* n_fallback, void* wsv,
-                              size_t ws_bytes, void* hip_stream) {
+                              int32_t wmin, int32_t rmax, int32_t cmax, int32_t* nbr,
+                              int64_t* n_fallback, void* wsv, size_t ws_bytes,
+                              void* hip_stream) {
   if (!p) return fail(VIF_E_ARG, "points is NULL");
   const Layout L = make_propose_layout(p->n);
   int32_t st = check_common(p, kern, m, wsv, ws_bytes, L.total);
@@ -864,6 +865,7 @@ int32_t vif_propose_neighbors(const vif_points* p, const vif_kernel* kern, int32
   if (ncand < m || ncand > 128) return fail(VIF_E_ARG, "need m <= ncand <= 128");
   if (!(cell > 0) || !isfinite(cell)) return fail(VIF_E_ARG, "cell must be positive");
   if (lags < 0) return fail(VIF_E_ARG, "lags < 0");
+  if (wmin < 0 || rmax < 1 || rmax > 1024) return fail(VIF_E_ARG, "need wmin >= 0, 1 <= rmax <= 1024");
   if (cmax < 1 || cmax > vif::kProposeCmax)
     return fail(VIF_E_ARG, "cmax must be in 1..%d", vif::kProposeCmax);
   if (n_fallback) *n_fallback = 0;
@@ -906,6 +908,8 @@ int32_t vif_propose_neighbors(const vif_points* p, const vif_kernel* kern, int32
   vif::ProposeArgs pa{};
   pa.ncand = ncand;
   pa.lags = lags;
+  pa.wmin = wmin;
+  pa.rmax = rmax;
   pa.cmax = cmax;
   pa.E = E;
   pa.fallback = reinterpret_cast<int32_t*>(ws + L.pflag);

@@ -44,6 +44,7 @@ constexpr int kMaxCells = 1 << 22;  // nslab * ncell
 struct ProposeArgs {
   int ncand;            // candidates kept for the exact rerank (<= 128)
   int lags;             // window: slabs t_i - lags .. t_i
+  int wmin, rmax;       // window radius: smallest r in 1..rmax with >= wmin points, else rmax
   int cmax;             // larger windows fall back to the exact search (<= kProposeCmax)
   const float* E;       // [n, 16] embeddings, or NULL: spatial distance
   int32_t* fallback;    // [n] 1 where the row must come from the exact search

@@ -474,7 +474,9 @@ hipError_t launch_grid_build(int64_t n, const double* sx, const double* sy, cons
 
 // ------------------------------------------------------- candidate proposal ----
 // One wavefront per query. The window (earlier points of slabs t_i - lags .. t_i
-// in the 3 x 3 grid cells around the query) is scored -- squared embedding
+// in the grid cells within r of the query's in x and y, r the smallest radius in
+// 1..rmax whose cells hold at least wmin points of those slabs, counted from the
+// cell offsets with the query's whole slab, else rmax) is scored -- squared embedding
 // distance in FP32 (dimension order, no contraction) or squared spatial distance
 // in FP64 -- into LDS; a bitonic sort on (score, index) picks the ncand best;
 // their exact ranking keys (the key of the exact search) are sorted on
@@ -527,13 +529,43 @@ __global__ __launch_bounds__(256) void propose_kernel(NbrArgs A, GridArgs G, Pro
   }
   int cnt = 0;
   const int lmax = P.lags < ti ? P.lags : ti;
+  // points of the slabs in the cells within radius r (CSR offsets; rows of cells
+  // are contiguous), summed over the wave
+  auto count_r = [&](int r) {
+    const int ny = 2 * r + 1;
+    const int cx0 = qcx - r < 0 ? 0 : qcx - r;
+    const int cx1 = qcx + r >= G.gx ? G.gx - 1 : qcx + r;
+    int part = 0;
+    for (int e = lane; e < ny * (lmax + 1); e += 64) {
+      const int lag = e / ny, cy = qcy - r + (e - lag * ny);
+      if (cy < 0 || cy >= G.gy) continue;
+      const int32_t* off = G.off + (int64_t)(ti - lag) * G.ncell + (int64_t)cy * G.gx;
+      part += off[cx1 + 1] - off[cx0];
+    }
+#pragma unroll
+    for (int sh = 32; sh > 0; sh >>= 1) part += __shfl_xor(part, sh);
+    return part;
+  };
+  int rad = P.rmax;
+  if (count_r(1) >= P.wmin) {
+    rad = 1;
+  } else {
+    int lo = 1, hi = P.rmax;  // count(lo) < wmin; find the smallest r with count >= wmin
+    if (count_r(hi) >= P.wmin) {
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (count_r(mid) >= P.wmin) hi = mid; else lo = mid;
+      }
+    }
+    rad = hi;
+  }
   for (int lag = 0; lag <= lmax; ++lag) {
     const int slab = ti - lag;
     const int32_t* off = G.off + (int64_t)slab * G.ncell;
-    for (int cy = qcy - 1; cy <= qcy + 1; ++cy) {
+    for (int cy = qcy - rad; cy <= qcy + rad; ++cy) {
       if (cy < 0 || cy >= G.gy) continue;
-      const int cx0 = qcx - 1 < 0 ? 0 : qcx - 1;
-      const int cx1 = qcx + 1 >= G.gx ? G.gx - 1 : qcx + 1;
+      const int cx0 = qcx - rad < 0 ? 0 : qcx - rad;
+      const int cx1 = qcx + rad >= G.gx ? G.gx - 1 : qcx + rad;
       // cells cx0..cx1 of one row are contiguous in the CSR order
       const int beg = off[cy * G.gx + cx0], end = off[cy * G.gx + cx1 + 1];
       for (int b0 = beg; b0 < end; b0 += 64) {

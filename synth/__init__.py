@@ -251,3 +251,18 @@ def perturb_hyper(kern, rng):
             lg = math.log(out[key] / (1.0 - out[key])) + rng.uniform(-1.0, 1.0)
             out[key] = float(1.0 / (1.0 + math.exp(-lg)))
     return out
+
+
+def config_station_days(seed=0, n_stations=3340, n_days=30, m=30, missing=0.1, perturb=False):
+    """Station network over a few days, no inducing points and no response: the
+    neighbor-search workload (training data of the learned proposal when
+    `perturb` draws its hyperparameters around the continental kernel)."""
+    rng = np.random.default_rng(seed)
+    sx, sy, t = station_days(n_stations, n_days, missing, rng)
+    sx, sy, t = time_stratified_order(sx, sy, t, rng)
+    kern = kern_gneiting(sigma2=1.0, a=1.0956, c=2.1277e-3, alpha=0.75, beta=0.5, gamma=0.5,
+                         tau=1.0, nugget=0.1)
+    if perturb:
+        kern = perturb_hyper(kern, rng)
+    return {"sx": sx, "sy": sy, "t": t, "kern": kern, "m": m, "n": int(sx.shape[0]), "k": 0,
+            "name": f"stations n={sx.shape[0]} m={m}"}

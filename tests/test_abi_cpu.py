@@ -104,8 +104,8 @@ def test_learned_proposal_argument_errors():
     P.sx = P.sy = P.t = ctypes.c_void_p(0x1000)
     nfb = ctypes.c_int64(0)
     # ncand above 128 and a NULL workspace are host-side errors
-    st = lib.vif_propose_neighbors(ctypes.byref(P), ctypes.byref(K), 5, None, 200, 1.0, 1, 64,
-                                   ctypes.c_void_p(0x1000), ctypes.byref(nfb), None, 0, None)
+    st = lib.vif_propose_neighbors(ctypes.byref(P), ctypes.byref(K), 5, None, 200, 1.0, 1, 0, 1,
+                                   64, ctypes.c_void_p(0x1000), ctypes.byref(nfb), None, 0, None)
     assert st == L.VIF_E_ARG
     centre = (ctypes.c_double * 10)(*([0.0] * 10))
     st = lib.vif_mlp_features(ctypes.byref(P), ctypes.byref(K), centre, ctypes.c_void_p(0x1000), None)

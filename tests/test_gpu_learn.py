@@ -132,20 +132,23 @@ CASES = {
 
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("use_e", [False, True])
-def test_propose_matches_oracle(name, use_e):
+@pytest.mark.parametrize("adaptive", [False, True])
+def test_propose_matches_oracle(name, use_e, adaptive):
     torch = torch_cuda()
     vif = lib()
     d = CASES[name]()
     X, _, _ = problem_on_device(d)
     n, m, kern = d["n"], d["m"], d["kern"]
     span_x = d["sx"].max() - d["sx"].min()
-    cell = span_x / 7.0
+    cell = span_x / (20.0 if adaptive else 7.0)
+    wmin, rmax = (4 * m, 9) if adaptive else (0, 1)
     E = np.random.default_rng(1).normal(size=(n, 16)).astype(np.float32) if use_e else None
     ncand, lags, cmax = min(4 * m, 128), 1, 600
     got, nfb = vif.vif_propose_neighbors(*X, kern, m, dev(E) if use_e else None, ncand, cell,
-                                         lags, cmax)
-    want, fb = LR.propose(kern, d["sx"], d["sy"], d["t"], m, E, ncand, cell, lags, cmax)
-    log(f"propose {name} E={use_e}: fallback {nfb} (oracle {int(fb.sum())})")
+                                         lags, cmax, wmin=wmin, rmax=rmax)
+    want, fb = LR.propose(kern, d["sx"], d["sy"], d["t"], m, E, ncand, cell, lags, cmax,
+                          wmin=wmin, rmax=rmax)
+    log(f"propose {name} E={use_e} adaptive={adaptive}: fallback {nfb} (oracle {int(fb.sum())})")
     assert nfb == int(fb.sum())
     assert np.array_equal(got.cpu().numpy(), want)
 
