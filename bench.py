@@ -50,7 +50,85 @@ def parse():
     ap.add_argument("--no-fp64-check", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (reference for HBM byte counters)")
+    ap.add_argument("--learned", action="store_true",
+                    help="also train the neighbor-proposal network on the GPU and evaluate it "
+                         "on the workload (recall, NLL change, search rate)")
+    ap.add_argument("--learn-steps", type=int, default=12000)
     return ap.parse_args()
+
+
+# Proposal window: 50 km cells, radius grown until 480 points of the two slabs
+# (lag 0 and 1) are inside, at most 30 cells; 4m candidates; windows above 1024
+# points take the exact search.
+PROPOSE = {"cell": 50.0, "lags": 1, "wmin": 480, "rmax": 30, "cmax": 1024}
+
+
+def learned_eval(args, d, X, y, Z, nbr_exact, t_exact_ms):
+    """Trains the proposal network on 32 station-network problems (half with perturbed
+    hyperparameters) and evaluates it on the workload against the exact search and against
+    spatial candidates."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2602_03609_amd as vif
+    from paper_2602_03609_amd import learn as LN
+
+    m = args.m
+    t0 = time.perf_counter()
+    # 30-day problems spread over the year (the network sees the workload's time range)
+    train = LN.training_problems(32, n_stations=args.stations, n_days=30, m=m)
+    torch.cuda.synchronize()
+    log(f"learned: 32 training problems ({sum(t.n for t in train)} points) in "
+        f"{time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    params, hist = LN.train(train, steps=args.learn_steps, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del train
+
+    ncand = min(4 * m, 128)
+    kern = d["kern"]
+
+    def run(E):
+        return vif.vif_propose_neighbors(*X, kern, m, E, ncand, PROPOSE["cell"], PROPOSE["lags"],
+                                         PROPOSE["cmax"], wmin=PROPOSE["wmin"],
+                                         rmax=PROPOSE["rmax"])
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - a) * 1000.0)
+        return out, float(np.median(ts))
+
+    (E, ), t_embed = timed(lambda: (LN.embed(params, X, kern),))
+    (nbr_l, nfb_l), t_prop = timed(lambda: run(E))
+    (nbr_s, nfb_s), t_sp = timed(lambda: run(None))
+    rec_l = LN.recall(nbr_l, nbr_exact)
+    rec_s = LN.recall(nbr_s, nbr_exact)
+    nll_e = vif.vif_nll(*X, y, kern, m, nbr_exact, ind=Z, prec="fp64")
+    nll_l = vif.vif_nll(*X, y, kern, m, nbr_l, ind=Z, prec="fp64")
+    nll_s = vif.vif_nll(*X, y, kern, m, nbr_s, ind=Z, prec="fp64")
+    n = d["n"]
+    res = {
+        "train_s": t_train, "train_steps": args.learn_steps, "final_loss": hist[-1][1],
+        "window": PROPOSE, "ncand": ncand,
+        "recall": rec_l, "recall_spatial_candidates": rec_s,
+        "fallback_rows": nfb_l, "fallback_rows_spatial": nfb_s,
+        "nll_exact_fp64": nll_e, "dnll_learned": nll_l - nll_e, "dnll_spatial": nll_s - nll_e,
+        "ms_embed": t_embed, "ms_propose": t_prop, "ms_exact": t_exact_ms,
+        "pts_per_s": n / ((t_embed + t_prop) / 1000.0), "pts_per_s_exact": n / (t_exact_ms / 1000.0),
+        "speedup_vs_exact": t_exact_ms / (t_embed + t_prop),
+    }
+    log(f"learned: recall {rec_l:.5f} (spatial candidates {rec_s:.5f}); dNLL {nll_l - nll_e:.4g} "
+        f"(spatial {nll_s - nll_e:.4g}); embed {t_embed:.2f} ms + propose {t_prop:.2f} ms vs exact "
+        f"{t_exact_ms:.2f} ms; fallback rows {nfb_l}")
+    return res
 
 
 def stage_work(n, m, k, kpad, es, prec):
@@ -327,6 +405,15 @@ def main():
         "stages": stages,
         "roofline": roof,
     }
+    if args.learned:
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(5):
+            a = time.perf_counter()
+            vif.vif_neighbors(*X, kern, m, nbr=nbr)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - a) * 1000.0)
+        out["learned_proposal"] = learned_eval(args, d, X, y, Z, nbr, float(np.median(ts)))
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(d, m)

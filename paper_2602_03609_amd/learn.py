@@ -6,10 +6,11 @@ used as labels, and the proposal search. PyTorch provides device memory and
 the uniform random integers that pick queries and random negatives.
 
 Training data: station-network problems like the continental workload (many
-seeds, hyperparameters perturbed around the workload's: +-1 in log for a and c,
-+-1 in logit for alpha, beta, gamma), labelled by the exact search
-(vif_neighbors with 2m neighbors: the first m are the positives, the next m the
-hard negatives), plus random earlier points as easy negatives.
+seeds, spread over the year; half of them with hyperparameters perturbed around
+the workload's: +-1 in log for a and c, +-1 in logit for alpha, beta, gamma),
+labelled by the exact search (vif_neighbors with 2m neighbors: the first m are
+the positives, the next m the hard negatives), plus random earlier points as
+easy negatives.
 """
 from __future__ import annotations
 
@@ -18,11 +19,22 @@ import time
 
 from . import _lib as L
 
-# Feature centre: workload-scale coordinates (km, days) and the continental
+# Feature centre: workload-scale coordinates (km) and days, and the continental
 # kernel's log hyperparameters (a = 1.0956, c = 2.1277e-3, alpha = 0.75,
-# beta = gamma = 0.5).
-CENTRE = (0.0, 0.0, 182.0, 1400.0, 105.0,
+# beta = gamma = 0.5). Time is scaled by 5 days, so that one day of lag weighs
+# about as much as the few hundred km of distance it is worth in correlation.
+CENTRE = (0.0, 0.0, 182.0, 1400.0, 5.0,
           math.log(1.0956), math.log(2.1277e-3), math.log(0.75), math.log(0.5), math.log(0.5))
+
+
+def training_problems(count=32, n_stations=3340, n_days=30, m=30, first_seed=1):
+    """Station-network problems spread over the year; odd seeds draw perturbed
+    hyperparameters, even seeds keep the workload's."""
+    import synth
+    return [Dataset(synth.config_station_days(seed=s, n_stations=n_stations, n_days=n_days, m=m,
+                                              perturb=(s % 2 == 1), day0=(37 * s) % (365 - n_days)),
+                    m)
+            for s in range(first_seed, first_seed + count)]
 
 
 def init_params(seed=0, device="cuda"):

@@ -253,13 +253,16 @@ def perturb_hyper(kern, rng):
     return out
 
 
-def config_station_days(seed=0, n_stations=3340, n_days=30, m=30, missing=0.1, perturb=False):
-    """Station network over a few days, no inducing points and no response: the
-    neighbor-search workload (training data of the learned proposal when
-    `perturb` draws its hyperparameters around the continental kernel)."""
+def config_station_days(seed=0, n_stations=3340, n_days=30, m=30, missing=0.1, perturb=False,
+                        day0=0):
+    """Station network over a few days (days day0 .. day0 + n_days - 1), no inducing
+    points and no response: the neighbor-search workload (training data of the
+    learned proposal when `perturb` draws its hyperparameters around the
+    continental kernel)."""
     rng = np.random.default_rng(seed)
     sx, sy, t = station_days(n_stations, n_days, missing, rng)
     sx, sy, t = time_stratified_order(sx, sy, t, rng)
+    t = t + float(day0)
     kern = kern_gneiting(sigma2=1.0, a=1.0956, c=2.1277e-3, alpha=0.75, beta=0.5, gamma=0.5,
                          tau=1.0, nugget=0.1)
     if perturb:

@@ -162,3 +162,26 @@ def test_propose_full_window_equals_exact_search():
                                          int(d["t"][-1] - d["t"][0]), 1024)
     exact = vif.vif_neighbors(*X, d["kern"], d["m"])
     assert torch.equal(got, exact)
+
+
+def test_trained_network_beats_spatial_candidates():
+    """What the network gains: trained on the GPU by the library's own kernels, its
+    candidates recover more exact neighbors than the same budget drawn from the same
+    window by spatial distance (on a held-out problem)."""
+    torch = torch_cuda()
+    vif = lib()
+    from paper_2602_03609_amd import learn as LN
+    m = 30
+    train = LN.training_problems(8, n_days=8, m=m)
+    params, hist = LN.train(train, steps=2500, log_every=500, log=log)
+    ev = synth.config_station_days(seed=100, n_days=8, m=m, day0=120)
+    X = tuple(dev(ev[k], torch.float64) for k in ("sx", "sy", "t"))
+    exact = vif.vif_neighbors(*X, ev["kern"], m)
+    E = LN.embed(params, X, ev["kern"])
+    args = dict(wmin=480, rmax=30)
+    learned, _ = vif.vif_propose_neighbors(*X, ev["kern"], m, E, 120, 50.0, 1, 1024, **args)
+    spatial, _ = vif.vif_propose_neighbors(*X, ev["kern"], m, None, 120, 50.0, 1, 1024, **args)
+    r_l, r_s = LN.recall(learned, exact), LN.recall(spatial, exact)
+    log(f"held-out recall: learned {r_l:.5f}, spatial candidates {r_s:.5f}")
+    assert hist[-1][1] < hist[0][1]
+    assert r_l > r_s + 0.01
