@@ -121,7 +121,8 @@ def learned_eval(args, d, X, y, Z, nbr_exact, t_exact_ms):
         "recall": rec_l, "recall_spatial_candidates": rec_s,
         "fallback_rows": nfb_l, "fallback_rows_spatial": nfb_s,
         "nll_exact_fp64": nll_e, "dnll_learned": nll_l - nll_e, "dnll_spatial": nll_s - nll_e,
-        "ms_embed": t_embed, "ms_propose": t_prop, "ms_exact": t_exact_ms,
+        "ms_embed": t_embed, "ms_propose": t_prop, "ms_propose_spatial": t_sp,
+        "ms_exact": t_exact_ms,
         "pts_per_s": n / ((t_embed + t_prop) / 1000.0), "pts_per_s_exact": n / (t_exact_ms / 1000.0),
         "speedup_vs_exact": t_exact_ms / (t_embed + t_prop),
     }

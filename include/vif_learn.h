@@ -91,15 +91,16 @@ size_t vif_propose_ws(int64_t n);
  * minimum coordinates, cell index = trunc((x - min) / cell) clamped) is within
  * r cells of the query's in x and in y, r the smallest radius in 1..rmax whose
  * cells hold at least wmin points of those slabs (the query's whole slab
- * counted), else rmax. The ncand (<= 128) window points of
+ * counted), else rmax; (lags + 1)(2 rmax + 1) <= 256. The ncand (<= 128) window
+ * points of
  * smallest |e_i - e_j|^2 (FP32, summed in dimension order, no fused
  * multiply-add), or of smallest squared spatial distance (FP64) when E is
  * NULL, ties to the lower index, are reranked by the exact key of
  * vif_neighbors; nbr [n, m] receives the best m (key descending, index
  * ascending, -1 padding). Rows whose window holds fewer than min(i, m) points
  * or more than cmax (<= 1024) take the exact search instead; *n_fallback (HOST,
- * may be NULL) receives their count. E: FP32 [n, 16] or NULL. Synchronises the
- * stream. */
+ * may be NULL) receives their count. E: FP32 [n, 16] (16-byte aligned) or
+ * NULL. Synchronises the stream. */
 int32_t vif_propose_neighbors(const vif_points* points, const vif_kernel* kern, int32_t m,
                               const float* E, int32_t ncand, double cell, int32_t lags,
                               int32_t wmin, int32_t rmax, int32_t cmax, int32_t* nbr,

@@ -154,16 +154,19 @@ def grid_cells(sx, sy, h):
     return cx, cy
 
 
+def cell_count(t, cx, cy, i, L, r):
+    """Points of the slabs t_i - L .. t_i (whole slabs) within r cells of the query."""
+    lo = int(np.searchsorted(t, t[i] - L, side="left"))
+    hi = int(np.searchsorted(t, t[i], side="right"))
+    cheb = np.maximum(np.abs(cx[lo:hi] - cx[i]), np.abs(cy[lo:hi] - cy[i]))
+    return int((cheb <= r).sum())
+
+
 def radius(t, cx, cy, i, L, wmin, rmax):
     """Smallest r in 1..rmax whose cells hold at least wmin points of the slabs
     t_i - L .. t_i (counting whole slabs), else rmax."""
-    lo = int(np.searchsorted(t, t[i] - L, side="left"))
-    hi = int(np.searchsorted(t, t[i], side="right"))
-    dx = np.abs(cx[lo:hi] - cx[i])
-    dy = np.abs(cy[lo:hi] - cy[i])
-    cheb = np.maximum(dx, dy)
     for r in range(1, rmax + 1):
-        if int((cheb <= r).sum()) >= wmin:
+        if cell_count(t, cx, cy, i, L, r) >= wmin:
             return r
     return rmax
 

@@ -88,7 +88,7 @@ int kpad_of(int k) { return k > 0 ? ((k + 1 + 63) / 64) * 64 : 0; }
 
 struct Layout {
   size_t c2 = 0, f2 = 0, b2 = 0, k2 = 0, px2 = 0, py2 = 0, pi2 = 0, pflag = 0, plist = 0,
-         pcount = 0;  // proposal search
+         pcount = 0, pemb = 0;  // proposal search
   size_t flags = 0, out = 0, part = 0, sums = 0, logD = 0, z = 0, Sk = 0, P = 0, Pb = 0, U = 0, W = 0,
          syrk = 0, M = 0, q = 0, dscr = 0, tab1 = 0, tab2 = 0, bnd = 0, bbox = 0, counts = 0,
          fill = 0, bsum = 0, key = 0, px = 0, py = 0, pidx = 0, total = 0;
@@ -190,6 +190,7 @@ Layout make_propose_layout(int64_t n) {
   L.pflag = take(sizeof(int32_t) * (size_t)n);
   L.plist = take(sizeof(int32_t) * (size_t)n);
   L.pcount = take(256);
+  L.pemb = take(sizeof(float) * 16 * (size_t)n);
   L.total = off;
   return L;
 }
@@ -865,9 +866,11 @@ int32_t vif_propose_neighbors(const vif_points* p, const vif_kernel* kern, int32
   if (ncand < m || ncand > 128) return fail(VIF_E_ARG, "need m <= ncand <= 128");
   if (!(cell > 0) || !isfinite(cell)) return fail(VIF_E_ARG, "cell must be positive");
   if (lags < 0) return fail(VIF_E_ARG, "lags < 0");
-  if (wmin < 0 || rmax < 1 || rmax > 1024) return fail(VIF_E_ARG, "need wmin >= 0, 1 <= rmax <= 1024");
+  if (wmin < 0 || rmax < 1 || (int64_t)(lags + 1) * (2 * rmax + 1) > 256)
+    return fail(VIF_E_ARG, "need wmin >= 0, rmax >= 1 and (lags + 1)(2 rmax + 1) <= 256");
   if (cmax < 1 || cmax > vif::kProposeCmax)
     return fail(VIF_E_ARG, "cmax must be in 1..%d", vif::kProposeCmax);
+  if (reinterpret_cast<uintptr_t>(E) % 16 != 0) return fail(VIF_E_ARG, "E must be 16-byte aligned");
   if (n_fallback) *n_fallback = 0;
   if (m == 0) return ok();
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
@@ -912,9 +915,12 @@ int32_t vif_propose_neighbors(const vif_points* p, const vif_kernel* kern, int32
   pa.rmax = rmax;
   pa.cmax = cmax;
   pa.E = E;
+  pa.Ecsr = reinterpret_cast<const float*>(ws + L.pemb);
   pa.fallback = reinterpret_cast<int32_t*>(ws + L.pflag);
   int32_t* count = reinterpret_cast<int32_t*>(ws + L.pcount);
   PROF(VIF_STAGE_NEIGHBORS, false);
+  if (E)
+    HIPCHK(vif::launch_permute16(p->n, g2.pidx, E, reinterpret_cast<float*>(ws + L.pemb), s));
   HIPCHK(vif::launch_propose(S.a, g2, pa, s));
   HIPCHK(vif::launch_zero_i32(count, 1, s));
   HIPCHK(vif::launch_compact(p->n, pa.fallback, reinterpret_cast<int32_t*>(ws + L.plist), count,

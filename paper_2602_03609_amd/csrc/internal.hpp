@@ -47,11 +47,15 @@ struct ProposeArgs {
   int wmin, rmax;       // window radius: smallest r in 1..rmax with >= wmin points, else rmax
   int cmax;             // larger windows fall back to the exact search (<= kProposeCmax)
   const float* E;       // [n, 16] embeddings, or NULL: spatial distance
+  const float* Ecsr;    // the embeddings permuted into the grid's CSR order
   int32_t* fallback;    // [n] 1 where the row must come from the exact search
 };
 constexpr int kProposeCmax = 1024;
 hipError_t launch_propose(const NbrArgs& a, const GridArgs& g, const ProposeArgs& pa,
                           hipStream_t s);
+// out[pos] = E[pidx[pos]] for 16-float rows.
+hipError_t launch_permute16(int64_t n, const int32_t* pidx, const float* E, float* out,
+                            hipStream_t s);
 // p[0 .. cnt) = 0.
 hipError_t launch_zero_i32(int32_t* p, int64_t cnt, hipStream_t s);
 // Compacts i with flag[i] != 0 into list, count into *count (device, zeroed first).

@@ -579,7 +579,7 @@ __global__ __launch_bounds__(256) void propose_kernel(NbrArgs A, GridArgs G, Pro
         }
         if (ok) {
           if (P.E) {
-            const float d = emb_dist(ei, P.E + (int64_t)j * 16);
+            const float d = emb_dist(ei, P.Ecsr + (int64_t)pos * 16);
             key = (uint64_t)__float_as_uint(d);
           } else {
             key = (uint64_t)__double_as_longlong(spatial_dist(G.px[pos] - qx, G.py[pos] - qy));
@@ -673,6 +673,16 @@ __global__ __launch_bounds__(256) void propose_kernel(NbrArgs A, GridArgs G, Pro
   if (lane < m) A.nbr[i * m + lane] = lane < nc ? I[lane] : -1;
 }
 
+__global__ void permute16_kernel(int64_t n, const int32_t* __restrict__ pidx,
+                                 const float* __restrict__ E, float* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * 4) return;
+  const int64_t pos = e >> 2;
+  const int q = (int)(e & 3);
+  reinterpret_cast<float4*>(out)[pos * 4 + q] =
+      reinterpret_cast<const float4*>(E)[(int64_t)pidx[pos] * 4 + q];
+}
+
 __global__ void compact_kernel(int64_t n, const int32_t* __restrict__ flag,
                                int32_t* __restrict__ list, int32_t* __restrict__ count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -716,6 +726,14 @@ hipError_t launch_compact(int64_t n, const int32_t* flag, int32_t* list, int32_t
 hipError_t launch_zero_i32(int32_t* p, int64_t cnt, hipStream_t s) {
   if (cnt <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, p, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute16(int64_t n, const int32_t* pidx, const float* E, float* out,
+                            hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(permute16_kernel, dim3((unsigned)((n * 4 + 255) / 256)), dim3(256), 0, s, n,
+                     pidx, E, out);
   return hipGetLastError();
 }
 
