@@ -396,11 +396,11 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
   constexpr int MAXP0 = (CAPB / VPE + NTH - 1) / NTH;
   constexpr int MAXP = MAXP0 < 10 ? MAXP0 : 10;             // 16-byte pieces per thread
   // FP32/FP64 staging: nu rows of (width + VPE) elements.
-  auto pick_width = [&](int cap) {
+  auto pick_width = [&](int cap, int rows) {
     cap = min(cap, MAXP * NTH * VPE);
-    if (nu * (4 * KC + VPE) <= cap && A.ldu % (8 * KC) == 0) return 4 * KC;
-    if (nu * (2 * KC + VPE) <= cap && A.ldu % (4 * KC) == 0) return 2 * KC;
-    return KC;  // nu <= NSLOT always fits; ldu is a multiple of 64 >= 2 KC
+    if (rows * (4 * KC + VPE) <= cap && A.ldu % (8 * KC) == 0) return 4 * KC;
+    if (rows * (2 * KC + VPE) <= cap && A.ldu % (4 * KC) == 0) return 2 * KC;
+    return KC;  // rows <= NSLOT + 15 always fits; ldu is a multiple of 64 >= 2 KC
   };
   // Split staging: nu rows of NSP planes of (width + BPAD) bfloat16.
   auto pick_width_split = [&]() {
@@ -411,7 +411,7 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
     return KC;
   };
   bool split_stage = SPLIT;            // Gram pass; the W pass stages FP32
-  int cw = SPLIT ? pick_width_split() : pick_width(CAPB);
+  int cw = SPLIT ? pick_width_split() : pick_width(CAPB, nu);
   int sld = SPLIT ? cw + BPAD : cw + VPE;  // row stride (bf16 per plane, or UT)
   int lppr = __builtin_ctz(cw / VPE);  // log2 of the 16-byte pieces per row and chunk
   int npieces = nu << lppr;
@@ -610,13 +610,13 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
 
   // W-pass geometry (FP32 staging after the selection matrix S) and the loads of
   // its first chunk, in flight during the per-point phase.
-  const int nup = (nu + 3) & ~3;
+  const int nup = (nu + 15) & ~15;
   const int sst = nup + 1;
   UT* sel = reinterpret_cast<UT*>(sBig);
   if constexpr (!WANT_B) {
     split_stage = false;
     stage = sel + ((16 * sst + VPE - 1) / VPE) * VPE;
-    cw = pick_width(CAPB - (int)(stage - sel));
+    cw = pick_width(CAPB - (int)(stage - sel), nup);
     sld = cw + VPE;
     lppr = __builtin_ctz(cw / VPE);
     npieces = nu << lppr;
@@ -697,23 +697,37 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
     // S (16 x nu, zero beyond the group's points and the rows they use) holds each
     // point's b_r at its rows' union slots; its row stride is odd against LDS banks.
     for (int e = tid; e < 16 * sst; e += NTH) sel[e] = UT(0);
+    for (int e = tid; e < (nup - nu) * sld; e += NTH) stage[nu * sld + e] = UT(0);
     __syncthreads();
     if (active && r < q) sel[pl * sst + sSlot[pl][r]] = (UT)sBv[pl][r];
     UT* W = reinterpret_cast<UT*>(A.W);
     auto w_chunk = [&](int kc) __attribute__((always_inline)) {
       const int ncb = cw >> 4;
       for (int cb = wave; cb < ncb; cb += NW) {
-        AccT aw = AccT{0, 0, 0, 0};
+        // union rows padded to a multiple of 16 with zeros (S and the staged rows),
+        // four K steps per iteration on two independent accumulators
+        AccT aw0 = AccT{0, 0, 0, 0}, aw1 = AccT{0, 0, 0, 0};
         const int col = cb * 16 + rr16;
-        for (int u0 = 0; u0 < nup; u0 += 4) {
-          const int u = u0 + kq;
-          const UT av = sel[rr16 * sst + u];
-          const UT bv = u < nu ? stage[u * sld + col] : UT(0);
-          if constexpr (PREC == 0)
-            aw = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, aw, 0, 0, 0);
-          else
-            aw = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, aw, 0, 0, 0);
+        for (int u0 = 0; u0 < nup; u0 += 16) {
+          UT av[4], bv[4];
+#pragma unroll
+          for (int q4 = 0; q4 < 4; ++q4) {
+            const int u = u0 + 4 * q4 + kq;
+            av[q4] = sel[rr16 * sst + u];
+            bv[q4] = stage[u * sld + col];
+          }
+#pragma unroll
+          for (int q4 = 0; q4 < 4; q4 += 2) {
+            if constexpr (PREC == 0) {
+              aw0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q4], bv[q4], aw0, 0, 0, 0);
+              aw1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q4 + 1], bv[q4 + 1], aw1, 0, 0, 0);
+            } else {
+              aw0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q4], bv[q4], aw0, 0, 0, 0);
+              aw1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q4 + 1], bv[q4 + 1], aw1, 0, 0, 0);
+            }
+          }
         }
+        const AccT aw = aw0 + aw1;
         if constexpr (SPLIT) {
           // Lane holds rows 4kq..4kq+3 of column col: one 8-byte piece per term plane.
           if (4 * kq < GP) {
