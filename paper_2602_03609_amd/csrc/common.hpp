@@ -59,6 +59,25 @@ __device__ __forceinline__ T cov_eval(const KernDev& K, T dx, T dy, T dt) {
   return T(K.sigma2) * matern_poly<T>(K.nu_code, x) * dexp(-T(K.dpg) * lp - x);
 }
 
+// The stretched-exponential Gneiting kernel (kind 1) factored for many pairs at
+// one time lag: gneiting_lag gives A = -tau log psi and e = exp(-beta gamma log psi)
+// for |dt|, gneiting_pair the covariance from them, with the operations of
+// cov_eval in the same order (so the values are identical).
+template <typename T>
+__device__ __forceinline__ void gneiting_lag(const KernDev& K, T dt, T& A, T& e) {
+  T adt = dt < T(0) ? -dt : dt;
+  T ta = adt > T(0) ? dexp(T(K.two_alpha) * dlog(adt)) : T(0);
+  T lp = dlog(T(K.a) * ta + T(1));
+  A = -T(K.tau) * lp;
+  e = dexp(-T(K.bg) * lp);
+}
+template <typename T>
+__device__ __forceinline__ T gneiting_pair(const KernDev& K, T dx, T dy, T A, T e) {
+  T h2 = dx * dx + dy * dy;
+  T g = K.gamma_half ? dsqrt(h2) : (h2 > T(0) ? dexp(T(K.gamma) * dlog(h2)) : T(0));
+  return T(K.sigma2) * dexp(A - T(K.c) * g * e);
+}
+
 // Wave-local memory ordering for communication through LDS between lanes of
 // one wavefront (LDS instructions of a wave execute in order).
 __device__ __forceinline__ void wave_lds_sync() {

@@ -461,6 +461,11 @@ __global__ __launch_bounds__(512) void lowrank_u_kernel(LowRankArgs A, const __b
         zy[c] = ok ? A.zy[l] : 0.0;
         zt[c] = ok ? A.zt[l] : 0.0;
       }
+      // Gneiting: the lag factors depend on (t_i, z_l) only, and consecutive
+      // points mostly share their time, so they are reused across rows.
+      const bool fac = A.K.kind == 1;
+      float fa[8], fe[8];
+      double tcache = NAN;
 #pragma unroll 1
       for (int rr = 0; rr < 8; ++rr) {
         const int row = rg * 8 + rr;
@@ -468,12 +473,22 @@ __global__ __launch_bounds__(512) void lowrank_u_kernel(LowRankArgs A, const __b
         bf8v h8, l8;
         if (i < A.n) {
           const double xi = A.sx[i], yi = A.sy[i], ti = A.t[i];
+          if (fac && !(ti == tcache)) {
+            tcache = ti;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) gneiting_lag<float>(A.K, (float)(ti - zt[c]), fa[c], fe[c]);
+          }
 #pragma unroll
           for (int c = 0; c < 8; ++c) {
             const int l = cg * 8 + c;
             float v = 0.f;
-            if (l < A.k)
-              v = cov_eval<float>(A.K, (float)(xi - zx[c]), (float)(yi - zy[c]), (float)(ti - zt[c]));
+            if (l < A.k) {
+              if (fac)
+                v = gneiting_pair<float>(A.K, (float)(xi - zx[c]), (float)(yi - zy[c]), fa[c], fe[c]);
+              else
+                v = cov_eval<float>(A.K, (float)(xi - zx[c]), (float)(yi - zy[c]),
+                                    (float)(ti - zt[c]));
+            }
             const __bf16 h = (__bf16)v;
             h8[c] = h;
             l8[c] = (__bf16)(v - (float)h);
