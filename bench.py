@@ -54,6 +54,12 @@ def parse():
                     help="also train the neighbor-proposal network on the GPU and evaluate it "
                          "on the workload (recall, NLL change, search rate)")
     ap.add_argument("--learn-steps", type=int, default=12000)
+    ap.add_argument("--batch", action="store_true",
+                    help="also time the batched workload: 64 independent problems evaluated "
+                         "through one autotuned, graph-captured batch")
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--batch-prec", default="fp32", choices=list(PREC_ES))
+    ap.add_argument("--batch-reps", type=int, default=10)
     return ap.parse_args()
 
 
@@ -130,6 +136,74 @@ def learned_eval(args, d, X, y, Z, nbr_exact, t_exact_ms):
         f"(spatial {nll_s - nll_e:.4g}); embed {t_embed:.2f} ms + propose {t_prop:.2f} ms vs exact "
         f"{t_exact_ms:.2f} ms; fallback rows {nfb_l}")
     return res
+
+
+def batch_eval(args):
+    """The batched workload: problems/s and points/s of one graph-captured batch
+    under the autotuned schedule, against the same problems one vif_nll call at a
+    time; FP64 single-problem NLLs of a few problems as the accuracy check."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2602_03609_amd as vif
+    t0 = time.perf_counter()
+    ds = synth.config_batch(seed=0, count=args.batch_count)
+    log(f"batch: generated {len(ds)} problems ({sum(d['n'] for d in ds)} points) in "
+        f"{time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    td = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    probs = []
+    for d in ds:
+        X = (td(d["sx"]), td(d["sy"]), td(d["t"]))
+        nb = vif.vif_neighbors(*X, d["kern"], d["m"])
+        probs.append({"sx": X[0], "sy": X[1], "t": X[2], "y": td(d["y"]), "kern": d["kern"],
+                      "nbr": nb, "ind": (td(d["zx"]), td(d["zy"]), td(d["zt"])), "m": d["m"]})
+    torch.cuda.synchronize()
+    points = sum(d["n"] for d in ds)
+    prec = args.batch_prec
+    b = vif.Batch(probs, prec=prec)
+    tune_ms = b.autotune(reps=2)
+    streams, rows = b.schedule()
+    log(f"batch: autotuned schedule streams={streams} rows={rows} ({tune_ms:.2f} ms)")
+    b.graph_launch()
+    torch.cuda.synchronize()
+    st = b.status()
+    if any(st):
+        raise RuntimeError(f"batch: failing problems {[i for i, s in enumerate(st) if s]}")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.batch_reps):
+        b.graph_launch()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.batch_reps
+    got = b.nll.cpu().numpy()
+    # the same problems one call at a time (each call synchronises)
+    t0 = time.perf_counter()
+    for p in probs:
+        vif.vif_nll(p["sx"], p["sy"], p["t"], p["y"], p["kern"], p["m"], p["nbr"], ind=p["ind"],
+                    prec=prec)
+    torch.cuda.synchronize()
+    ms_seq = (time.perf_counter() - t0) * 1000.0
+    errs = []
+    for i in range(0, len(probs), max(1, len(probs) // 8)):
+        p = probs[i]
+        ref = vif.vif_nll(p["sx"], p["sy"], p["t"], p["y"], p["kern"], p["m"], p["nbr"],
+                          ind=p["ind"], prec="fp64")
+        errs.append(abs(got[i] - ref) / abs(ref))
+    log(f"batch: {ms:.2f} ms per batch ({len(probs) / ms * 1000:.1f} problems/s, "
+        f"{points / ms / 1000:.3g} Mpts/s); one call at a time {ms_seq:.2f} ms; "
+        f"max rel err vs fp64 {max(errs):.2e}")
+    b.close()
+    return {"workload": f"{len(ds)} station-network problems, n log-uniform in 10k..200k "
+                        f"(total {points}), m in {{10,20,30}}, k in {{200,500}}, perturbed "
+                        f"Gneiting kernels; one graph-captured batch", "precision": prec,
+            "problems": len(ds), "points": points, "ms_per_batch": ms,
+            "problems_per_s": len(ds) / ms * 1000.0, "points_per_s": points / ms * 1000.0,
+            "schedule": {"streams": streams, "chunk_rows": rows},
+            "ms_one_call_at_a_time": ms_seq, "speedup_vs_one_at_a_time": ms_seq / ms,
+            "max_rel_err_vs_fp64_sampled": max(errs), "fp64_sampled_problems": len(errs)}
 
 
 def stage_work(n, m, k, kpad, es, prec):
@@ -415,6 +489,8 @@ def main():
             torch.cuda.synchronize()
             ts.append((time.perf_counter() - a) * 1000.0)
         out["learned_proposal"] = learned_eval(args, d, X, y, Z, nbr, float(np.median(ts)))
+    if args.batch:
+        out["batched"] = batch_eval(args)
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(d, m)

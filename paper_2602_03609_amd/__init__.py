@@ -5,6 +5,10 @@ The compute path is the HIP library libvif.so (C ABI in include/vif.h); this
 package holds its build script and a thin ctypes binding with the same names.
 """
 from ._lib import (  # noqa: F401
+    Batch,
+    VIF_E_ARG,
+    VIF_E_NOT_PD,
+    VIF_OK,
     VifError,
     VIF_KERNEL_GNEITING,
     VIF_KERNEL_GNEITING_MATERN,

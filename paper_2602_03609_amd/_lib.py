@@ -25,7 +25,11 @@ EXPORTS = ("vif_workspace_bytes", "vif_neighbors", "vif_factor", "vif_nll", "vif
            "vif_last_error", "vif_profile", "vif_profile_read",
            "vif_mlp_features", "vif_mlp_forward", "vif_mlp_backward_ws", "vif_mlp_backward",
            "vif_mlp_pair_loss", "vif_mlp_adam", "vif_mlp_batch", "vif_propose_ws",
-           "vif_propose_neighbors")
+           "vif_propose_neighbors", "vif_batch_create", "vif_batch_workspace_bytes",
+           "vif_batch_enqueue", "vif_batch_graph_launch", "vif_batch_autotune",
+           "vif_batch_schedule", "vif_batch_set_schedule", "vif_batch_status",
+           "vif_batch_destroy")
+BATCH_PLAN_SCRATCH = 16384
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 8, 64, 16, 9936
 STAGES = ("neighbors", "sigma_k", "crosscov", "trmm", "point_factor", "syrk", "assembly")
 
@@ -46,6 +50,11 @@ class Kernel(ctypes.Structure):
 class Points(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("sx", ctypes.c_void_p), ("sy", ctypes.c_void_p),
                 ("t", ctypes.c_void_p)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("points", Points), ("y", ctypes.c_void_p), ("kern", Kernel),
+                ("m", ctypes.c_int32), ("nbr", ctypes.c_void_p), ("ind", Points)]
 
 
 _lib = None
@@ -100,6 +109,25 @@ def load(path=LIB_PATH):
         lib.vif_propose_neighbors.argtypes = [pP, pK, i32, vp, i32, ctypes.c_double, i32, i32,
                                               i32, i32, vp, ctypes.POINTER(i64), vp, sz, vp]
         lib.vif_propose_neighbors.restype = i32
+        pi32 = ctypes.POINTER(i32)
+        lib.vif_batch_create.argtypes = [ctypes.POINTER(Problem), i32, i32, vp, sz, vp]
+        lib.vif_batch_create.restype = vp
+        lib.vif_batch_workspace_bytes.argtypes = [vp]
+        lib.vif_batch_workspace_bytes.restype = sz
+        lib.vif_batch_enqueue.argtypes = [vp, vp, sz, vp, vp]
+        lib.vif_batch_enqueue.restype = i32
+        lib.vif_batch_graph_launch.argtypes = [vp, vp, sz, vp, vp]
+        lib.vif_batch_graph_launch.restype = i32
+        lib.vif_batch_autotune.argtypes = [vp, vp, sz, vp, i32, pd, vp]
+        lib.vif_batch_autotune.restype = i32
+        lib.vif_batch_schedule.argtypes = [vp, pi32, pi32]
+        lib.vif_batch_schedule.restype = i32
+        lib.vif_batch_set_schedule.argtypes = [vp, i32, i32]
+        lib.vif_batch_set_schedule.restype = i32
+        lib.vif_batch_status.argtypes = [vp, vp, pi32, vp]
+        lib.vif_batch_status.restype = i32
+        lib.vif_batch_destroy.argtypes = [vp]
+        lib.vif_batch_destroy.restype = None
         _lib = lib
         return lib
 
@@ -390,3 +418,85 @@ def vif_propose_neighbors(sx, sy, t, kern, m, E, ncand, cell, lags, cmax=1024, n
                                      ctypes.byref(nfb), ws.data_ptr(), ws.numel(),
                                      _stream(stream)))
     return nbr, int(nfb.value)
+
+
+# --------------------------------------------------------------------- batches ----
+class Batch:
+    """Many NLL evaluations planned once and enqueued together (include/vif_batch.h).
+
+    problems: sequence of dicts with device tensors sx, sy, t, y, nbr (int32
+    [n, m]), optional ind = (zx, zy, zt), and a kernel dict `kern`. The tensors
+    are kept referenced for the batch's lifetime. Results land in `self.nll`
+    (float64 CUDA tensor [count]).
+    """
+
+    def __init__(self, problems, prec="fp32", stream=None):
+        torch = _torch()
+        lib = load()
+        self._keep = []
+        arr = (Problem * len(problems))()
+        for i, d in enumerate(problems):
+            pr = arr[i]
+            pr.points = make_points(d["sx"], d["sy"], d["t"])
+            pr.y = _dev_ptr(d["y"], torch.float64, "y")
+            pr.kern = make_kernel(d["kern"])
+            m = int(d["nbr"].shape[1]) if d.get("nbr") is not None else 0
+            pr.m = m
+            pr.nbr = _dev_ptr(d["nbr"], torch.int32, "nbr") if m > 0 else None
+            ind = d.get("ind")
+            if ind is not None:
+                pr.ind = make_points(*ind, name="ind")
+            self._keep.append(d)
+        dev = problems[0]["sx"].device
+        scratch = torch.empty(BATCH_PLAN_SCRATCH, dtype=torch.uint8, device=dev)
+        h = lib.vif_batch_create(arr, len(problems), _prec(prec), scratch.data_ptr(),
+                                 scratch.numel(), _stream(stream))
+        if not h:
+            raise VifError(VIF_E_ARG, lib.vif_last_error().decode(errors="replace"))
+        self._h = ctypes.c_void_p(h)
+        self.count = len(problems)
+        self.ws = torch.empty(int(lib.vif_batch_workspace_bytes(self._h)), dtype=torch.uint8,
+                              device=dev)
+        self.nll = torch.zeros(self.count, dtype=torch.float64, device=dev)
+
+    def _args(self):
+        return self._h, self.ws.data_ptr(), self.ws.numel(), self.nll.data_ptr()
+
+    def enqueue(self, stream=None):
+        _check(load().vif_batch_enqueue(*self._args(), _stream(stream)))
+        return self.nll
+
+    def graph_launch(self, stream=None):
+        _check(load().vif_batch_graph_launch(*self._args(), _stream(stream)))
+        return self.nll
+
+    def autotune(self, reps=3, stream=None):
+        best = ctypes.c_double(0.0)
+        _check(load().vif_batch_autotune(*self._args(), int(reps), ctypes.byref(best),
+                                         _stream(stream)))
+        return best.value
+
+    def schedule(self):
+        a, b = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(load().vif_batch_schedule(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def set_schedule(self, streams, chunk_rows):
+        _check(load().vif_batch_set_schedule(self._h, int(streams), int(chunk_rows)))
+
+    def status(self, stream=None):
+        """Per-problem status list (VIF_OK or VIF_E_*) of the last evaluation."""
+        st = (ctypes.c_int32 * self.count)()
+        load().vif_batch_status(self._h, self.ws.data_ptr(), st, _stream(stream))
+        return list(st)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().vif_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -8,11 +8,13 @@
 #include <string.h>
 
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "internal.hpp"
 #include "vif.h"
 #include "vif_learn.h"
+#include "vif_batch.h"
 
 namespace {
 
@@ -102,7 +104,7 @@ constexpr size_t kFlagBytes = 256;
 // Average number of points of one time slab per grid cell of the neighbor index.
 constexpr double kCellTarget = 32.0;
 
-Layout make_layout(int64_t n, int m, int k, int prec, int op) {
+Layout make_layout(int64_t n, int m, int k, int prec, int op, int chunk_rows = 4096) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -147,7 +149,7 @@ Layout make_layout(int64_t n, int m, int k, int prec, int op) {
     const size_t kk = (size_t)L.kpad * L.kpad;
     L.Sk = take(sizeof(double) * kk);
     L.P = take(sizeof(double) * kk);
-    if (prec >= VIF_PREC_BF16X3) L.Pb = take(4 * kk);
+    if (prec >= VIF_PREC_BF16X3) L.Pb = take((prec == VIF_PREC_BF16X6 ? 6 : 4) * kk);
     L.dscr = take(sizeof(double) * 64 * 64);
     L.U = take(es * (size_t)n * L.kpad);
     if (op == VIF_OP_NLL) {
@@ -156,8 +158,8 @@ Layout make_layout(int64_t n, int m, int k, int prec, int op) {
         const int64_t wr = vif::w_plane_rows(n);
         const size_t nsp = prec == VIF_PREC_BF16X6 ? 3 : 2;
         L.W = take(2 * nsp * (size_t)wr * L.kpad);
-        L.splits = vif::syrk_chunks(wr, L.kpad, prec);
-        L.syrk = take(vif::syrk_part_bytes(wr, L.kpad, prec));
+        L.splits = vif::syrk_chunks(wr, L.kpad, prec, chunk_rows);
+        L.syrk = take(vif::syrk_part_bytes(wr, L.kpad, prec, chunk_rows));
       } else {
         L.W = take(es * (size_t)n * L.kpad);
         L.splits = vif::syrk_chunks(n, L.kpad, prec);
@@ -383,10 +385,10 @@ int32_t run_lowrank(const vif_points* p, const vif_points* ind, const vif_kernel
   HIPCHK(vif::launch_cholesky(L.kpad, Sk, reinterpret_cast<double*>(ws + L.dscr), fl + 1, s));
   HIPCHK(vif::launch_trinv(L.kpad, Sk, P, s));
   PROF(VIF_STAGE_SIGMA_K, true);
-  if (prec >= VIF_PREC_BF16X3 && vif::lowrank_fused_ok(L.kpad)) {
+  if (prec >= VIF_PREC_BF16X3 && vif::lowrank_fused_ok(L.kpad, prec)) {
     // Cross-covariance evaluated on chip inside the product.
     PROF(VIF_STAGE_TRMM, false);
-    HIPCHK(vif::launch_lowrank_fused(a, P, ws + L.Pb, reinterpret_cast<float*>(ws + L.U), s));
+    HIPCHK(vif::launch_lowrank_fused(a, P, ws + L.Pb, reinterpret_cast<float*>(ws + L.U), prec, s));
     PROF(VIF_STAGE_TRMM, true);
     return VIF_OK;
   }
@@ -943,4 +945,406 @@ int32_t vif_propose_neighbors(const vif_points* p, const vif_kernel* kern, int32
   return ok();
 }
 
+
+// ------------------------------------------------------------------- batches ----
+}  // extern "C"
+
+namespace {
+
+struct ProbPlan {
+  vif_points p{};
+  const double* y = nullptr;
+  vif_kernel kern{};
+  int m = 0;
+  const int32_t* nbr = nullptr;
+  vif_points ind{};
+  int k = 0;
+  Layout L;
+  size_t off = 0;
+  vif::GridArgs og{};  // processing-order grid (k > 0)
+  double t0 = 0.0;
+};
+
+constexpr int kBatchMaxStreams = 4;
+constexpr int kBatchPlanScratch = VIF_BATCH_PLAN_SCRATCH;
+
+}  // namespace
+
+struct vif_batch {
+  int prec = 0;
+  std::vector<ProbPlan> probs;
+  size_t total = 0;
+  int streams = 1;
+  int chunk_rows = 4096;
+  hipStream_t side[kBatchMaxStreams] = {};
+  hipStream_t cap = nullptr;  // capture stream (the caller's may be the null stream)
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kBatchMaxStreams] = {};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* g_ws = nullptr;
+  double* g_nll = nullptr;
+  int g_streams = 0, g_chunk = 0;
+};
+
+namespace {
+
+void drop_graph(vif_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+// One problem's NLL, kernels only (capturable): the path of vif_nll with the
+// host-side quantities taken from the plan.
+int32_t enqueue_problem(const ProbPlan& P, int prec, int chunk_rows, char* wsb, double* nll_out,
+                        hipStream_t s) {
+  const Layout& L = P.L;
+  char* ws = wsb + P.off;
+  auto* fl = reinterpret_cast<unsigned long long*>(ws + L.flags);
+  double* sums = reinterpret_cast<double*>(ws + L.sums);
+  double* part = reinterpret_cast<double*>(ws + L.part);
+  double* out = reinterpret_cast<double*>(ws + L.out);
+  HIPCHK(vif::launch_init_flags(ws + L.flags, s));
+  vif::FactorArgs fa{};
+  fa.n = P.p.n;
+  fa.m = P.m;
+  fa.k = P.k;
+  fa.ldu = L.kpad;
+  fa.K = to_dev(&P.kern);
+  fa.sx = P.p.sx; fa.sy = P.p.sy; fa.t = P.p.t; fa.y = P.y;
+  fa.nbr = P.nbr;
+  fa.logD = reinterpret_cast<double*>(ws + L.logD);
+  fa.z = reinterpret_cast<double*>(ws + L.z);
+  fa.fail = fl;
+  fa.bad_nbr = fl + 3;
+  if (P.k > 0) {
+    vif::GridArgs g = P.og;
+    HIPCHK(vif::launch_grid_build(P.p.n, P.p.sx, P.p.sy, P.p.t, P.t0, g,
+                                  reinterpret_cast<int32_t*>(ws + L.counts),
+                                  reinterpret_cast<int32_t*>(ws + L.fill),
+                                  reinterpret_cast<int32_t*>(ws + L.bsum),
+                                  reinterpret_cast<int32_t*>(ws + L.key), nullptr, nullptr,
+                                  reinterpret_cast<int32_t*>(ws + L.pidx), s));
+    fa.ord = reinterpret_cast<const int32_t*>(ws + L.pidx);
+    int32_t st = run_lowrank(&P.p, &P.ind, &P.kern, prec, ws, L, s);
+    if (st) return st;
+    fa.U = ws + L.U;
+    fa.W = ws + L.W;
+    fa.wrb = vif::w_plane_rows(P.p.n) / 8;
+    HIPCHK(vif::launch_point_factor(fa, 0, prec, s));
+    double* M = reinterpret_cast<double*>(ws + L.M);
+    double* q = reinterpret_cast<double*>(ws + L.q);
+    const int64_t wrows = prec >= VIF_PREC_BF16X3 ? vif::w_plane_rows(P.p.n) : P.p.n;
+    const int nchunk = vif::syrk_chunks(wrows, L.kpad, prec, chunk_rows);
+    HIPCHK(vif::launch_syrk(wrows, L.kpad, ws + L.W, prec, ws + L.syrk, nchunk, s, chunk_rows));
+    HIPCHK(vif::launch_syrk_reduce(P.k, L.kpad, ws + L.syrk, prec, nchunk, M, q, sums + 2, s));
+    HIPCHK(vif::launch_cholesky(L.kpad, M, reinterpret_cast<double*>(ws + L.dscr), fl + 2, s));
+    HIPCHK(vif::launch_sum(P.p.n, fa.logD, 0, part, sums + 0, s));
+    HIPCHK(vif::launch_sum(P.p.n, fa.z, 1, part, sums + 1, s));
+    HIPCHK(vif::launch_finalize(P.p.n, P.k, L.kpad, M, q, sums + 0, sums + 1, out, s));
+  } else {
+    HIPCHK(vif::launch_point_factor(fa, 0, prec, s));
+    HIPCHK(vif::launch_sum(P.p.n, fa.logD, 0, part, sums + 0, s));
+    HIPCHK(vif::launch_sum(P.p.n, fa.z, 1, part, sums + 1, s));
+    HIPCHK(vif::launch_finalize(P.p.n, 0, 0, nullptr, nullptr, sums + 0, sums + 1, out, s));
+  }
+  HIPCHK(vif::launch_copy_f64(out, nll_out, s));
+  return VIF_OK;
+}
+
+int32_t batch_enqueue(vif_batch* b, char* ws, double* nll, hipStream_t s) {
+  const int ns = b->streams;
+  const int np = (int)b->probs.size();
+  if (ns > 1) {
+    HIPCHK(hipEventRecord(b->ev_fork, s));
+    for (int j = 0; j < ns; ++j) HIPCHK(hipStreamWaitEvent(b->side[j], b->ev_fork, 0));
+  }
+  // largest problems first, round-robin over the streams
+  for (int r = 0; r < np; ++r) {
+    const int i = r;
+    hipStream_t ss = ns > 1 ? b->side[r % ns] : s;
+    int32_t st = enqueue_problem(b->probs[i], b->prec, b->chunk_rows, ws, nll + i, ss);
+    if (st) return st;
+  }
+  if (ns > 1) {
+    for (int j = 0; j < ns; ++j) {
+      HIPCHK(hipEventRecord(b->ev_join[j], b->side[j]));
+      HIPCHK(hipStreamWaitEvent(s, b->ev_join[j], 0));
+    }
+  }
+  return VIF_OK;
+}
+
+int32_t batch_check(const vif_batch* b, void* ws, size_t ws_bytes, const double* nll) {
+  if (!b) return fail(VIF_E_ARG, "batch is NULL");
+  if (!ws) return fail(VIF_E_ARG, "workspace is NULL");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
+    return fail(VIF_E_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < b->total)
+    return fail(VIF_E_WORKSPACE, "workspace too small: %zu < %zu", ws_bytes, b->total);
+  if (!nll) return fail(VIF_E_ARG, "nll is NULL");
+  return VIF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vif_batch* vif_batch_create(const vif_problem* probs, int32_t count, int32_t prec, void* scratch,
+                            size_t scratch_bytes, void* hip_stream) {
+  if (!probs || count < 1) {
+    fail(VIF_E_ARG, "need at least one problem");
+    return nullptr;
+  }
+  if (prec < VIF_PREC_FP64 || prec > VIF_PREC_BF16X6) {
+    fail(VIF_E_ARG, "unknown precision %d", prec);
+    return nullptr;
+  }
+  if (!scratch || scratch_bytes < (size_t)kBatchPlanScratch ||
+      (reinterpret_cast<uintptr_t>(scratch) & 255) != 0) {
+    fail(VIF_E_WORKSPACE, "plan scratch must hold %d bytes, 256-byte aligned", kBatchPlanScratch);
+    return nullptr;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  std::unique_ptr<vif_batch> b(new vif_batch());
+  b->prec = prec;
+  size_t off = 0;
+  char* scr = reinterpret_cast<char*>(scratch);
+  for (int i = 0; i < count; ++i) {
+    const vif_problem& q = probs[i];
+    ProbPlan P;
+    P.p = q.points;
+    P.y = q.y;
+    P.kern = q.kern;
+    P.m = q.m;
+    P.nbr = q.nbr;
+    P.ind = q.ind;
+    int k = 0;
+    if (q.ind.n != 0 && check_ind(&q.ind, &k)) return nullptr;
+    P.k = k;
+    P.L = make_layout(q.points.n, q.m, k, prec, VIF_OP_NLL, 1024);
+    if (check_common(&q.points, &q.kern, q.m, scr, (size_t)-1, 0)) return nullptr;  // ws unused
+    if (!q.y || (q.m > 0 && !q.nbr)) {
+      fail(VIF_E_ARG, "problem %d: y or nbr is NULL", i);
+      return nullptr;
+    }
+    if (k > 0) {
+      // the processing-order grid, as in vif_nll, from the problem's bounding box
+      double* bbox = reinterpret_cast<double*>(scr + 256);
+      uint32_t* tflag = reinterpret_cast<uint32_t*>(scr);
+      if (vif::launch_zero_i32(reinterpret_cast<int32_t*>(scr), 64, s) != hipSuccess ||
+          vif::launch_validate_times(q.points.n, q.points.t, tflag, s) != hipSuccess ||
+          vif::launch_bbox(q.points.n, q.points.sx, q.points.sy, bbox, bbox + 4 * 256, s) !=
+              hipSuccess) {
+        fail(VIF_E_DEVICE, "problem %d: launch failed", i);
+        return nullptr;
+      }
+      uint32_t tf = 0;
+      double tt[2], bb[4];
+      if (hipMemcpyAsync(&tf, tflag, sizeof(tf), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipMemcpyAsync(&tt[0], q.points.t, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipMemcpyAsync(&tt[1], q.points.t + (q.points.n - 1), sizeof(double),
+                         hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipMemcpyAsync(bb, bbox + 4 * 256, sizeof(bb), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) {
+        fail(VIF_E_DEVICE, "problem %d: readback failed", i);
+        return nullptr;
+      }
+      if (tf & 1u) {
+        fail(VIF_E_ARG, "problem %d: times must be finite", i);
+        return nullptr;
+      }
+      if (!isfinite(bb[0]) || !isfinite(bb[1]) || !isfinite(bb[2]) || !isfinite(bb[3])) {
+        fail(VIF_E_ARG, "problem %d: coordinates must be finite", i);
+        return nullptr;
+      }
+      int nslab = 1;
+      const double span = tt[1] - tt[0];
+      if (!(tf & 6u) && span >= 0 && span < (double)VIF_MAX_LAGS) nslab = (int)span + 1;
+      const double per = (double)q.points.n / nslab;
+      int bits = 0;
+      while (bits < 10 && (double)(1 << (2 * (bits + 1))) * 3.0 <= per &&
+             (int64_t)(1 << (2 * (bits + 1))) * nslab <= vif::kMaxCells)
+        ++bits;
+      const double w = bb[1] - bb[0], h = bb[3] - bb[2];
+      vif::GridArgs& g = P.og;
+      g.gx = g.gy = 1 << bits;
+      g.ncell = g.gx * g.gy;
+      g.nslab = nslab;
+      g.morton = 1;
+      g.xmin = bb[0];
+      g.ymin = bb[2];
+      g.cw = w > 0 ? w / g.gx : 1.0;
+      g.ch = h > 0 ? h / g.gy : 1.0;
+      g.icw = w > 0 ? g.gx / w : 0.0;
+      g.ich = h > 0 ? g.gy / h : 0.0;
+      P.t0 = tt[0];
+    }
+    P.off = off;
+    off += align256(P.L.total);
+    b->probs.push_back(P);
+  }
+  b->total = off;
+  if (vif::prepare_lowrank_fused() != hipSuccess) {
+    fail(VIF_E_DEVICE, "kernel attribute could not be set");
+    return nullptr;
+  }
+  for (int j = 0; j < kBatchMaxStreams; ++j) {
+    if (hipStreamCreateWithFlags(&b->side[j], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_join[j], hipEventDisableTiming) != hipSuccess) {
+      fail(VIF_E_DEVICE, "stream or event creation failed");
+      vif_batch_destroy(b.release());
+      return nullptr;
+    }
+  }
+  if (hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+    fail(VIF_E_DEVICE, "stream or event creation failed");
+    vif_batch_destroy(b.release());
+    return nullptr;
+  }
+  ok();
+  return b.release();
+}
+
+size_t vif_batch_workspace_bytes(const vif_batch* b) { return b ? b->total : 0; }
+
+int32_t vif_batch_enqueue(vif_batch* b, void* ws, size_t ws_bytes, double* nll, void* hip_stream) {
+  int32_t st = batch_check(b, ws, ws_bytes, nll);
+  if (st) return st;
+  if ((st = batch_enqueue(b, reinterpret_cast<char*>(ws), nll,
+                          reinterpret_cast<hipStream_t>(hip_stream))))
+    return st;
+  return ok();
+}
+
+int32_t vif_batch_graph_launch(vif_batch* b, void* ws, size_t ws_bytes, double* nll,
+                               void* hip_stream) {
+  int32_t st = batch_check(b, ws, ws_bytes, nll);
+  if (st) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  if (!b->exec || b->g_ws != ws || b->g_nll != nll || b->g_streams != b->streams ||
+      b->g_chunk != b->chunk_rows) {
+    drop_graph(b);
+    HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    st = batch_enqueue(b, reinterpret_cast<char*>(ws), nll, b->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (st) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(VIF_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    b->graph = g;
+    HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->g_ws = ws;
+    b->g_nll = nll;
+    b->g_streams = b->streams;
+    b->g_chunk = b->chunk_rows;
+  }
+  HIPCHK(hipGraphLaunch(b->exec, s));
+  return ok();
+}
+
+int32_t vif_batch_autotune(vif_batch* b, void* ws, size_t ws_bytes, double* nll, int32_t reps,
+                           double* best_ms, void* hip_stream) {
+  int32_t st = batch_check(b, ws, ws_bytes, nll);
+  if (st) return st;
+  if (reps < 1) return fail(VIF_E_ARG, "reps < 1");
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  const int cand_streams[3] = {1, 2, 4};
+  const int cand_chunk[2] = {1024, 4096};
+  const int nchunk_cand = b->prec >= VIF_PREC_BF16X3 ? 2 : 1;  // rows per partial: split modes
+  struct Events {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Events() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } ev;
+  HIPCHK(hipEventCreate(&ev.e0));
+  HIPCHK(hipEventCreate(&ev.e1));
+  hipEvent_t e0 = ev.e0, e1 = ev.e1;
+  double best = INFINITY;
+  int bs = b->streams, bc = b->chunk_rows;
+  for (int a = 0; a < 3; ++a) {
+    for (int c = 0; c < nchunk_cand; ++c) {
+      b->streams = cand_streams[a];
+      b->chunk_rows = nchunk_cand == 2 ? cand_chunk[c] : 4096;
+      if ((st = vif_batch_graph_launch(b, ws, ws_bytes, nll, hip_stream))) break;  // warm-up
+      HIPCHK(hipEventRecord(e0, s));
+      for (int r = 0; r < reps && !st; ++r) st = vif_batch_graph_launch(b, ws, ws_bytes, nll, hip_stream);
+      if (st) break;
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      const double per = ms / reps;
+      if (per < best) {
+        best = per;
+        bs = b->streams;
+        bc = b->chunk_rows;
+      }
+    }
+    if (st) break;
+  }
+  b->streams = bs;
+  b->chunk_rows = bc;
+  drop_graph(b);
+  if (st) return st;
+  if (best_ms) *best_ms = best;
+  return ok();
+}
+
+int32_t vif_batch_schedule(const vif_batch* b, int32_t* streams, int32_t* chunk_rows) {
+  if (!b) return fail(VIF_E_ARG, "batch is NULL");
+  if (streams) *streams = b->streams;
+  if (chunk_rows) *chunk_rows = b->chunk_rows;
+  return ok();
+}
+
+int32_t vif_batch_set_schedule(vif_batch* b, int32_t streams, int32_t chunk_rows) {
+  if (!b) return fail(VIF_E_ARG, "batch is NULL");
+  if (streams < 1 || streams > kBatchMaxStreams)
+    return fail(VIF_E_ARG, "streams must be in 1 .. %d", kBatchMaxStreams);
+  if (chunk_rows < 1024 || chunk_rows > 65536 || chunk_rows % 8)
+    return fail(VIF_E_ARG, "chunk_rows must be a multiple of 8 in 1024 .. 65536");
+  b->streams = streams;
+  b->chunk_rows = chunk_rows;
+  drop_graph(b);
+  return ok();
+}
+
+int32_t vif_batch_status(vif_batch* b, void* ws, int32_t* status, void* hip_stream) {
+  if (!b || !ws) return fail(VIF_E_ARG, "NULL argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  const int np = (int)b->probs.size();
+  std::vector<Flags> f((size_t)np);
+  for (int i = 0; i < np; ++i)
+    HIPCHK(hipMemcpyAsync(&f[i], reinterpret_cast<char*>(ws) + b->probs[i].off + b->probs[i].L.flags,
+                          sizeof(Flags), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int32_t first = VIF_OK;
+  for (int i = 0; i < np; ++i) {
+    const int32_t st = report_flags(f[i]);
+    if (status) status[i] = st;
+    if (st && first == VIF_OK) first = st;
+  }
+  if (first == VIF_OK) return ok();
+  return first;
+}
+
+void vif_batch_destroy(vif_batch* b) {
+  if (!b) return;
+  drop_graph(b);
+  for (int j = 0; j < kBatchMaxStreams; ++j) {
+    if (b->side[j]) (void)hipStreamDestroy(b->side[j]);
+    if (b->ev_join[j]) (void)hipEventDestroy(b->ev_join[j]);
+  }
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
+}
 }  // extern "C"

@@ -142,19 +142,25 @@ hipError_t launch_crosscov(const LowRankArgs& a, void* U, int prec, hipStream_t 
 // In place: U[i, :] <- U[i, :] P^T with P lower triangular (U = C(X,Z) L_k^-T).
 hipError_t launch_trmm(const LowRankArgs& a, const double* P, void* U, int prec, hipStream_t s);
 // Split-BF16 modes, kpad small enough for 32 rows of C in LDS (lowrank_fused_ok):
-// U = C(X, Z) P' in one pass, C evaluated on chip; Pb: 2 * kpad^2 bfloat16 scratch.
-bool lowrank_fused_ok(int kpad);
-hipError_t launch_lowrank_fused(const LowRankArgs& a, const double* P, void* Pb, float* U,
+// U = C(X, Z) P' in one pass, C evaluated on chip, with C and P split into two
+// bfloat16 terms (prec 2) or three (prec 3, FP32-accurate); Pb: 2 * kpad^2
+// (prec 2) or 3 * kpad^2 (prec 3) bfloat16 scratch.
+bool lowrank_fused_ok(int kpad, int prec);
+// Raises the fused kernel's dynamic-LDS limit on the current device (once per
+// device; called by launch_lowrank_fused, and before graph capture).
+hipError_t prepare_lowrank_fused();
+hipError_t launch_lowrank_fused(const LowRankArgs& a, const double* P, void* Pb, float* U, int prec,
                                 hipStream_t s);
 // Partial Gram of W over row chunks: part[c][tile] = sum over the rows of chunk c
 // of W_I' W_J (FP64 64 x 64 tiles for prec 0/1, FP32 128 x 128 tiles for the
 // split-BF16 modes). syrk_chunks gives the chunk count, syrk_part_bytes the size
 // of part.
 // For the split-BF16 modes, n is the padded row count of the W planes (wrb * 8).
-int syrk_chunks(int64_t n, int kpad, int prec);
-size_t syrk_part_bytes(int64_t n, int kpad, int prec);
+// chunk_rows (a multiple of 8) sets the rows per FP32 partial in the split-BF16 modes.
+int syrk_chunks(int64_t n, int kpad, int prec, int chunk_rows = 4096);
+size_t syrk_part_bytes(int64_t n, int kpad, int prec, int chunk_rows = 4096);
 hipError_t launch_syrk(int64_t n, int kpad, const void* W, int prec, void* part, int nchunk,
-                       hipStream_t s);
+                       hipStream_t s, int chunk_rows = 4096);
 // Rows of W (processing order, padded) in the split-BF16 plane layout.
 inline int64_t w_plane_rows(int64_t n) { return (n + 15) / 16 * 16; }
 // M = I + (sum_c part[c])[0:k,0:k] with identity padding; q = column k; zz = entry (k,k).
@@ -168,6 +174,8 @@ hipError_t launch_init_flags(void* flags, hipStream_t s);
 hipError_t launch_sum(int64_t n, const double* x, int squared, double* partial, double* out,
                       hipStream_t s);
 // out[0] = nll, out[1..4] = terms; uses logdet/quad from the Cholesky of M when k > 0.
+// *dst = *src (device scalars).
+hipError_t launch_copy_f64(const double* src, double* dst, hipStream_t s);
 hipError_t launch_finalize(int64_t n, int k, int kpad, const double* LM, const double* q,
                            const double* sum_logD, const double* zz, double* out, hipStream_t s);
 

@@ -17,6 +17,7 @@
 //    reduced in FP64 in a fixed order (deterministic; no floating-point atomics).
 #include <math.h>
 
+#include <atomic>
 #include <type_traits>
 
 #include "internal.hpp"
@@ -417,16 +418,20 @@ __global__ __launch_bounds__(256) void trmm_f32_kernel(int64_t n, int kpad, floa
 }
 
 // ------------------------------------------- U = C(X, Z) P' fused (split-BF16) ----
-// P = L_k^-1 in FP32-rounded bfloat16 pairs (h, l): P ~ h + l.
+// P = L_k^-1 rounded to FP32 and split into NS bfloat16 terms, plane p at
+// Pb + p * total: two terms keep its leading 16 significant bits, three all 24.
+template <int NS>
 __global__ __launch_bounds__(256) void split_p_kernel(int64_t total, const double* __restrict__ P,
-                                                      __bf16* __restrict__ Ph,
-                                                      __bf16* __restrict__ Pl) {
+                                                      __bf16* __restrict__ Pb) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= total) return;
-  const float x = (float)P[e];
-  const __bf16 h = (__bf16)x;
-  Ph[e] = h;
-  Pl[e] = (__bf16)(x - (float)h);
+  float x = (float)P[e];
+#pragma unroll
+  for (int p = 0; p < NS; ++p) {
+    const __bf16 h = (__bf16)x;
+    Pb[p * total + e] = h;
+    x -= (float)h;  // exact: h holds the leading bits of x
+  }
 }
 
 // One block per 32 rows of X: the rows' cross-covariances C(x_i, z_l), l < kpad,
@@ -435,6 +440,75 @@ __global__ __launch_bounds__(256) void split_p_kernel(int64_t total, const doubl
 // goes to HBM; U is written once.
 constexpr int URB = 32;
 constexpr int UPAD = 8;
+
+// C(x_i, z_l) for the URB rows from i0 and the columns lbeg .. lbeg + ncol - 1
+// (ncol a multiple of 8) into NS bfloat16 planes of LDS (plane stride pst, row
+// stride ldc, column l at l - lbeg): the FP32 value split into NS terms, each
+// the bfloat16 rounding of what the previous ones leave. Rows past n and
+// columns past k hold zeros. One thread per 8 consecutive columns x 8 rows.
+template <int NS>
+__device__ __forceinline__ void fill_c_planes(const LowRankArgs& A, int64_t i0, int lbeg, int ncol,
+                                              __bf16* C0, int pst, int ldc) {
+  const int tid = threadIdx.x;
+  const int ncg = ncol / 8;  // column groups
+  for (int task = tid; task < ncg * (URB / 8); task += 512) {
+    const int cg = task % ncg, rg = task / ncg;
+    double zx[8], zy[8], zt[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int l = lbeg + cg * 8 + c;
+      const bool ok = l < A.k;
+      zx[c] = ok ? A.zx[l] : 0.0;
+      zy[c] = ok ? A.zy[l] : 0.0;
+      zt[c] = ok ? A.zt[l] : 0.0;
+    }
+    // Gneiting: the lag factors depend on (t_i, z_l) only, and consecutive
+    // points mostly share their time, so they are reused across rows.
+    const bool fac = A.K.kind == 1;
+    float fa[8], fe[8];
+    double tcache = NAN;
+#pragma unroll 1
+    for (int rr = 0; rr < 8; ++rr) {
+      const int row = rg * 8 + rr;
+      const int64_t i = i0 + row;
+      bf8v pl[NS];
+      if (i < A.n) {
+        const double xi = A.sx[i], yi = A.sy[i], ti = A.t[i];
+        if (fac && !(ti == tcache)) {
+          tcache = ti;
+#pragma unroll
+          for (int c = 0; c < 8; ++c) gneiting_lag<float>(A.K, (float)(ti - zt[c]), fa[c], fe[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int l = lbeg + cg * 8 + c;
+          float v = 0.f;
+          if (l < A.k) {
+            if (fac)
+              v = gneiting_pair<float>(A.K, (float)(xi - zx[c]), (float)(yi - zy[c]), fa[c], fe[c]);
+            else
+              v = cov_eval<float>(A.K, (float)(xi - zx[c]), (float)(yi - zy[c]),
+                                  (float)(ti - zt[c]));
+          }
+#pragma unroll
+          for (int p = 0; p < NS; ++p) {
+            const __bf16 h = (__bf16)v;
+            pl[p][c] = h;
+            v -= (float)h;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int p = 0; p < NS; ++p)
+#pragma unroll
+          for (int c = 0; c < 8; ++c) pl[p][c] = (__bf16)0.f;
+      }
+#pragma unroll
+      for (int p = 0; p < NS; ++p)
+        *reinterpret_cast<bf8v*>(C0 + p * pst + row * ldc + cg * 8) = pl[p];
+    }
+  }
+}
 
 __global__ __launch_bounds__(512) void lowrank_u_kernel(LowRankArgs A, const __bf16* __restrict__ Ph,
                                                         const __bf16* __restrict__ Pl,
@@ -447,64 +521,7 @@ __global__ __launch_bounds__(512) void lowrank_u_kernel(LowRankArgs A, const __b
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t i0 = (int64_t)blockIdx.x * URB;
 
-  // ---- C rows into LDS: thread -> 8 consecutive columns x 8 rows ----
-  {
-    const int ncg = kpad / 8;  // column groups
-    for (int task = tid; task < ncg * (URB / 8); task += 512) {
-      const int cg = task % ncg, rg = task / ncg;
-      double zx[8], zy[8], zt[8];
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const int l = cg * 8 + c;
-        const bool ok = l < A.k;
-        zx[c] = ok ? A.zx[l] : 0.0;
-        zy[c] = ok ? A.zy[l] : 0.0;
-        zt[c] = ok ? A.zt[l] : 0.0;
-      }
-      // Gneiting: the lag factors depend on (t_i, z_l) only, and consecutive
-      // points mostly share their time, so they are reused across rows.
-      const bool fac = A.K.kind == 1;
-      float fa[8], fe[8];
-      double tcache = NAN;
-#pragma unroll 1
-      for (int rr = 0; rr < 8; ++rr) {
-        const int row = rg * 8 + rr;
-        const int64_t i = i0 + row;
-        bf8v h8, l8;
-        if (i < A.n) {
-          const double xi = A.sx[i], yi = A.sy[i], ti = A.t[i];
-          if (fac && !(ti == tcache)) {
-            tcache = ti;
-#pragma unroll
-            for (int c = 0; c < 8; ++c) gneiting_lag<float>(A.K, (float)(ti - zt[c]), fa[c], fe[c]);
-          }
-#pragma unroll
-          for (int c = 0; c < 8; ++c) {
-            const int l = cg * 8 + c;
-            float v = 0.f;
-            if (l < A.k) {
-              if (fac)
-                v = gneiting_pair<float>(A.K, (float)(xi - zx[c]), (float)(yi - zy[c]), fa[c], fe[c]);
-              else
-                v = cov_eval<float>(A.K, (float)(xi - zx[c]), (float)(yi - zy[c]),
-                                    (float)(ti - zt[c]));
-            }
-            const __bf16 h = (__bf16)v;
-            h8[c] = h;
-            l8[c] = (__bf16)(v - (float)h);
-          }
-        } else {
-#pragma unroll
-          for (int c = 0; c < 8; ++c) {
-            h8[c] = (__bf16)0.f;
-            l8[c] = (__bf16)0.f;
-          }
-        }
-        *reinterpret_cast<bf8v*>(Ch + row * ldc + cg * 8) = h8;
-        *reinterpret_cast<bf8v*>(Cl + row * ldc + cg * 8) = l8;
-      }
-    }
-  }
+  fill_c_planes<2>(A, i0, 0, kpad, Ch, URB * ldc, ldc);
   __syncthreads();
 
   // ---- U = C P' on MFMA: wave -> column blocks of 16 (snake order for balance) ----
@@ -742,14 +759,14 @@ __global__ __launch_bounds__(256) void syrk_kernel(int64_t n, int kpad, const vo
 // runs the tiles of chunks x, x + 8, ... one chunk after the other, so that the
 // tiles sharing a chunk's rows run together and find them in that XCD's L2.
 constexpr int TB = 128;    // output tile
-constexpr int CHR = 4096;  // rows per chunk (one FP32 accumulation)
+constexpr int CHR = 4096;  // default rows per chunk (one FP32 accumulation)
 constexpr int SBK = 32;    // rows per step (the bf16 MFMA K)
 
 template <int NS>
 __global__ __launch_bounds__(256, 2) void syrk_split_kernel(int64_t nrows, int kpad,
                                                          const __bf16* __restrict__ Wp,
                                                          float* __restrict__ part, int nchunk,
-                                                         int ntile) {
+                                                         int ntile, int chunk_blocks) {
   constexpr int PPS = NS * (SBK / 8) * TB / 256;  // 16-byte pieces per thread and strip
   __shared__ bf8v sP[1][2][NS][SBK / 8][TB];
   const int x = blockIdx.x & 7;
@@ -765,8 +782,8 @@ __global__ __launch_bounds__(256, 2) void syrk_split_kernel(int64_t nrows, int k
   // On a diagonal tile the upper-right quarter is the transpose of the lower-left.
   const bool skip = diag && wr < wc;
   const int64_t wrb = nrows / 8;
-  const int64_t bbeg = (int64_t)c * (CHR / 8);
-  const int64_t bend = bbeg + CHR / 8 < wrb ? bbeg + CHR / 8 : wrb;
+  const int64_t bbeg = (int64_t)c * chunk_blocks;
+  const int64_t bend = bbeg + chunk_blocks < wrb ? bbeg + chunk_blocks : wrb;
   bf8v ra[PPS], rb[PPS];
   // Unconditional loads (out-of-range pieces re-read a valid one and are zeroed
   // at the store), so that each store waits for its own loads only.
@@ -935,24 +952,148 @@ hipError_t launch_crosscov(const LowRankArgs& a, void* U, int prec, hipStream_t 
   return hipGetLastError();
 }
 
-size_t lowrank_fused_lds(int kpad) { return (size_t)2 * URB * (kpad + UPAD) * sizeof(__bf16); }
+// Three-term variant (FP32-accurate U): C and P split into three bfloat16
+// terms, six products per step (lh, mm, hl, mh, hm, hh; smallest first). Three
+// planes of 32 rows do not fit in LDS for the full k, so the columns l of C are
+// taken in two halves. Output column blocks j < kpad / 2 need only the first
+// half (P_j,l = 0 for l > j): they are finished and written in the first
+// phase. The upper blocks keep their accumulators in registers across the
+// phases and are written after the second.
+constexpr int U6_MAXHI = 7;  // upper column blocks per wave: kpad <= 2 * 8 * 16 * 7
 
-bool lowrank_fused_ok(int kpad) { return lowrank_fused_lds(kpad) <= 160 * 1024; }
+__global__ __launch_bounds__(512) void lowrank_u6_kernel(LowRankArgs A, const __bf16* __restrict__ Pb,
+                                                         float* __restrict__ U) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int kpad = A.kpad;
+  const int kh = kpad / 2;  // kpad is a multiple of 64, so kh is one of 32
+  const int ldc = kh + UPAD;
+  const int pst = URB * ldc;
+  __bf16* C0 = reinterpret_cast<__bf16*>(smem);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * URB;
+  const int64_t kk = (int64_t)kpad * kpad;
+  const int nlo = kpad / 32;  // column blocks below kh; as many above
+  const int g = lane >> 4, j = lane & 15;
 
-hipError_t launch_lowrank_fused(const LowRankArgs& a, const double* P, void* Pb, float* U,
+  // acc[r] += C[r * 16 + .., k0 .. k0 + 31] P[cb * 16 + .., k0 .. k0 + 31]' for
+  // k0 = kb, kb + 32, .. < ke; C columns of this phase start at lbeg.
+  auto contract = [&](int cb, int lbeg, int kb, int ke, f4v* acc) __attribute__((always_inline)) {
+    const __bf16* p0 = Pb + (int64_t)(cb * 16 + j) * kpad + 8 * g;
+    bf8v b0 = *reinterpret_cast<const bf8v*>(p0 + kb);
+    bf8v b1 = *reinterpret_cast<const bf8v*>(p0 + kk + kb);
+    bf8v b2 = *reinterpret_cast<const bf8v*>(p0 + 2 * kk + kb);
+    for (int k0 = kb; k0 < ke; k0 += 32) {
+      bf8v n0 = b0, n1 = b1, n2 = b2;
+      if (k0 + 32 < ke) {
+        n0 = *reinterpret_cast<const bf8v*>(p0 + k0 + 32);
+        n1 = *reinterpret_cast<const bf8v*>(p0 + kk + k0 + 32);
+        n2 = *reinterpret_cast<const bf8v*>(p0 + 2 * kk + k0 + 32);
+      }
+      const int ko = k0 - lbeg + 8 * g;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const __bf16* c = C0 + (r * 16 + j) * ldc + ko;
+        const bf8v a0 = *reinterpret_cast<const bf8v*>(c);
+        const bf8v a1 = *reinterpret_cast<const bf8v*>(c + pst);
+        const bf8v a2 = *reinterpret_cast<const bf8v*>(c + 2 * pst);
+        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b0, acc[r], 0, 0, 0);
+        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[r], 0, 0, 0);
+        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b2, acc[r], 0, 0, 0);
+        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[r], 0, 0, 0);
+        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[r], 0, 0, 0);
+        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[r], 0, 0, 0);
+      }
+      b0 = n0;
+      b1 = n1;
+      b2 = n2;
+    }
+  };
+  auto store = [&](int cb, const f4v* acc) __attribute__((always_inline)) {
+    const int jrow = cb * 16 + j;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = mfma16_row_f32acc(lane, e);
+      const int64_t ia = i0 + r, ib = i0 + 16 + r;
+      if (ia < A.n) U[ia * kpad + jrow] = acc[0][e];
+      if (ib < A.n) U[ib * kpad + jrow] = acc[1][e];
+    }
+  };
+
+  // ---- first half of the columns of C ----
+  fill_c_planes<3>(A, i0, 0, kh, C0, pst, ldc);
+  __syncthreads();
+  for (int pass = 0; pass * 8 < nlo; ++pass) {  // lower blocks, snake order for balance
+    const int cb = pass * 8 + ((pass & 1) ? 7 - wave : wave);
+    if (cb >= nlo) continue;
+    f4v acc[2] = {f4v{0.f, 0.f, 0.f, 0.f}, f4v{0.f, 0.f, 0.f, 0.f}};
+    contract(cb, 0, 0, cb * 16 + 16, acc);
+    store(cb, acc);
+  }
+  f4v hi[U6_MAXHI][2];
+#pragma unroll
+  for (int p = 0; p < U6_MAXHI; ++p) {
+    hi[p][0] = hi[p][1] = f4v{0.f, 0.f, 0.f, 0.f};
+    const int hb = p * 8 + ((p & 1) ? 7 - wave : wave);
+    if (hb < nlo) contract(nlo + hb, 0, 0, kh, hi[p]);
+  }
+  __syncthreads();  // every read of the first half is done
+
+  // ---- second half ----
+  fill_c_planes<3>(A, i0, kh, kh, C0, pst, ldc);
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < U6_MAXHI; ++p) {
+    const int hb = p * 8 + ((p & 1) ? 7 - wave : wave);
+    if (hb >= nlo) continue;
+    const int cb = nlo + hb;
+    contract(cb, kh, kh, cb * 16 + 16, hi[p]);
+    store(cb, hi[p]);
+  }
+}
+
+size_t lowrank_fused_lds(int kpad, int prec) {
+  if (prec == 3) return (size_t)3 * URB * (kpad / 2 + UPAD) * sizeof(__bf16);
+  return (size_t)2 * URB * (kpad + UPAD) * sizeof(__bf16);
+}
+
+bool lowrank_fused_ok(int kpad, int prec) {
+  if (prec == 3 && kpad > 2 * 8 * 16 * U6_MAXHI) return false;
+  return lowrank_fused_lds(kpad, prec) <= 160 * 1024;
+}
+
+hipError_t prepare_lowrank_fused() {
+  // The dynamic-LDS limit is raised to the largest size once per device.
+  static std::atomic<int> attr_dev[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev >= 0 && dev < 64 && attr_dev[dev].load(std::memory_order_acquire)) return hipSuccess;
+  e = hipFuncSetAttribute((const void*)lowrank_u_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          160 * 1024);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)lowrank_u6_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e == hipSuccess && dev >= 0 && dev < 64) attr_dev[dev].store(1, std::memory_order_release);
+  return e;
+}
+
+hipError_t launch_lowrank_fused(const LowRankArgs& a, const double* P, void* Pb, float* U, int prec,
                                 hipStream_t s) {
   const int64_t kk = (int64_t)a.kpad * a.kpad;
   __bf16* Ph = reinterpret_cast<__bf16*>(Pb);
-  __bf16* Pl = Ph + kk;
-  hipLaunchKernelGGL(split_p_kernel, dim3((unsigned)((kk + 255) / 256)), dim3(256), 0, s, kk, P,
-                     Ph, Pl);
-  const size_t lds = lowrank_fused_lds(a.kpad);
-  hipError_t e = hipFuncSetAttribute((const void*)lowrank_u_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = prepare_lowrank_fused();
   if (e != hipSuccess) return e;
+  const dim3 gs((unsigned)((kk + 255) / 256));
+  const size_t lds = lowrank_fused_lds(a.kpad, prec);
   const unsigned grid = (unsigned)((a.n + URB - 1) / URB);
-  hipLaunchKernelGGL(lowrank_u_kernel, dim3(grid), dim3(512), lds, s, a, (const __bf16*)Ph,
-                     (const __bf16*)Pl, U);
+  if (prec == 3) {
+    hipLaunchKernelGGL(split_p_kernel<3>, gs, dim3(256), 0, s, kk, P, Ph);
+    hipLaunchKernelGGL(lowrank_u6_kernel, dim3(grid), dim3(512), lds, s, a, (const __bf16*)Ph, U);
+  } else {
+    hipLaunchKernelGGL(split_p_kernel<2>, gs, dim3(256), 0, s, kk, P, Ph);
+    hipLaunchKernelGGL(lowrank_u_kernel, dim3(grid), dim3(512), lds, s, a, (const __bf16*)Ph,
+                       (const __bf16*)(Ph + kk), U);
+  }
   return hipGetLastError();
 }
 
@@ -976,29 +1117,29 @@ int syrk_ntile(int kpad, int tb) {
 }
 }  // namespace
 
-int syrk_chunks(int64_t n, int, int prec) {
+int syrk_chunks(int64_t n, int, int prec, int chunk_rows) {
   if (prec <= 1) return 8;
-  const int64_t c = (n + CHR - 1) / CHR;
+  const int64_t c = (n + chunk_rows - 1) / chunk_rows;
   return (int)(((c + 7) / 8) * 8);
 }
 
-size_t syrk_part_bytes(int64_t n, int kpad, int prec) {
-  const size_t c = (size_t)syrk_chunks(n, kpad, prec);
+size_t syrk_part_bytes(int64_t n, int kpad, int prec, int chunk_rows) {
+  const size_t c = (size_t)syrk_chunks(n, kpad, prec, chunk_rows);
   if (prec <= 1) return sizeof(double) * c * syrk_ntile(kpad, NB) * NB * NB;
   return sizeof(float) * c * syrk_ntile(kpad, TB) * TB * TB;
 }
 
 hipError_t launch_syrk(int64_t n, int kpad, const void* W, int prec, void* part, int nchunk,
-                       hipStream_t s) {
+                       hipStream_t s, int chunk_rows) {
   if (prec >= 2) {
     const int ntile = syrk_ntile(kpad, TB);
     dim3 grid((unsigned)(ntile * nchunk));
     if (prec == 2)
       hipLaunchKernelGGL(syrk_split_kernel<2>, grid, dim3(256), 0, s, n, kpad,
-                         (const __bf16*)W, (float*)part, nchunk, ntile);
+                         (const __bf16*)W, (float*)part, nchunk, ntile, chunk_rows / 8);
     else
       hipLaunchKernelGGL(syrk_split_kernel<3>, grid, dim3(256), 0, s, n, kpad,
-                         (const __bf16*)W, (float*)part, nchunk, ntile);
+                         (const __bf16*)W, (float*)part, nchunk, ntile, chunk_rows / 8);
     return hipGetLastError();
   }
   const int ntile = syrk_ntile(kpad, NB);

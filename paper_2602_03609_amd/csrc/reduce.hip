@@ -132,6 +132,15 @@ hipError_t launch_sum(int64_t n, const double* x, int squared, double* partial, 
   return hipGetLastError();
 }
 
+__global__ void copy_f64_kernel(const double* __restrict__ src, double* __restrict__ dst) {
+  if (threadIdx.x == 0) *dst = *src;
+}
+
+hipError_t launch_copy_f64(const double* src, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(copy_f64_kernel, dim3(1), dim3(64), 0, s, src, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_finalize(int64_t n, int k, int kpad, const double* LM, const double* q,
                            const double* sum_logD, const double* zz, double* out, hipStream_t s) {
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, s, n, k, kpad, LM, q, sum_logD, zz,

@@ -269,3 +269,30 @@ def config_station_days(seed=0, n_stations=3340, n_days=30, m=30, missing=0.1, p
         kern = perturb_hyper(kern, rng)
     return {"sx": sx, "sy": sy, "t": t, "kern": kern, "m": m, "n": int(sx.shape[0]), "k": 0,
             "name": f"stations n={sx.shape[0]} m={m}"}
+
+
+def config_batch(seed=0, count=64, n_lo=10_000, n_hi=200_000, ms=(10, 20, 30), ks=(200, 500),
+                 n_stations=3340, missing=0.1):
+    """Independent station-network problems for batched evaluation: n log-uniform
+    in [n_lo, n_hi] (a time-ordered prefix of a station network observed daily),
+    m and k drawn from `ms` and `ks`, hyperparameters drawn around the
+    continental kernel (perturb_hyper), k kMeans++ inducing points, a smooth
+    random response."""
+    rng = np.random.default_rng(seed)
+    base = kern_gneiting(sigma2=1.0, a=1.0956, c=2.1277e-3, alpha=0.75, beta=0.5, gamma=0.5,
+                         tau=1.0, nugget=0.1)
+    out = []
+    for b in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        m = int(rng.choice(ms))
+        k = int(rng.choice(ks))
+        n_days = max(2, int(math.ceil(n / (n_stations * (1.0 - missing)))) + 1)
+        sx, sy, t = station_days(n_stations, n_days, missing, rng)
+        sx, sy, t = time_stratified_order(sx, sy, t, rng)
+        sx, sy, t = sx[:n], sy[:n], t[:n]
+        kern = perturb_hyper(base, rng)
+        ind = inducing_points(sx, sy, t, k, 1408.0, 6.7, rng, lloyd_iters=2, seed_sample=20_000,
+                              lloyd_sample=50_000)
+        y = rff_field(sx, sy, t, rng, ls_s=400.0, ls_t=3.0, noise=kern["nugget"], n_feat=64)
+        out.append(_pack(sx, sy, t, y, kern, m, ind, name=f"batch[{b}] n={n} m={m} k={k}"))
+    return out

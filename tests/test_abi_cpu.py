@@ -110,3 +110,35 @@ def test_learned_proposal_argument_errors():
     centre = (ctypes.c_double * 10)(*([0.0] * 10))
     st = lib.vif_mlp_features(ctypes.byref(P), ctypes.byref(K), centre, ctypes.c_void_p(0x1000), None)
     assert st == L.VIF_E_ARG and b"scale" in lib.vif_last_error()
+
+
+def test_batch_argument_errors():
+    """Batch planning rejects bad arguments before any device call."""
+    import paper_2602_03609_amd._lib as L
+    lib = L.load()
+    assert lib.vif_batch_create(None, 1, 0, ctypes.c_void_p(0x1000), 16384, None) is None
+    assert b"at least one problem" in lib.vif_last_error()
+    probs = (L.Problem * 1)()
+    assert lib.vif_batch_create(probs, 1, 7, ctypes.c_void_p(0x1000), 16384, None) is None
+    assert b"precision" in lib.vif_last_error()
+    assert lib.vif_batch_create(probs, 1, 1, ctypes.c_void_p(0x1000), 100, None) is None
+    assert b"scratch" in lib.vif_last_error()
+    assert lib.vif_batch_create(probs, 1, 1, ctypes.c_void_p(0x1001), 16384, None) is None
+    assert b"aligned" in lib.vif_last_error()
+    probs[0].points.n = 10
+    probs[0].points.sx = probs[0].points.sy = probs[0].points.t = 0x1000
+    probs[0].y = 0x1000
+    probs[0].kern = L.make_kernel({"kind": 1, "sigma2": 1.0, "nugget": 0.1, "a": 0.5, "c": 20.0,
+                                   "alpha": 0.75, "beta": 0.5, "gamma": 0.5, "tau": 1.0})
+    probs[0].m = 70
+    probs[0].nbr = 0x1000
+    assert lib.vif_batch_create(probs, 1, 1, ctypes.c_void_p(0x1000), 16384, None) is None
+    assert b"VIF_MAX_M" in lib.vif_last_error()
+    probs[0].m = 5
+    probs[0].nbr = None
+    assert lib.vif_batch_create(probs, 1, 1, ctypes.c_void_p(0x1000), 16384, None) is None
+    assert b"nbr is NULL" in lib.vif_last_error()
+    assert lib.vif_batch_workspace_bytes(None) == 0
+    assert lib.vif_batch_enqueue(None, None, 0, None, None) == L.VIF_E_ARG
+    assert lib.vif_batch_set_schedule(None, 1, 4096) == L.VIF_E_ARG
+    lib.vif_batch_destroy(None)

@@ -1,0 +1,213 @@
+"""Batched evaluation (include/vif_batch.h) through the C ABI.
+
+Bars: every problem's NLL from a batch is within the precision's bar of the
+FP64 oracle (the bars of the single-problem parity tests); under the default
+schedule (one stream, 4096-row FP32 partials) it equals vif_nll of the same
+problem bit for bit, on the eager enqueue and on every replay of the captured
+graph (the same kernels on the same data in the same order); other schedules
+change only the FP32 partial sums of the split-BF16 Gram and stay within the
+bar. At the batched workload's sizes the FP32 batch is checked against the
+FP64 single-problem path, whose parity with the oracle is tested elsewhere.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import likelihood as LK
+from oracle import neighbors as NB
+from tests.gpu_util import dev, lib, log, problem_on_device, rel, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+NLL_TOL = {"fp64": 1e-8, "fp32": 1e-5, "bf16x6": 1e-5, "bf16x3": 1e-4}
+
+
+def _small_problems():
+    """Uneven sizes, ragged early rows, Vecchia, FITC (m = 0) and VIF, several kernels."""
+    ds = [
+        synth.config_small(seed=31, n_sites=150, n_times=6, k=40, m=12, kind=1),
+        synth.config_small(seed=32, n_sites=60, n_times=4, k=0, m=8, kind=1),
+        synth.config_small(seed=33, n_times=5, k=60, m=30, kind=1, n_stations=250),
+        synth.config_small(seed=34, n_sites=90, n_times=5, k=25, m=0, kind=2),
+        synth.config_small(seed=35, n_sites=100, n_times=7, k=70, m=20, kind=3),
+    ]
+    ds[2]["kern"] = synth.perturb_hyper(ds[2]["kern"], np.random.default_rng(2))
+    return ds
+
+
+def _oracle_nll(d, nb):
+    X = (d["sx"], d["sy"], d["t"])
+    if d["k"]:
+        return LK.vif(d["kern"], X, d["y"], nb, (d["zx"], d["zy"], d["zt"]))["nll"]
+    return LK.vecchia(d["kern"], X, d["y"], nb)["nll"]
+
+
+def _on_device(ds, nbrs):
+    torch = torch_cuda()
+    probs = []
+    for d, nb in zip(ds, nbrs):
+        X, y, Z = problem_on_device(d)
+        probs.append({"sx": X[0], "sy": X[1], "t": X[2], "y": y, "kern": d["kern"],
+                      "nbr": dev(nb, torch.int32) if d["m"] > 0 else None, "ind": Z, "m": d["m"]})
+    return probs
+
+
+def _single(vif, p, prec):
+    return vif.vif_nll(p["sx"], p["sy"], p["t"], p["y"], p["kern"], p["m"], p["nbr"], ind=p["ind"],
+                       prec=prec)
+
+
+@pytest.fixture(scope="module")
+def small():
+    ds = _small_problems()
+    nbrs = [NB.brute_force(d["kern"], d["sx"], d["sy"], d["t"], d["m"]) for d in ds]
+    want = [_oracle_nll(d, nb) for d, nb in zip(ds, nbrs)]
+    return ds, nbrs, want
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+def test_batch_matches_oracle_and_single_calls(small, prec):
+    torch = torch_cuda()
+    vif = lib()
+    ds, nbrs, want = small
+    probs = _on_device(ds, nbrs)
+    b = vif.Batch(probs, prec=prec)
+    assert b.schedule() == (1, 4096)
+    got = b.enqueue().cpu().numpy()
+    assert b.status() == [0] * len(ds)
+    for i, p in enumerate(probs):
+        single = _single(vif, p, prec)
+        err = rel(got[i], want[i])
+        log(f"[batch] {prec} problem {i} n={ds[i]['n']} m={ds[i]['m']} k={ds[i]['k']}: "
+            f"batch={got[i]:.12g} single={single:.12g} oracle={want[i]:.12g} rel={err:.2e}")
+        assert got[i] == single
+        assert err <= NLL_TOL[prec]
+    b.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
+def test_batch_schedules(small, prec):
+    torch = torch_cuda()
+    vif = lib()
+    ds, nbrs, want = small
+    b = vif.Batch(_on_device(ds, nbrs), prec=prec)
+    ref = b.enqueue().clone()
+    for streams, rows in [(2, 4096), (4, 4096), (4, 1024), (1, 2048)]:
+        b.set_schedule(streams, rows)
+        assert b.schedule() == (streams, rows)
+        got = b.enqueue().cpu().numpy()
+        log(f"[batch schedule] {prec} streams={streams} rows={rows}: {got}")
+        if rows == 4096 or prec == "fp32":
+            assert np.array_equal(got, ref.cpu().numpy())
+        for i in range(len(ds)):
+            assert rel(got[i], want[i]) <= NLL_TOL[prec]
+    with pytest.raises(vif.VifError):
+        b.set_schedule(5, 4096)
+    with pytest.raises(vif.VifError):
+        b.set_schedule(1, 1000)
+    b.close()
+
+
+@pytest.mark.parametrize("streams", [1, 4])
+def test_graph_replays_equal_eager(small, streams):
+    """Replays of the captured graph, with eager library work and torch work on the
+    same stream between them, each reproduce the eager enqueue bit for bit."""
+    torch = torch_cuda()
+    vif = lib()
+    ds, nbrs, want = small
+    probs = _on_device(ds, nbrs)
+    b = vif.Batch(probs, prec="bf16x6")
+    b.set_schedule(streams, 4096)
+    eager = b.enqueue().clone()
+    torch.cuda.synchronize()
+    for r in range(4):
+        b.nll.fill_(float("nan"))
+        b.graph_launch()
+        got = b.nll.clone()
+        torch.cuda.synchronize()
+        log(f"[graph] streams={streams} replay {r}: {got.cpu().numpy()}")
+        assert torch.equal(got, eager)
+        # eager work between replays: a single-problem NLL through the same kernels
+        x = _single(vif, probs[r % len(probs)], "fp32")
+        assert np.isfinite(x)
+    # a new schedule is captured afresh
+    b.set_schedule(2, 1024)
+    b.graph_launch()
+    got = b.nll.cpu().numpy()
+    for i in range(len(ds)):
+        assert rel(got[i], want[i]) <= NLL_TOL["bf16x6"]
+    b.close()
+
+
+def test_autotune_picks_a_candidate(small):
+    torch = torch_cuda()
+    vif = lib()
+    ds, nbrs, want = small
+    b = vif.Batch(_on_device(ds, nbrs), prec="bf16x6")
+    ms = b.autotune(reps=2)
+    streams, rows = b.schedule()
+    log(f"[autotune] best {ms:.3f} ms at streams={streams} rows={rows}")
+    assert ms > 0 and streams in (1, 2, 4) and rows in (1024, 4096)
+    got = b.graph_launch().cpu().numpy()
+    for i in range(len(ds)):
+        assert rel(got[i], want[i]) <= NLL_TOL["bf16x6"]
+    b.close()
+
+
+def test_status_isolates_a_bad_problem(small):
+    torch = torch_cuda()
+    vif = lib()
+    ds, nbrs, want = small
+    bad = [nb.copy() for nb in nbrs]
+    bad[2][40, 3] = 41  # not an earlier point
+    b = vif.Batch(_on_device(ds, bad), prec="fp32")
+    got = b.enqueue().cpu().numpy()
+    st = b.status()
+    log(f"[batch status] {st}")
+    assert st[2] == vif.VIF_E_ARG
+    assert [s for i, s in enumerate(st) if i != 2] == [0] * (len(ds) - 1)
+    for i in range(len(ds)):
+        if i != 2:
+            assert rel(got[i], want[i]) <= NLL_TOL["fp32"]
+    b.close()
+
+
+def test_create_rejects_bad_problems(small):
+    torch = torch_cuda()
+    vif = lib()
+    ds, nbrs, _ = small
+    probs = _on_device(ds, nbrs)
+    probs[1] = dict(probs[1], m=70, nbr=torch.zeros((probs[1]["sx"].shape[0], 70), dtype=torch.int32,
+                                                    device="cuda"))
+    with pytest.raises(vif.VifError, match="VIF_MAX_M"):
+        vif.Batch(probs, prec="fp32")
+
+
+def test_batched_workload_sizes():
+    """Problems of the batched workload (n log-uniform in 10k..200k, m in {10, 20,
+    30}, k in {200, 500}, perturbed kernels): the FP32 batch under every schedule
+    against the FP64 single-problem path, and bit for bit against FP32 vif_nll
+    under the default schedule."""
+    torch = torch_cuda()
+    vif = lib()
+    ds = synth.config_batch(seed=0, count=6)
+    probs = []
+    for d in ds:
+        X, y, Z = problem_on_device(d)
+        nb = vif.vif_neighbors(*X, d["kern"], d["m"])
+        probs.append({"sx": X[0], "sy": X[1], "t": X[2], "y": y, "kern": d["kern"], "nbr": nb,
+                      "ind": Z, "m": d["m"]})
+    ref64 = [_single(vif, p, "fp64") for p in probs]
+    ref32 = [_single(vif, p, "fp32") for p in probs]
+    b = vif.Batch(probs, prec="fp32")
+    for streams in (1, 2, 4):
+        b.set_schedule(streams, 4096)
+        got = b.graph_launch().cpu().numpy()
+        assert b.status() == [0] * len(ds)
+        for i, d in enumerate(ds):
+            err = rel(got[i], ref64[i])
+            log(f"[batch sizes] streams={streams} {d['name']}: fp32 batch {got[i]:.12g} "
+                f"fp64 {ref64[i]:.12g} rel {err:.2e}")
+            assert got[i] == ref32[i]
+            assert err <= NLL_TOL["fp32"]
+    b.close()
