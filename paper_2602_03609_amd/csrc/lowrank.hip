@@ -420,35 +420,60 @@ __global__ __launch_bounds__(256) void trmm_f32_kernel(int64_t n, int kpad, floa
 // ------------------------------------------- U = C(X, Z) P' fused (split-BF16) ----
 // P = L_k^-1 rounded to FP32 and split into NS bfloat16 terms, plane p at
 // Pb + p * total: two terms keep its leading 16 significant bits, three all 24.
+// Each plane is stored in the order the U kernel reads it: tiles of 16 rows x
+// 32 columns (row j, column l at offset j * 32 + l % 32 in the tile), the tile
+// of rows 16 t .. 16 t + 15 and columns 32 s .. 32 s + 31 at index
+// ((t / 2) * (kpad / 32) + s) * 2 + t % 2; one wave's fragment load of a step
+// is then one contiguous kilobyte.
 template <int NS>
-__global__ __launch_bounds__(256) void split_p_kernel(int64_t total, const double* __restrict__ P,
+__global__ __launch_bounds__(256) void split_p_kernel(int64_t total, int kpad,
+                                                      const double* __restrict__ P,
                                                       __bf16* __restrict__ Pb) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= total) return;
+  const int row = (int)(e / kpad), col = (int)(e - (int64_t)row * kpad);
+  const int t = row >> 4, sl = col >> 5;
+  const int64_t o =
+      ((((int64_t)(t >> 1) * (kpad >> 5) + sl) * 2 + (t & 1)) * 16 + (row & 15)) * 32 + (col & 31);
   float x = (float)P[e];
 #pragma unroll
   for (int p = 0; p < NS; ++p) {
     const __bf16 h = (__bf16)x;
-    Pb[p * total + e] = h;
+    Pb[p * total + o] = h;
     x -= (float)h;  // exact: h holds the leading bits of x
   }
 }
 
-// One block per 32 rows of X: the rows' cross-covariances C(x_i, z_l), l < kpad,
-// are evaluated once into LDS as bfloat16 pairs, then U_i,j = sum_{l <= j} C_i,l
-// P_j,l for all j on MFMA (3 products: hh, hl, lh), P streamed from L2. C never
-// goes to HBM; U is written once.
+// One block per 32 rows of X: the rows' cross-covariances C(x_i, z_l) are
+// evaluated into LDS as NS bfloat16 terms, then U_i,j = sum_{l <= j} C_i,l P_j,l
+// for all j on MFMA, P (split the same way) streamed from L2. C never goes to
+// HBM; U is written once.
 constexpr int URB = 32;
 constexpr int UPAD = 8;
+
+// The URB rows' coordinates into LDS (one load per row, all in flight at once),
+// so that the row loop of fill_c_planes reads no global memory. Ends with a
+// barrier.
+__device__ __forceinline__ void stage_rows(const LowRankArgs& A, int64_t i0, double* sRow) {
+  const int tid = threadIdx.x;
+  if (tid < 3 * URB) {
+    const int row = tid / 3, c = tid - 3 * (tid / 3);
+    const int64_t i = i0 + row;
+    const double* src = c == 0 ? A.sx : (c == 1 ? A.sy : A.t);
+    sRow[tid] = i < A.n ? src[i] : 0.0;
+  }
+  __syncthreads();
+}
 
 // C(x_i, z_l) for the URB rows from i0 and the columns lbeg .. lbeg + ncol - 1
 // (ncol a multiple of 8) into NS bfloat16 planes of LDS (plane stride pst, row
 // stride ldc, column l at l - lbeg): the FP32 value split into NS terms, each
 // the bfloat16 rounding of what the previous ones leave. Rows past n and
 // columns past k hold zeros. One thread per 8 consecutive columns x 8 rows.
+// sRow: the rows' (x, y, t), staged in LDS by stage_rows.
 template <int NS>
-__device__ __forceinline__ void fill_c_planes(const LowRankArgs& A, int64_t i0, int lbeg, int ncol,
-                                              __bf16* C0, int pst, int ldc) {
+__device__ __forceinline__ void fill_c_planes(const LowRankArgs& A, int64_t i0, const double* sRow,
+                                              int lbeg, int ncol, __bf16* C0, int pst, int ldc) {
   const int tid = threadIdx.x;
   const int ncg = ncol / 8;  // column groups
   for (int task = tid; task < ncg * (URB / 8); task += 512) {
@@ -473,7 +498,7 @@ __device__ __forceinline__ void fill_c_planes(const LowRankArgs& A, int64_t i0, 
       const int64_t i = i0 + row;
       bf8v pl[NS];
       if (i < A.n) {
-        const double xi = A.sx[i], yi = A.sy[i], ti = A.t[i];
+        const double xi = sRow[3 * row], yi = sRow[3 * row + 1], ti = sRow[3 * row + 2];
         if (fac && !(ti == tcache)) {
           tcache = ti;
 #pragma unroll
@@ -510,62 +535,6 @@ __device__ __forceinline__ void fill_c_planes(const LowRankArgs& A, int64_t i0, 
   }
 }
 
-__global__ __launch_bounds__(512) void lowrank_u_kernel(LowRankArgs A, const __bf16* __restrict__ Ph,
-                                                        const __bf16* __restrict__ Pl,
-                                                        float* __restrict__ U) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const int kpad = A.kpad;
-  const int ldc = kpad + UPAD;
-  __bf16* Ch = reinterpret_cast<__bf16*>(smem);
-  __bf16* Cl = Ch + URB * ldc;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t i0 = (int64_t)blockIdx.x * URB;
-
-  fill_c_planes<2>(A, i0, 0, kpad, Ch, URB * ldc, ldc);
-  __syncthreads();
-
-  // ---- U = C P' on MFMA: wave -> column blocks of 16 (snake order for balance) ----
-  const int ncb = kpad / 16;
-  const int g = lane >> 4, j = lane & 15;
-  for (int pass = 0; pass * 8 < ncb; ++pass) {
-    const int cb = pass * 8 + ((pass & 1) ? 7 - wave : wave);
-    if (cb >= ncb) continue;
-    const int jrow = cb * 16 + j;  // output column = row of P
-    const __bf16* ph = Ph + (int64_t)jrow * kpad + 8 * g;
-    const __bf16* pl = Pl + (int64_t)jrow * kpad + 8 * g;
-    const int kend = cb * 16 + 16;  // P_j,l = 0 for l > j
-    f4v acc0 = f4v{0.f, 0.f, 0.f, 0.f}, acc1 = f4v{0.f, 0.f, 0.f, 0.f};
-    bf8v bh = *reinterpret_cast<const bf8v*>(ph);
-    bf8v bl = *reinterpret_cast<const bf8v*>(pl);
-    for (int k0 = 0; k0 < kend; k0 += 32) {
-      bf8v nh = bh, nl = bl;
-      if (k0 + 32 < kend) {
-        nh = *reinterpret_cast<const bf8v*>(ph + k0 + 32);
-        nl = *reinterpret_cast<const bf8v*>(pl + k0 + 32);
-      }
-      const int ko = k0 + 8 * g;
-      const bf8v a0h = *reinterpret_cast<const bf8v*>(Ch + j * ldc + ko);
-      const bf8v a0l = *reinterpret_cast<const bf8v*>(Cl + j * ldc + ko);
-      const bf8v a1h = *reinterpret_cast<const bf8v*>(Ch + (16 + j) * ldc + ko);
-      const bf8v a1l = *reinterpret_cast<const bf8v*>(Cl + (16 + j) * ldc + ko);
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0l, bh, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1l, bh, acc1, 0, 0, 0);
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0h, bl, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1h, bl, acc1, 0, 0, 0);
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0h, bh, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1h, bh, acc1, 0, 0, 0);
-      bh = nh;
-      bl = nl;
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int r = mfma16_row_f32acc(lane, e);
-      const int64_t ia = i0 + r, ib = i0 + 16 + r;
-      if (ia < A.n) U[ia * kpad + jrow] = acc0[e];
-      if (ib < A.n) U[ib * kpad + jrow] = acc1[e];
-    }
-  }
-}
 
 // ------------------------------------------------------------------- SYRK ----
 __device__ __forceinline__ void tile_of(int t, int& TI, int& TJ) {
@@ -952,17 +921,20 @@ hipError_t launch_crosscov(const LowRankArgs& a, void* U, int prec, hipStream_t 
   return hipGetLastError();
 }
 
-// Three-term variant (FP32-accurate U): C and P split into three bfloat16
-// terms, six products per step (lh, mm, hl, mh, hm, hh; smallest first). Three
-// planes of 32 rows do not fit in LDS for the full k, so the columns l of C are
-// taken in two halves. Output column blocks j < kpad / 2 need only the first
-// half (P_j,l = 0 for l > j): they are finished and written in the first
-// phase. The upper blocks keep their accumulators in registers across the
-// phases and are written after the second.
-constexpr int U6_MAXHI = 7;  // upper column blocks per wave: kpad <= 2 * 8 * 16 * 7
+// NS = 2 terms keep 16 significant bits of C and P (three products per step:
+// lh, hl, hh); NS = 3 keep all 24 (FP32-accurate U; six products: lh, mm, hl,
+// mh, hm, hh), smallest first. A wave takes 32 output columns at a time (two
+// 16-column blocks sharing the k range, since P_j,l = 0 for l > j), so each A
+// fragment read from LDS feeds 2 NS products. The columns l of C are taken in
+// two halves (three planes of 32 rows do not fit in LDS for the full k).
+// Output columns j < kpad / 2 need only the first half: they are finished and
+// written in the first phase. The upper columns keep their accumulators in
+// registers across the phases and are written after the second.
+constexpr int U6_MAXHI = 4;  // upper 32-column blocks per wave: kpad <= 2 * 8 * 32 * 4
 
-__global__ __launch_bounds__(512) void lowrank_u6_kernel(LowRankArgs A, const __bf16* __restrict__ Pb,
-                                                         float* __restrict__ U) {
+template <int NS>
+__global__ __launch_bounds__(512) void lowrank_u_kernel(LowRankArgs A, const __bf16* __restrict__ Pb,
+                                                        float* __restrict__ U) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int kpad = A.kpad;
   const int kh = kpad / 2;  // kpad is a multiple of 64, so kh is one of 32
@@ -972,93 +944,118 @@ __global__ __launch_bounds__(512) void lowrank_u6_kernel(LowRankArgs A, const __
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t i0 = (int64_t)blockIdx.x * URB;
   const int64_t kk = (int64_t)kpad * kpad;
-  const int nlo = kpad / 32;  // column blocks below kh; as many above
+  const int nlo = kpad / 64;  // 32-column blocks below kh; as many above
   const int g = lane >> 4, j = lane & 15;
 
-  // acc[r] += C[r * 16 + .., k0 .. k0 + 31] P[cb * 16 + .., k0 .. k0 + 31]' for
-  // k0 = kb, kb + 32, .. < ke; C columns of this phase start at lbeg.
-  auto contract = [&](int cb, int lbeg, int kb, int ke, f4v* acc) __attribute__((always_inline)) {
-    const __bf16* p0 = Pb + (int64_t)(cb * 16 + j) * kpad + 8 * g;
-    bf8v b0 = *reinterpret_cast<const bf8v*>(p0 + kb);
-    bf8v b1 = *reinterpret_cast<const bf8v*>(p0 + kk + kb);
-    bf8v b2 = *reinterpret_cast<const bf8v*>(p0 + 2 * kk + kb);
-    for (int k0 = kb; k0 < ke; k0 += 32) {
-      bf8v n0 = b0, n1 = b1, n2 = b2;
-      if (k0 + 32 < ke) {
-        n0 = *reinterpret_cast<const bf8v*>(p0 + k0 + 32);
-        n1 = *reinterpret_cast<const bf8v*>(p0 + kk + k0 + 32);
-        n2 = *reinterpret_cast<const bf8v*>(p0 + 2 * kk + k0 + 32);
+  // acc[r][c] += C[r * 16 + .., k0 .. k0 + 31] P[pb * 32 + c * 16 + .., k0 .. k0 + 31]'
+  // for k0 = kb, kb + 32, .. < ke; C columns of this phase start at lbeg. Two
+  // register sets alternate (steps unrolled by two), so that the P fragments
+  // of the next step load while this one computes with no copy between sets.
+  auto contract = [&](int pb, int lbeg, int kb, int ke, f4v (*acc)[2]) __attribute__((always_inline)) {
+    // P in 16 x 32 tiles (split_p_kernel<NS>): the fragment of column
+    // block c at step k0 is the kilobyte at ((pb * kpad / 32 + k0 / 32) * 2 + c) * 512.
+    const __bf16* p0 = Pb + (int64_t)pb * kpad * 32 + j * 32 + 8 * g;
+    auto load = [&](bf8v (*b)[NS], int k0) __attribute__((always_inline)) {
+      const __bf16* q = p0 + k0 * 32;
+#pragma unroll
+      for (int p = 0; p < NS; ++p) {
+        b[0][p] = *reinterpret_cast<const bf8v*>(q + p * kk);
+        b[1][p] = *reinterpret_cast<const bf8v*>(q + p * kk + 512);
       }
+    };
+    auto step = [&](bf8v (*b)[NS], int k0) __attribute__((always_inline)) {
       const int ko = k0 - lbeg + 8 * g;
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
-        const __bf16* c = C0 + (r * 16 + j) * ldc + ko;
-        const bf8v a0 = *reinterpret_cast<const bf8v*>(c);
-        const bf8v a1 = *reinterpret_cast<const bf8v*>(c + pst);
-        const bf8v a2 = *reinterpret_cast<const bf8v*>(c + 2 * pst);
-        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b0, acc[r], 0, 0, 0);
-        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[r], 0, 0, 0);
-        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b2, acc[r], 0, 0, 0);
-        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[r], 0, 0, 0);
-        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[r], 0, 0, 0);
-        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[r], 0, 0, 0);
-      }
-      b0 = n0;
-      b1 = n1;
-      b2 = n2;
-    }
-  };
-  auto store = [&](int cb, const f4v* acc) __attribute__((always_inline)) {
-    const int jrow = cb * 16 + j;
+        const __bf16* cp = C0 + (r * 16 + j) * ldc + ko;
+        bf8v a[NS];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int r = mfma16_row_f32acc(lane, e);
-      const int64_t ia = i0 + r, ib = i0 + 16 + r;
-      if (ia < A.n) U[ia * kpad + jrow] = acc[0][e];
-      if (ib < A.n) U[ib * kpad + jrow] = acc[1][e];
+        for (int p = 0; p < NS; ++p) a[p] = *reinterpret_cast<const bf8v*>(cp + p * pst);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          f4v x = acc[r][c];
+          if constexpr (NS == 3) {
+            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[c][0], x, 0, 0, 0);
+            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[c][1], x, 0, 0, 0);
+            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[c][2], x, 0, 0, 0);
+          }
+          x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[c][0], x, 0, 0, 0);
+          x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[c][1], x, 0, 0, 0);
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[c][0], x, 0, 0, 0);
+        }
+      }
+    };
+    bf8v x[2][NS], y[2][NS];
+    load(x, kb);
+    int k0 = kb;
+    for (; k0 + 32 < ke; k0 += 64) {
+      load(y, k0 + 32);
+      __builtin_amdgcn_sched_barrier(0);  // issued before the step that hides them
+      step(x, k0);
+      load(x, k0 + 64 < ke ? k0 + 64 : k0 + 32);  // past the end: re-read (unconditional)
+      __builtin_amdgcn_sched_barrier(0);
+      step(y, k0 + 32);
+    }
+    if (k0 < ke) step(x, k0);  // odd step count
+  };
+  auto store = [&](int pb, f4v (*acc)[2]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int jcol = pb * 32 + c * 16 + j;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = mfma16_row_f32acc(lane, e);
+        const int64_t ia = i0 + r, ib = i0 + 16 + r;
+        if (ia < A.n) U[ia * kpad + jcol] = acc[0][c][e];
+        if (ib < A.n) U[ib * kpad + jcol] = acc[1][c][e];
+      }
     }
   };
 
   // ---- first half of the columns of C ----
-  fill_c_planes<3>(A, i0, 0, kh, C0, pst, ldc);
+  __shared__ double sRow[3 * URB];
+  stage_rows(A, i0, sRow);
+  fill_c_planes<NS>(A, i0, sRow, 0, kh, C0, pst, ldc);
   __syncthreads();
   for (int pass = 0; pass * 8 < nlo; ++pass) {  // lower blocks, snake order for balance
-    const int cb = pass * 8 + ((pass & 1) ? 7 - wave : wave);
-    if (cb >= nlo) continue;
-    f4v acc[2] = {f4v{0.f, 0.f, 0.f, 0.f}, f4v{0.f, 0.f, 0.f, 0.f}};
-    contract(cb, 0, 0, cb * 16 + 16, acc);
-    store(cb, acc);
-  }
-  f4v hi[U6_MAXHI][2];
+    const int pb = pass * 8 + ((pass & 1) ? 7 - wave : wave);
+    if (pb >= nlo) continue;
+    f4v acc[2][2];
 #pragma unroll
-  for (int p = 0; p < U6_MAXHI; ++p) {
-    hi[p][0] = hi[p][1] = f4v{0.f, 0.f, 0.f, 0.f};
-    const int hb = p * 8 + ((p & 1) ? 7 - wave : wave);
-    if (hb < nlo) contract(nlo + hb, 0, 0, kh, hi[p]);
+    for (int r = 0; r < 2; ++r) acc[r][0] = acc[r][1] = f4v{0.f, 0.f, 0.f, 0.f};
+    contract(pb, 0, 0, pb * 32 + 32, acc);
+    store(pb, acc);
+  }
+  f4v hi[U6_MAXHI][2][2];
+#pragma unroll
+  for (int q = 0; q < U6_MAXHI; ++q) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) hi[q][r][0] = hi[q][r][1] = f4v{0.f, 0.f, 0.f, 0.f};
+    const int hb = q * 8 + ((q & 1) ? 7 - wave : wave);
+    if (hb < nlo) contract(nlo + hb, 0, 0, kh, hi[q]);
   }
   __syncthreads();  // every read of the first half is done
 
   // ---- second half ----
-  fill_c_planes<3>(A, i0, kh, kh, C0, pst, ldc);
+  fill_c_planes<NS>(A, i0, sRow, kh, kh, C0, pst, ldc);
   __syncthreads();
 #pragma unroll
-  for (int p = 0; p < U6_MAXHI; ++p) {
-    const int hb = p * 8 + ((p & 1) ? 7 - wave : wave);
+  for (int q = 0; q < U6_MAXHI; ++q) {
+    const int hb = q * 8 + ((q & 1) ? 7 - wave : wave);
     if (hb >= nlo) continue;
-    const int cb = nlo + hb;
-    contract(cb, kh, kh, cb * 16 + 16, hi[p]);
-    store(cb, hi[p]);
+    const int pb = nlo + hb;
+    contract(pb, kh, kh, pb * 32 + 32, hi[q]);
+    store(pb, hi[q]);
   }
 }
 
 size_t lowrank_fused_lds(int kpad, int prec) {
-  if (prec == 3) return (size_t)3 * URB * (kpad / 2 + UPAD) * sizeof(__bf16);
-  return (size_t)2 * URB * (kpad + UPAD) * sizeof(__bf16);
+  return (size_t)(prec == 3 ? 3 : 2) * URB * (kpad / 2 + UPAD) * sizeof(__bf16);
 }
 
 bool lowrank_fused_ok(int kpad, int prec) {
-  if (prec == 3 && kpad > 2 * 8 * 16 * U6_MAXHI) return false;
-  return lowrank_fused_lds(kpad, prec) <= 160 * 1024;
+  if (kpad > 2 * 8 * 32 * U6_MAXHI) return false;
+  return lowrank_fused_lds(kpad, prec) + 3 * URB * sizeof(double) <= 160 * 1024;
 }
 
 hipError_t prepare_lowrank_fused() {
@@ -1068,11 +1065,12 @@ hipError_t prepare_lowrank_fused() {
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   if (dev >= 0 && dev < 64 && attr_dev[dev].load(std::memory_order_acquire)) return hipSuccess;
-  e = hipFuncSetAttribute((const void*)lowrank_u_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          160 * 1024);
+  const int dyn = 160 * 1024 - 3 * URB * (int)sizeof(double);  // beside the static row stage
+  e = hipFuncSetAttribute((const void*)lowrank_u_kernel<2>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)lowrank_u6_kernel,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    e = hipFuncSetAttribute((const void*)lowrank_u_kernel<3>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
   if (e == hipSuccess && dev >= 0 && dev < 64) attr_dev[dev].store(1, std::memory_order_release);
   return e;
 }
@@ -1087,12 +1085,11 @@ hipError_t launch_lowrank_fused(const LowRankArgs& a, const double* P, void* Pb,
   const size_t lds = lowrank_fused_lds(a.kpad, prec);
   const unsigned grid = (unsigned)((a.n + URB - 1) / URB);
   if (prec == 3) {
-    hipLaunchKernelGGL(split_p_kernel<3>, gs, dim3(256), 0, s, kk, P, Ph);
-    hipLaunchKernelGGL(lowrank_u6_kernel, dim3(grid), dim3(512), lds, s, a, (const __bf16*)Ph, U);
+    hipLaunchKernelGGL(split_p_kernel<3>, gs, dim3(256), 0, s, kk, a.kpad, P, Ph);
+    hipLaunchKernelGGL(lowrank_u_kernel<3>, dim3(grid), dim3(512), lds, s, a, (const __bf16*)Ph, U);
   } else {
-    hipLaunchKernelGGL(split_p_kernel<2>, gs, dim3(256), 0, s, kk, P, Ph);
-    hipLaunchKernelGGL(lowrank_u_kernel, dim3(grid), dim3(512), lds, s, a, (const __bf16*)Ph,
-                       (const __bf16*)(Ph + kk), U);
+    hipLaunchKernelGGL(split_p_kernel<2>, gs, dim3(256), 0, s, kk, a.kpad, P, Ph);
+    hipLaunchKernelGGL(lowrank_u_kernel<2>, dim3(grid), dim3(512), lds, s, a, (const __bf16*)Ph, U);
   }
   return hipGetLastError();
 }
