@@ -468,7 +468,7 @@ int32_t nll_impl(const vif_points* p, const double* y, const vif_kernel* kern, i
     HIPCHK(vif::launch_cholesky(L.kpad, M, reinterpret_cast<double*>(ws + L.dscr), fl + 2, s));
     HIPCHK(vif::launch_sum(p->n, fa.logD, 0, part, sums + 0, s));
     HIPCHK(vif::launch_sum(p->n, fa.z, 1, part, sums + 1, s));
-    HIPCHK(vif::launch_finalize(p->n, k, L.kpad, M, q, sums + 0, sums + 1, out, s));
+    HIPCHK(vif::launch_finalize(p->n, k, L.kpad, M, sums + 0, sums + 1, out, s));
     PROF(VIF_STAGE_ASSEMBLY, true);
   } else {
     fa.z = reinterpret_cast<double*>(ws + L.z);
@@ -478,7 +478,7 @@ int32_t nll_impl(const vif_points* p, const double* y, const vif_kernel* kern, i
     PROF(VIF_STAGE_ASSEMBLY, false);
     HIPCHK(vif::launch_sum(p->n, fa.logD, 0, part, sums + 0, s));
     HIPCHK(vif::launch_sum(p->n, fa.z, 1, part, sums + 1, s));
-    HIPCHK(vif::launch_finalize(p->n, 0, 0, nullptr, nullptr, sums + 0, sums + 1, out, s));
+    HIPCHK(vif::launch_finalize(p->n, 0, 0, nullptr, sums + 0, sums + 1, out, s));
     PROF(VIF_STAGE_ASSEMBLY, true);
   }
   Flags f;
@@ -1043,12 +1043,12 @@ int32_t enqueue_problem(const ProbPlan& P, int prec, int chunk_rows, char* wsb, 
     HIPCHK(vif::launch_cholesky(L.kpad, M, reinterpret_cast<double*>(ws + L.dscr), fl + 2, s));
     HIPCHK(vif::launch_sum(P.p.n, fa.logD, 0, part, sums + 0, s));
     HIPCHK(vif::launch_sum(P.p.n, fa.z, 1, part, sums + 1, s));
-    HIPCHK(vif::launch_finalize(P.p.n, P.k, L.kpad, M, q, sums + 0, sums + 1, out, s));
+    HIPCHK(vif::launch_finalize(P.p.n, P.k, L.kpad, M, sums + 0, sums + 1, out, s));
   } else {
     HIPCHK(vif::launch_point_factor(fa, 0, prec, s));
     HIPCHK(vif::launch_sum(P.p.n, fa.logD, 0, part, sums + 0, s));
     HIPCHK(vif::launch_sum(P.p.n, fa.z, 1, part, sums + 1, s));
-    HIPCHK(vif::launch_finalize(P.p.n, 0, 0, nullptr, nullptr, sums + 0, sums + 1, out, s));
+    HIPCHK(vif::launch_finalize(P.p.n, 0, 0, nullptr, sums + 0, sums + 1, out, s));
   }
   HIPCHK(vif::launch_copy_f64(out, nll_out, s));
   return VIF_OK;

@@ -163,7 +163,9 @@ hipError_t launch_syrk(int64_t n, int kpad, const void* W, int prec, void* part,
                        hipStream_t s, int chunk_rows = 4096);
 // Rows of W (processing order, padded) in the split-BF16 plane layout.
 inline int64_t w_plane_rows(int64_t n) { return (n + 15) / 16 * 16; }
-// M = I + (sum_c part[c])[0:k,0:k] with identity padding; q = column k; zz = entry (k,k).
+// From G = sum_c part[c], the Gram of [W z]: M = the augmented Woodbury matrix
+// (I + G[0:k,0:k], row and column k = q = G[k,0:k], entry (k,k) = 2 G[k,k] + 1,
+// identity padding); q = G[k,0:k]; zz = G[k,k].
 hipError_t launch_syrk_reduce(int k, int kpad, const void* part, int prec, int nchunk, double* M,
                               double* q, double* zz, hipStream_t s);
 
@@ -173,10 +175,12 @@ hipError_t launch_init_flags(void* flags, hipStream_t s);
 // Deterministic sum of x[0..n) into *out (two-level tree, fixed order). partial: [256] scratch.
 hipError_t launch_sum(int64_t n, const double* x, int squared, double* partial, double* out,
                       hipStream_t s);
-// out[0] = nll, out[1..4] = terms; uses logdet/quad from the Cholesky of M when k > 0.
 // *dst = *src (device scalars).
 hipError_t launch_copy_f64(const double* src, double* dst, hipStream_t s);
-hipError_t launch_finalize(int64_t n, int k, int kpad, const double* LM, const double* q,
-                           const double* sum_logD, const double* zz, double* out, hipStream_t s);
+// out[0] = nll, out[1..4] = terms. For k > 0, LM is the Cholesky factor of the
+// augmented Woodbury matrix written by launch_syrk_reduce: log det M from its
+// first k pivots, q' M^-1 q from its row k.
+hipError_t launch_finalize(int64_t n, int k, int kpad, const double* LM, const double* sum_logD,
+                           const double* zz, double* out, hipStream_t s);
 
 }  // namespace vif

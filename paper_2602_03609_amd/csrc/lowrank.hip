@@ -67,6 +67,14 @@ __device__ __forceinline__ void tri_solve_regs(double v[16], const double (*T)[N
   }
 }
 
+// x from lane `lane` of the wave (a uniform value, through scalar registers).
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Panel kernel: block w factors the diagonal block jb (redundantly) and, for
 // w > 0, solves row block jb + w of the panel against it.
 __global__ __launch_bounds__(256) void chol_panel_kernel(int N, double* __restrict__ A, int jb,
@@ -78,39 +86,34 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(int N, double* __restri
   const int w = blockIdx.x;
   const int64_t d0 = (int64_t)jb * NB;
   const int lane = tid & 63, s = tid >> 2, g = tid & 3;
-  // Row s of the panel block (w > 0), entries g + 4i, loaded before the factorisation.
-  double v[16];
-  if (w > 0) {
-    const int64_t r0 = (int64_t)(jb + w) * NB;
+  // Right-looking factorisation of the diagonal block by wave 0 in registers:
+  // lane r holds row r; the pivot and each multiplier l_c are read from their
+  // owner lane with readlane (scalar registers), so there is no LDS traffic and
+  // no synchronisation until the factor is stored. Entries above the diagonal
+  // are never touched: the multiplier of rows r <= kk is zero.
+  if (tid < NB) {
+    const int r = tid;
+    double a[NB];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = A[(r0 + s) * N + d0 + g + 4 * i];
-  }
-  if (tid == 0) bad = -1;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e / NB, c = e % NB;
-    Ld[r][c] = (c <= r) ? A[(d0 + r) * N + d0 + c] : 0.0;
+    for (int c = 0; c < NB; ++c) a[c] = (c <= r) ? A[(d0 + r) * N + d0 + c] : 0.0;
+    int badl = -1;
+#pragma unroll
+    for (int kk = 0; kk < NB; ++kk) {
+      const double d = readlane_f64(a[kk], kk);
+      const bool okp = d > 0.0 && d < INFINITY;
+      const double piv = okp ? sqrt(d) : 1.0;
+      if (!okp && badl < 0) badl = kk;
+      const double lm = r > kk ? a[kk] / piv : 0.0;
+      if (r >= kk) a[kk] = r > kk ? lm : piv;
+#pragma unroll
+      for (int c = kk + 1; c < NB; ++c) a[c] -= lm * readlane_f64(lm, c);
+      __builtin_amdgcn_sched_barrier(0);  // one column at a time (bounded scalar live ranges)
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) Ld[r][c] = (c <= r) ? a[c] : 0.0;
+    if (r == 0) bad = badl;
   }
   __syncthreads();
-  // Right-looking factorisation of the diagonal block; thread (r = tid & 63)
-  // updates row r, columns c = kk + 1 + (tid >> 6) + 4j <= r.
-  const int ur = tid & 63, uc = tid >> 6;
-  for (int kk = 0; kk < NB; ++kk) {
-    double d = Ld[kk][kk];
-    const bool okp = d > 0.0 && d < INFINITY;
-    const double piv = okp ? sqrt(d) : 1.0;
-    __syncthreads();
-    if (tid == 0) {
-      if (!okp && bad < 0) bad = kk;
-      Ld[kk][kk] = piv;
-    }
-    if (tid > kk && tid < NB) Ld[tid][kk] /= piv;
-    __syncthreads();
-    if (ur > kk) {
-      const double lr = Ld[ur][kk];
-      for (int c = kk + 1 + uc; c <= ur; c += 4) Ld[ur][c] -= lr * Ld[c][kk];
-    }
-    __syncthreads();
-  }
   if (w == 0) {
     // The other blocks of this launch still read the unfactored diagonal block,
     // so the factor goes to scratch; the update launch copies it into place.
@@ -121,9 +124,13 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(int N, double* __restri
     }
     return;
   }
-  // X L' = A_panel, i.e. L x = a for each row a of the panel block.
-  tri_solve_regs(v, Ld, g, lane);
+  // X L' = A_panel, i.e. L x = a for each row a of the panel block: row s,
+  // entries g + 4i.
   const int64_t r0 = (int64_t)(jb + w) * NB;
+  double v[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = A[(r0 + s) * N + d0 + g + 4 * i];
+  tri_solve_regs(v, Ld, g, lane);
 #pragma unroll
   for (int i = 0; i < 16; ++i) A[(r0 + s) * N + d0 + g + 4 * i] = v[i];
 }
@@ -841,6 +848,21 @@ __global__ __launch_bounds__(256, 2) void syrk_split_kernel(int64_t nrows, int k
 }
 
 // M = I + sum over chunks (FP64, fixed order) of the lower tiles, q = row k, zz = (k, k).
+// Entry (r, c) of the matrix whose Cholesky factor gives both terms of the
+// Woodbury assembly: rows and columns 0 .. k-1 hold M = I + W'W, row k holds
+// q' = (W'z)' and, on the diagonal, 2 z'z + 1, rows past k the identity. Its
+// factor is [[L_M, 0], [v', d]] with v = L_M^-1 q, so q' M^-1 q = |v|^2 with no
+// separate triangular solve; the last pivot 2 z'z + 1 - q' M^-1 q exceeds z'z
+// + 1 (q' M^-1 q <= z'z), so the factorisation cannot fail there. s is the
+// Gram entry of [W z].
+__device__ __forceinline__ double augmented_entry(int r, int c, int k, double s) {
+  if (r < k && c < k) return (r == c ? 1.0 : 0.0) + s;
+  if (r == k && c < k) return s;
+  if (c == k && r < k) return s;
+  if (r == k && c == k) return 2.0 * s + 1.0;
+  return r == c ? 1.0 : 0.0;
+}
+
 __global__ __launch_bounds__(256) void syrk_split_reduce_kernel(int k, int kpad,
                                                                 const float* __restrict__ part,
                                                                 int nchunk, int ntile,
@@ -860,11 +882,7 @@ __global__ __launch_bounds__(256) void syrk_split_reduce_kernel(int k, int kpad,
 #pragma unroll 8
   for (int cc = 0; cc < nchunk; ++cc) s += (double)src[cc * stride];
   const int r = TI * TB + er, col = TJ * TB + ec;
-  if (r < kpad && col < kpad) {
-    double v = (r == col) ? 1.0 : 0.0;
-    if (r < k && col < k) v += s;
-    M[(int64_t)r * kpad + col] = v;
-  }
+  if (r < kpad && col < kpad) M[(int64_t)r * kpad + col] = augmented_entry(r, col, k, s);
   if (r == k && col < k) q[col] = s;
   if (r == k && col == k) *zz = s;
 }
@@ -879,9 +897,7 @@ __global__ void syrk_reduce_kernel(int k, int kpad, const double* __restrict__ p
     double s = 0.0;
     for (int sp = 0; sp < splits; ++sp) s += part[((int64_t)sp * ntile + t) * (NB * NB) + e];
     const int r = TI * NB + e / NB, c = TJ * NB + e % NB;
-    double v = (r == c) ? 1.0 : 0.0;
-    if (r < k && c < k) v += s;
-    M[(int64_t)r * kpad + c] = v;
+    M[(int64_t)r * kpad + c] = augmented_entry(r, c, k, s);
     if (r == k && c < k) q[c] = s;
     if (r == k && c == k) *zz = s;
   }

@@ -49,54 +49,26 @@ __global__ __launch_bounds__(kSumThreads) void sum_stage2(const double* __restri
   if (threadIdx.x == 0) *out = s;
 }
 
-// One workgroup: log det M from the diagonal of its Cholesky factor and
-// q' M^-1 q = |L_M^-1 q|^2 by blocked forward substitution.
+// One workgroup: log det M from the diagonal of the Cholesky factor of the
+// augmented Woodbury matrix (M in rows 0 .. k-1, q' in row k), and q' M^-1 q as
+// the squared norm of the factor's row k, which is L_M^-1 q.
 __global__ __launch_bounds__(1024) void finalize_kernel(int64_t n, int k, int kpad,
                                                         const double* __restrict__ LM,
-                                                        const double* __restrict__ q,
                                                         const double* __restrict__ sum_logD,
                                                         const double* __restrict__ zz,
                                                         double* __restrict__ out) {
-  __shared__ double v[4096 + 64];
   __shared__ double sh[1024];
-  __shared__ double t[64];
   const int tid = threadIdx.x;
   double logdet = 0.0, quad = 0.0;
   if (k > 0) {
-    double acc = 0.0;
-    for (int a = tid; a < k; a += 1024) acc += log(LM[(int64_t)a * kpad + a]);
-    logdet = 2.0 * block_sum(acc, sh);
-    const int NT = kpad / 64;
-    for (int b = 0; b < NT; ++b) {
-      const int r0 = b * 64;
-      // t[r] = q[r0+r] - sum_{c<r0} L[r0+r][c] v[c]; 16 threads per row.
-      const int r = tid >> 4, part = tid & 15;
-      double s = 0.0;
-      for (int c = part; c < r0; c += 16) s += LM[(int64_t)(r0 + r) * kpad + c] * v[c];
-      sh[tid] = s;
-      __syncthreads();
-      if (part == 0) {
-        double tot = 0.0;
-        for (int u = 0; u < 16; ++u) tot += sh[tid + u];
-        t[r] = ((r0 + r) < k ? q[r0 + r] : 0.0) - tot;
-      }
-      __syncthreads();
-      if (tid < 64) {
-        // Triangular solve of the diagonal block by wave 0: lane c holds L[rr][c].
-        for (int rr = 0; rr < 64; ++rr) {
-          const double* Lrow = LM + (int64_t)(r0 + rr) * kpad + r0;
-          double p = tid < rr ? Lrow[tid] * v[r0 + tid] : 0.0;
-#pragma unroll
-          for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off);
-          const double x = (t[rr] - p) / Lrow[rr];
-          if (tid == 0) v[r0 + rr] = x;
-          wave_lds_sync();
-        }
-      }
-      __syncthreads();
+    double acc = 0.0, qa = 0.0;
+    for (int a = tid; a < k; a += 1024) {
+      acc += log(LM[(int64_t)a * kpad + a]);
+      const double v = LM[(int64_t)k * kpad + a];
+      qa += v * v;
     }
-    double qa = 0.0;
-    for (int a = tid; a < kpad; a += 1024) qa += v[a] * v[a];
+    logdet = 2.0 * block_sum(acc, sh);
+    __syncthreads();
     quad = block_sum(qa, sh);
   }
   if (tid == 0) {
@@ -141,9 +113,9 @@ hipError_t launch_copy_f64(const double* src, double* dst, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(int64_t n, int k, int kpad, const double* LM, const double* q,
-                           const double* sum_logD, const double* zz, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, s, n, k, kpad, LM, q, sum_logD, zz,
+hipError_t launch_finalize(int64_t n, int k, int kpad, const double* LM, const double* sum_logD,
+                           const double* zz, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, s, n, k, kpad, LM, sum_logD, zz,
                      out);
   return hipGetLastError();
 }
