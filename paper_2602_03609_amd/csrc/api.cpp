@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <string>
+#include <algorithm>
 #include <memory>
 #include <vector>
 
@@ -150,7 +151,7 @@ Layout make_layout(int64_t n, int m, int k, int prec, int op, int chunk_rows = 4
     L.Sk = take(sizeof(double) * kk);
     L.P = take(sizeof(double) * kk);
     if (prec >= VIF_PREC_BF16X3) L.Pb = take((prec == VIF_PREC_BF16X6 ? 6 : 4) * kk);
-    L.dscr = take(sizeof(double) * 64 * 64);
+    L.dscr = take(std::max(sizeof(double) * 64 * 64, vif::trinv_scratch_bytes(L.kpad)));
     L.U = take(es * (size_t)n * L.kpad);
     if (op == VIF_OP_NLL) {
       if (prec >= VIF_PREC_BF16X3) {
@@ -383,7 +384,7 @@ int32_t run_lowrank(const vif_points* p, const vif_points* ind, const vif_kernel
   PROF(VIF_STAGE_SIGMA_K, false);
   HIPCHK(vif::launch_cov_kk(a, Sk, s));
   HIPCHK(vif::launch_cholesky(L.kpad, Sk, reinterpret_cast<double*>(ws + L.dscr), fl + 1, s));
-  HIPCHK(vif::launch_trinv(L.kpad, Sk, P, s));
+  HIPCHK(vif::launch_trinv(L.kpad, Sk, P, reinterpret_cast<double*>(ws + L.dscr), s));
   PROF(VIF_STAGE_SIGMA_K, true);
   if (prec >= VIF_PREC_BF16X3 && vif::lowrank_fused_ok(L.kpad, prec)) {
     // Cross-covariance evaluated on chip inside the product.

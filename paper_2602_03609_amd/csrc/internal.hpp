@@ -135,8 +135,10 @@ hipError_t launch_cov_kk(const LowRankArgs& a, double* S, hipStream_t s);
 // the diagonal blocks zeroed, other upper blocks untouched). scratch: 64*64 doubles.
 hipError_t launch_cholesky(int N, double* A, double* scratch, unsigned long long* fail,
                            hipStream_t s);
-// P = L^-1 for lower-triangular L (N x N, N multiple of 64); upper part of P set to 0.
-hipError_t launch_trinv(int N, const double* L, double* P, hipStream_t s);
+// P = L^-1 (N a multiple of 64, both N x N row-major FP64, zeros above the
+// diagonal); T: scratch of trinv_scratch_bytes(N).
+size_t trinv_scratch_bytes(int N);
+hipError_t launch_trinv(int N, const double* L, double* P, double* T, hipStream_t s);
 // U[i, l] = C(x_i, z_l) for l < k, 0 for k <= l < kpad; FP64 (prec 0) or FP32 (prec >= 1).
 hipError_t launch_crosscov(const LowRankArgs& a, void* U, int prec, hipStream_t s);
 // In place: U[i, :] <- U[i, :] P^T with P lower triangular (U = C(X,Z) L_k^-T).

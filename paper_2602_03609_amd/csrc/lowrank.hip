@@ -181,67 +181,101 @@ __global__ __launch_bounds__(256) void chol_update_kernel(int N, double* __restr
 }
 
 // ----------------------------------------------------------- triangular inverse
-// Block cb computes column block cb of P = L^-1: for rb = cb.., P_rb,cb =
-// L_rb,rb^-1 (delta I - sum_{cb<=j<rb} L_rb,j P_j,cb).
-__global__ __launch_bounds__(256) void trinv_kernel(int N, const double* __restrict__ L,
-                                                    double* __restrict__ P) {
+// P = L^-1 by doubling: the 64 x 64 diagonal blocks are inverted first; then,
+// for block sizes b = 64, 128, 256, ..., each pair of adjacent inverted blocks
+// A (upper left) and C (lower right) is joined by X = -C^-1 L_CA A^-1, the
+// lower-left block of the inverse of [[L_A, 0], [L_CA, L_C]]. Each level is two
+// launches of 64 x 64 FP64 tile products (T = L_CA A^-1 into scratch, then
+// X = -C^-1 T), with as many workgroups as the level has output tiles, instead
+// of one serial chain per column block.
+
+// Block t: P_tt = L_tt^-1 (64 right-hand sides of the identity solved in
+// registers) and the tiles of P above the diagonal in row block t set to zero.
+__global__ __launch_bounds__(256) void trinv_diag_kernel(int N, const double* __restrict__ L,
+                                                         double* __restrict__ P) {
   __shared__ double Ta[NB][NB + 1];
-  __shared__ double Tb[NB][NB + 1];
-  __shared__ double R[NB][NB + 1];
-  const int cb = blockIdx.x;
+  const int t = blockIdx.x;
   const int NT = N / NB;
   const int tid = threadIdx.x;
-  const int64_t c0 = (int64_t)cb * NB;
-  for (int rb = 0; rb < cb; ++rb)
-    for (int e = tid; e < NB * NB; e += 256) P[((int64_t)rb * NB + e / NB) * N + c0 + e % NB] = 0.0;
-  const int tr = tid / 16, tc = tid % 16;
-  for (int rb = cb; rb < NT; ++rb) {
-    const int64_t r0 = (int64_t)rb * NB;
-    double acc[4][4] = {};
-    for (int j = cb; j < rb; ++j) {
-      __syncthreads();
-      for (int e = tid; e < NB * NB; e += 256) {
-        int r = e / NB, c = e % NB;
-        Ta[r][c] = L[(r0 + r) * N + (int64_t)j * NB + c];          // L_rb,j [r][c]
-        Tb[r][c] = P[((int64_t)j * NB + r) * N + c0 + c];          // P_j,cb [r][c]
-      }
-      __syncthreads();
-      for (int kk = 0; kk < NB; ++kk) {
-        double av[4], bv[4];
+  const int64_t r0 = (int64_t)t * NB;
+  for (int cb = t + 1; cb < NT; ++cb)
+    for (int e = tid; e < NB * NB; e += 256) P[(r0 + e / NB) * N + (int64_t)cb * NB + e % NB] = 0.0;
+  for (int e = tid; e < NB * NB; e += 256) Ta[e / NB][e % NB] = L[(r0 + e / NB) * N + r0 + e % NB];
+  __syncthreads();
+  const int lane = tid & 63, sc = tid >> 2, g = tid & 3;
+  double v[16];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) av[i] = Ta[tr + 16 * i][kk];
+  for (int i = 0; i < 16; ++i) v[i] = (g + 4 * i == sc) ? 1.0 : 0.0;
+  tri_solve_regs(v, Ta, g, lane);
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) bv[jj] = Tb[kk][tc + 16 * jj];
+  for (int i = 0; i < 16; ++i) P[(r0 + g + 4 * i) * N + r0 + sc] = v[i];
+}
+
+// acc (4 x 4 per thread, rows tr + 16 i, columns tc + 16 j of a 64 x 64 tile)
+// += X_tile * Y_tile for row-major 64 x 64 tiles at x and y (leading dims lx, ly).
+__device__ __forceinline__ void tile_fma(double (*Xs)[NB + 1], double (*Ys)[NB + 1],
+                                         const double* __restrict__ x, int64_t lx,
+                                         const double* __restrict__ y, int64_t ly,
+                                         double acc[4][4]) {
+  const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
+  __syncthreads();
+  for (int e = tid; e < NB * NB; e += 256) {
+    Xs[e / NB][e % NB] = x[(int64_t)(e / NB) * lx + e % NB];
+    Ys[e / NB][e % NB] = y[(int64_t)(e / NB) * ly + e % NB];
+  }
+  __syncthreads();
+  for (int kk = 0; kk < NB; ++kk) {
+    double av[4], bv[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i) av[i] = Xs[tr + 16 * i][kk];
 #pragma unroll
-          for (int jj = 0; jj < 4; ++jj) acc[i][jj] += av[i] * bv[jj];
-      }
-    }
-    __syncthreads();
+    for (int j = 0; j < 4; ++j) bv[j] = Ys[kk][tc + 16 * j];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        int r = tr + 16 * i, c = tc + 16 * jj;
-        R[r][c] = ((rb == cb && r == c) ? 1.0 : 0.0) - acc[i][jj];
-      }
-    for (int e = tid; e < NB * NB; e += 256) {
-      int r = e / NB, c = e % NB;
-      Ta[r][c] = L[(r0 + r) * N + r0 + c];  // diagonal block
-    }
-    __syncthreads();
-    // Forward substitution of the 64 columns of R, in registers.
-    {
-      const int lane = tid & 63, sc = tid >> 2, g = tid & 3;
-      double v[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = R[g + 4 * i][sc];
-      tri_solve_regs(v, Ta, g, lane);
-#pragma unroll
-      for (int i = 0; i < 16; ++i) P[(r0 + g + 4 * i) * N + c0 + sc] = v[i];
-    }
+      for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
   }
+}
+
+// One level of the doubling, block size bt tiles. Workgroup -> (pair p, output
+// tile (Il, Jl)); the pair's A block is tiles [s, s + bt), its C block tiles
+// [s + bt, min(s + 2 bt, NT)), s = 2 p bt. PHASE 0: T[Il][Jl] = sum_{K >= J}
+// L[I][K] P[K][J] (A^-1 is lower triangular); PHASE 1: P[I][J] = -sum_{K <= I}
+// P[I][K] T[K][Jl] over the C block.
+template <int PHASE>
+__global__ __launch_bounds__(256) void trinv_level_kernel(int N, const double* __restrict__ L,
+                                                          double* __restrict__ P,
+                                                          double* __restrict__ T, int bt) {
+  __shared__ double Xs[NB][NB + 1];
+  __shared__ double Ys[NB][NB + 1];
+  const int NT = N / NB;
+  const int per = bt * bt;
+  const int p = blockIdx.x / per, rem = blockIdx.x - p * per;
+  const int Il = rem / bt, Jl = rem - (rem / bt) * bt;
+  const int s = 2 * p * bt, c0 = s + bt;
+  const int I = c0 + Il, J = s + Jl;
+  if (I >= NT) return;  // ragged last C block: whole workgroup, before any barrier
+  double* Tp = T + (int64_t)p * per * NB * NB;
+  double acc[4][4] = {};
+  if (PHASE == 0) {
+    for (int K = J; K < c0; ++K)
+      tile_fma(Xs, Ys, L + (int64_t)I * NB * N + (int64_t)K * NB, N,
+               P + (int64_t)K * NB * N + (int64_t)J * NB, N, acc);
+  } else {
+    for (int K = c0; K <= I; ++K)
+      tile_fma(Xs, Ys, P + (int64_t)I * NB * N + (int64_t)K * NB, N,
+               Tp + (int64_t)((K - c0) * bt + Jl) * NB * NB, NB, acc);
+  }
+  const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (PHASE == 0)
+        Tp[(int64_t)(Il * bt + Jl) * NB * NB + (tr + 16 * i) * NB + tc + 16 * j] = acc[i][j];
+      else
+        P[((int64_t)I * NB + tr + 16 * i) * N + (int64_t)J * NB + tc + 16 * j] = -acc[i][j];
+    }
 }
 
 // --------------------------------------------------------------- U = C P' ----
@@ -923,8 +957,25 @@ hipError_t launch_cholesky(int N, double* A, double* scratch, unsigned long long
   return hipGetLastError();
 }
 
-hipError_t launch_trinv(int N, const double* L, double* P, hipStream_t s) {
-  hipLaunchKernelGGL(trinv_kernel, dim3(N / NB), dim3(256), 0, s, N, L, P);
+size_t trinv_scratch_bytes(int N) {
+  const int NT = N / NB;
+  size_t tiles = 0;
+  for (int bt = 1; bt < NT; bt *= 2) {
+    const size_t pairs = (size_t)(NT + 2 * bt - 1) / (2 * bt);
+    tiles = tiles > pairs * bt * bt ? tiles : pairs * bt * bt;
+  }
+  return tiles * NB * NB * sizeof(double);
+}
+
+hipError_t launch_trinv(int N, const double* L, double* P, double* T, hipStream_t s) {
+  const int NT = N / NB;
+  hipLaunchKernelGGL(trinv_diag_kernel, dim3(NT), dim3(256), 0, s, N, L, P);
+  for (int bt = 1; bt < NT; bt *= 2) {
+    const unsigned pairs = (unsigned)((NT + 2 * bt - 1) / (2 * bt));
+    const dim3 grid(pairs * bt * bt);
+    hipLaunchKernelGGL(trinv_level_kernel<0>, grid, dim3(256), 0, s, N, L, P, T, bt);
+    hipLaunchKernelGGL(trinv_level_kernel<1>, grid, dim3(256), 0, s, N, L, P, T, bt);
+  }
   return hipGetLastError();
 }
 
