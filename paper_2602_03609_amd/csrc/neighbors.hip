@@ -174,31 +174,34 @@ __global__ void grid_scatter_kernel(int64_t n, const double* __restrict__ sx,
 // The scatter leaves each cell's points in arrival order; sorting every cell by
 // point index makes the processing order built from the grid independent of
 // scheduling (the neighbor search itself does not depend on the order inside a
-// cell). One thread per cell: insertion sort for short cells, heapsort otherwise.
+// cell). One wavefront per cell: the cell's indices are staged in LDS and each
+// is written back at its rank (the count of smaller indices in the cell);
+// cells longer than kCellCap take a heapsort by one lane instead.
+constexpr int kCellCap = 1024;
+
 __global__ __launch_bounds__(256) void cell_sort_kernel(int64_t ncells,
                                                         const int32_t* __restrict__ off,
                                                         int32_t* __restrict__ pidx) {
-  __shared__ int32_t buf[32][257];  // column per thread: short cells sort in LDS
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncells) return;
+  __shared__ int32_t sbuf[4][kCellCap];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)blockIdx.x * 4 + wave;
+  if (c >= ncells) return;  // whole wavefront; no workgroup barriers below
   int32_t* a = pidx + off[c];
   const int len = off[c + 1] - off[c];
   if (len < 2) return;
-  if (len <= 32) {
-    const int tx = threadIdx.x;
-    for (int q = 0; q < len; ++q) buf[q][tx] = a[q];
-    for (int q = 1; q < len; ++q) {
-      const int32_t v = buf[q][tx];
-      int r = q - 1;
-      while (r >= 0 && buf[r][tx] > v) {
-        buf[r + 1][tx] = buf[r][tx];
-        --r;
-      }
-      buf[r + 1][tx] = v;
+  if (len <= kCellCap) {
+    int32_t* buf = sbuf[wave];
+    for (int q = lane; q < len; q += 64) buf[q] = a[q];
+    wave_lds_sync();
+    for (int q = lane; q < len; q += 64) {
+      const int32_t v = buf[q];
+      int rank = 0;
+      for (int r = 0; r < len; ++r) rank += buf[r] < v ? 1 : 0;
+      a[rank] = v;
     }
-    for (int q = 0; q < len; ++q) a[q] = buf[q][tx];
     return;
   }
+  if (lane != 0) return;
   auto sift = [&](int root, int end) {
     while (2 * root + 1 < end) {
       int child = 2 * root + 1;
@@ -466,8 +469,8 @@ hipError_t launch_grid_build(int64_t n, const double* sx, const double* sy, cons
   if (!px) {
     // processing order: made independent of scheduling
     const int64_t ncells = len - 1;
-    hipLaunchKernelGGL(cell_sort_kernel, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0,
-                       s, ncells, (const int32_t*)counts, pidx);
+    hipLaunchKernelGGL(cell_sort_kernel, dim3((unsigned)((ncells + 3) / 4)), dim3(256), 0, s,
+                       ncells, (const int32_t*)counts, pidx);
   }
   return hipGetLastError();
 }
