@@ -35,5 +35,6 @@ from ._lib import (  # noqa: F401
     vif_profile,
     vif_profile_read,
     vif_propose_neighbors,
+    vif_residual_neighbors,
     vif_workspace_bytes,
 )

@@ -28,7 +28,7 @@ EXPORTS = ("vif_workspace_bytes", "vif_neighbors", "vif_factor", "vif_nll", "vif
            "vif_propose_neighbors", "vif_batch_create", "vif_batch_workspace_bytes",
            "vif_batch_enqueue", "vif_batch_graph_launch", "vif_batch_autotune",
            "vif_batch_schedule", "vif_batch_set_schedule", "vif_batch_status",
-           "vif_batch_destroy")
+           "vif_batch_destroy", "vif_residual_ws", "vif_residual_neighbors")
 BATCH_PLAN_SCRATCH = 16384
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 8, 64, 16, 9936
 STAGES = ("neighbors", "sigma_k", "crosscov", "trmm", "point_factor", "syrk", "assembly")
@@ -126,6 +126,10 @@ def load(path=LIB_PATH):
         lib.vif_batch_set_schedule.restype = i32
         lib.vif_batch_status.argtypes = [vp, vp, pi32, vp]
         lib.vif_batch_status.restype = i32
+        lib.vif_residual_ws.argtypes = [i64, i32]
+        lib.vif_residual_ws.restype = sz
+        lib.vif_residual_neighbors.argtypes = [pP, pK, i32, pP, vp, vp, sz, vp]
+        lib.vif_residual_neighbors.restype = i32
         lib.vif_batch_destroy.argtypes = [vp]
         lib.vif_batch_destroy.restype = None
         _lib = lib
@@ -301,6 +305,28 @@ def vif_profile_read():
     calls = (ctypes.c_int32 * n)()
     _check(load().vif_profile_read(ms, calls, n))
     return {STAGES[i]: (ms[i], calls[i]) for i in range(n)}
+
+
+# ---------------------------------------------------------- residual neighbors ----
+def vif_residual_neighbors(sx, sy, t, kern, m, ind=None, nbr=None, stream=None):
+    """Residual-correlation neighbors for VIF (include/vif_residual.h); int32 [n, m]."""
+    torch = _torch()
+    lib = load()
+    n = sx.shape[0]
+    if nbr is None:
+        nbr = torch.empty((n, m), dtype=torch.int32, device=sx.device)
+    p = make_points(sx, sy, t)
+    K = make_kernel(kern)
+    ip, k = _ind(ind)
+    nbytes = int(lib.vif_residual_ws(int(n), int(k)))
+    if nbytes == 0:
+        raise VifError(VIF_E_ARG, "invalid sizes")
+    ws = _scratch(("resid", str(sx.device)), nbytes, sx.device)
+    _check(lib.vif_residual_neighbors(ctypes.byref(p), ctypes.byref(K), int(m),
+                                      ctypes.byref(ip) if ip is not None else None,
+                                      _dev_ptr(nbr, torch.int32, "nbr"), ws.data_ptr(), ws.numel(),
+                                      _stream(stream)))
+    return nbr
 
 
 # ------------------------------------------------------------ learned proposal ----

@@ -16,6 +16,7 @@
 #include "vif.h"
 #include "vif_learn.h"
 #include "vif_batch.h"
+#include "vif_residual.h"
 
 namespace {
 
@@ -171,6 +172,14 @@ Layout make_layout(int64_t n, int m, int k, int prec, int op, int chunk_rows = 4
     }
   }
   L.total = off;
+  return L;
+}
+
+// Low-rank factor in FP64 (Sigma_k, L_k^-1, U) plus the residual variances.
+Layout make_residual_layout(int64_t n, int k) {
+  Layout L = make_layout(n, 0, k, VIF_PREC_FP64, VIF_OP_FACTOR);
+  L.logD = L.total;  // residual variances r(j, j)
+  L.total += align256(sizeof(double) * (size_t)n);
   return L;
 }
 
@@ -946,6 +955,50 @@ int32_t vif_propose_neighbors(const vif_points* p, const vif_kernel* kern, int32
   return ok();
 }
 
+
+// ------------------------------------------------------- residual neighbors ----
+size_t vif_residual_ws(int64_t n, int32_t k) {
+  if (n < 1 || n >= (int64_t)INT32_MAX || k < 0 || k > VIF_MAX_K) return 0;
+  return make_residual_layout(n, k).total;
+}
+
+int32_t vif_residual_neighbors(const vif_points* p, const vif_kernel* kern, int32_t m,
+                               const vif_points* ind, int32_t* nbr, void* wsv, size_t ws_bytes,
+                               void* hip_stream) {
+  int k = 0;
+  int32_t st = check_ind(ind, &k);
+  if (st) return st;
+  if (!p) return fail(VIF_E_ARG, "points is NULL");
+  if (m < 1) return fail(VIF_E_ARG, "m must be >= 1");
+  const Layout L = make_residual_layout(p->n, k);
+  st = check_common(p, kern, m, wsv, ws_bytes, L.total);
+  if (st) return st;
+  if (!nbr) return fail(VIF_E_ARG, "nbr is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  char* ws = reinterpret_cast<char*>(wsv);
+  if ((st = init_flags(ws, L, s))) return st;
+  double* d = reinterpret_cast<double*>(ws + L.logD);
+  const double* U = nullptr;
+  if (k > 0) {
+    if ((st = run_lowrank(p, ind, kern, VIF_PREC_FP64, ws, L, s))) return st;
+    U = reinterpret_cast<const double*>(ws + L.U);
+  }
+  HIPCHK(vif::launch_resid_var(p->n, L.kpad, kern->sigma2, U, d, s));
+  vif::ResidArgs a{};
+  a.n = p->n;
+  a.m = m;
+  a.kpad = L.kpad;
+  a.K = to_dev(kern);
+  a.sx = p->sx; a.sy = p->sy; a.t = p->t;
+  a.U = U;
+  a.d = d;
+  a.nbr = nbr;
+  HIPCHK(vif::launch_resid_topm(a, s));
+  Flags f;
+  if ((st = read_flags(ws, L, &f, nullptr, 0, s))) return st;
+  if ((st = report_flags(f))) return st;
+  return ok();
+}
 
 // ------------------------------------------------------------------- batches ----
 }  // extern "C"

@@ -185,4 +185,20 @@ hipError_t launch_copy_f64(const double* src, double* dst, hipStream_t s);
 hipError_t launch_finalize(int64_t n, int k, int kpad, const double* LM, const double* sum_logD,
                            const double* zz, double* out, hipStream_t s);
 
+
+// Residual-correlation neighbors (residual.hip).
+struct ResidArgs {
+  int64_t n;
+  int m, kpad;
+  KernDev K;
+  const double *sx, *sy, *t;
+  const double* U;  // [n, kpad] FP64 (NULL when kpad = 0)
+  const double* d;  // residual variances [n]
+  int32_t* nbr;     // [n, m]
+};
+// d[i] = sigma2 - |U_i|^2.
+hipError_t launch_resid_var(int64_t n, int kpad, double sigma2, const double* U, double* d,
+                            hipStream_t s);
+hipError_t launch_resid_topm(const ResidArgs& a, hipStream_t s);
+
 }  // namespace vif

@@ -142,3 +142,25 @@ def test_batch_argument_errors():
     assert lib.vif_batch_enqueue(None, None, 0, None, None) == L.VIF_E_ARG
     assert lib.vif_batch_set_schedule(None, 1, 4096) == L.VIF_E_ARG
     lib.vif_batch_destroy(None)
+
+
+def test_residual_argument_errors():
+    import paper_2602_03609_amd._lib as L
+    lib = L.load()
+    assert lib.vif_residual_ws(0, 10) == 0
+    assert lib.vif_residual_ws(100, 5000) == 0
+    assert lib.vif_residual_ws(1000, 50) > lib.vif_residual_ws(1000, 0) > 0
+    K = L.make_kernel({"kind": 1, "sigma2": 1.0, "nugget": 0.1, "a": 0.5, "c": 20.0, "alpha": 0.75,
+                       "beta": 0.5, "gamma": 0.5, "tau": 1.0})
+    P = L.Points()
+    P.n = 10
+    P.sx = P.sy = P.t = ctypes.c_void_p(0x1000)
+    st = lib.vif_residual_neighbors(ctypes.byref(P), ctypes.byref(K), 0, None,
+                                    ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), 1 << 20, None)
+    assert st == L.VIF_E_ARG and b"m must be" in lib.vif_last_error()
+    st = lib.vif_residual_neighbors(ctypes.byref(P), ctypes.byref(K), 5, None, None,
+                                    ctypes.c_void_p(0x1000), 1 << 20, None)
+    assert st == L.VIF_E_ARG and b"nbr" in lib.vif_last_error()
+    st = lib.vif_residual_neighbors(ctypes.byref(P), ctypes.byref(K), 5, None,
+                                    ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), 16, None)
+    assert st == L.VIF_E_WORKSPACE
