@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-prec", default="fp32", choices=list(PREC_ES))
     ap.add_argument("--batch-reps", type=int, default=10)
+    ap.add_argument("--residual", action="store_true",
+                    help="time the residual-correlation neighbor search on the n=100k, k=500 "
+                         "workload and print its own JSON line")
     ap.add_argument("--batch-only", action="store_true",
                     help="time only the batched workload and print its own JSON line")
     return ap.parse_args()
@@ -206,6 +209,55 @@ def batch_eval(args):
             "schedule": {"streams": streams, "chunk_rows": rows},
             "ms_one_call_at_a_time": ms_seq, "speedup_vs_one_at_a_time": ms_seq / ms,
             "max_rel_err_vs_fp64_sampled": max(errs), "fp64_sampled_problems": len(errs)}
+
+
+def residual_eval(args, reps=3):
+    """Residual-correlation neighbor search (n = 100,000 sites x days, k = 500, m = 30):
+    time per search with HIP events, FP64 MFMA rate of the U U' contraction, and the
+    oracle on sampled rows."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2602_03609_amd as vif
+    from oracle import residual as RS
+    d = synth.config_cfg2()
+    n, m, k = d["n"], d["m"], d["k"]
+    dev = torch.device("cuda:0")
+    td = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    X = (td(d["sx"]), td(d["sy"]), td(d["t"]))
+    Z = (td(d["zx"]), td(d["zy"]), td(d["zt"]))
+    nbr = vif.vif_residual_neighbors(*X, d["kern"], m, ind=Z)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        vif.vif_residual_neighbors(*X, d["kern"], m, ind=Z, nbr=nbr)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    kpad = ((k + 1 + 63) // 64) * 64
+    nb = (n + 63) // 64
+    flops = 2.0 * 64 * 64 * kpad * nb * (nb + 1) / 2   # tiles computed (lower triangle, padded K)
+    got = nbr.cpu().numpy()
+    rows = np.random.default_rng(0).integers(0, n, 20)
+    t0 = time.perf_counter()
+    want = RS.brute_force(d["kern"], (d["sx"], d["sy"], d["t"]), (d["zx"], d["zy"], d["zt"]), m,
+                          rows=rows)
+    t_oracle = time.perf_counter() - t0
+    same = int(sum(np.array_equal(got[r], w) for r, w in zip(rows, want)))
+    log(f"residual: {ms:.1f} ms per search ({n / ms * 1000:.3g} pts/s, "
+        f"{flops / ms / 1e9:.1f} TFLOP/s FP64 MFMA); oracle rows equal {same}/{len(rows)}")
+    return {"metric": "residual-correlation neighbor search pts/s (n=100k, k=500, m=30)",
+            "value": n / ms * 1000.0, "unit": "pts/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "f64", "data": "synthetic", "ms_per_search": ms,
+            "config": {"workload": "5000 uniform sites x 20 days (n=100k), m=30, k=500 kMeans++ "
+                                   "inducing points, Gneiting kernel", "n": n, "m": m, "k": k},
+            "roofline": {"bound": "mfma", "achieved": flops / ms / 1e9, "peak": PEAK["fp64_TFs"],
+                         "unit": "TFLOP/s", "frac": flops / ms / 1e9 / PEAK["fp64_TFs"],
+                         "traffic": None},
+            "oracle_rows_checked": int(len(rows)), "oracle_rows_equal": same,
+            "oracle_s_for_sampled_rows": t_oracle}
 
 
 def stage_work(n, m, k, kpad, es, prec):
@@ -362,6 +414,9 @@ def main():
         sys.exit(1)
     vif.load()
     dev = torch.device("cuda:0")
+    if args.residual:
+        print(json.dumps(residual_eval(args)), flush=True)
+        return
     if args.batch_only:
         b = batch_eval(args)
         print(json.dumps({"metric": "batched VIF NLL problems/s and points/s", "value": b["problems_per_s"],
