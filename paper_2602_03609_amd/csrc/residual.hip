@@ -28,7 +28,6 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 
 constexpr int RB = 64;    // queries per workgroup and candidates per tile
 constexpr int RBK = 16;   // K per LDS stage
-constexpr int RMAXM = 64; // list capacity (m < 64)
 
 __global__ __launch_bounds__(256) void resid_var_kernel(int64_t n, int kpad, double sigma2,
                                                         const double* __restrict__ U,
@@ -46,12 +45,15 @@ __global__ __launch_bounds__(256) void resid_var_kernel(int64_t n, int kpad, dou
   if (lane == 0) d[i] = sigma2 - s;
 }
 
+// MAXM: list capacity (32 when m <= 32, so that two workgroups fit in one CU's
+// LDS; 64 otherwise).
+template <int MAXM>
 __global__ __launch_bounds__(256) void resid_topm_kernel(ResidArgs A) {
   __shared__ double As[RB][RBK + 1];
   __shared__ double Bs[RB][RBK + 1];
   __shared__ double keyT[RB][RB + 1];
-  __shared__ double lk[RB][RMAXM];
-  __shared__ int32_t li[RB][RMAXM];
+  __shared__ double lk[RB][MAXM];
+  __shared__ int32_t li[RB][MAXM];
   __shared__ int32_t cnt[RB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
@@ -164,7 +166,10 @@ hipError_t launch_resid_var(int64_t n, int kpad, double sigma2, const double* U,
 
 hipError_t launch_resid_topm(const ResidArgs& a, hipStream_t s) {
   const unsigned nb = (unsigned)((a.n + RB - 1) / RB);
-  hipLaunchKernelGGL(resid_topm_kernel, dim3(nb), dim3(256), 0, s, a);
+  if (a.m <= 32)
+    hipLaunchKernelGGL(resid_topm_kernel<32>, dim3(nb), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(resid_topm_kernel<64>, dim3(nb), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
