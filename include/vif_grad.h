@@ -1,0 +1,52 @@
+/* vif_grad.h -- gradient of the Vecchia NLL in the kernel hyperparameters
+ * (C ABI of libvif.so).
+ *
+ * The paper fits the hyperparameters by minimising the NLL with a quasi-Newton
+ * method that uses its gradient (Sec. "Estimation and prediction"). For the
+ * plain Vecchia approximation on Sigma + nugget I (the likelihood of vif_nll
+ * with ind = NULL) the NLL is a sum over points of 1/2 [l(S_i) - l(N_i)],
+ * l(T) = log det Sigma~_TT + y_T' Sigma~_TT^-1 y_T, S_i = N(i) + {i}; its
+ * gradient is the sum of the Gaussian formula
+ *     1/2 [tr(Sigma~_T^-1 dSigma~_T) - alpha_T' dSigma~_T alpha_T]
+ * over the two nested blocks of every point.
+ *
+ * Parameters, in this order (the gradient array holds vif_grad_params(kind)):
+ *   VIF_KERNEL_GNEITING:     sigma2, nugget, a, c, alpha, beta, gamma, tau
+ *   VIF_KERNEL_MATERN_ANISO: sigma2, nugget, range_s, range_t   (nu fixed)
+ * VIF_KERNEL_GNEITING_MATERN and inducing points (VIF) are not supported.
+ *
+ * Conventions as in vif.h: DEVICE arrays owned by the caller, work on the
+ * caller's HIP stream, VIF_* status, argument errors found before any launch.
+ */
+#ifndef VIF_GRAD_H
+#define VIF_GRAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "vif.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VIF_GRAD_MAX_PARAMS 8
+
+/* Number of gradient entries for a kernel kind (0 if not supported). */
+int32_t vif_grad_params(int32_t kind);
+
+/* Workspace bytes for vif_nll_grad (0 for invalid sizes). */
+size_t vif_grad_ws(int64_t n);
+
+/* *nll (HOST) and grad (HOST, vif_grad_params(kern->kind) values) of the
+ * Vecchia NLL, nbr as for vif_nll (m <= VIF_MAX_M). Per-point terms are summed
+ * in FP64 in a fixed order (repeatable bits). Synchronises the stream. */
+int32_t vif_nll_grad(const vif_points* points, const double* y, const vif_kernel* kern, int32_t m,
+                     const int32_t* nbr, double* nll, double* grad, void* ws, size_t ws_bytes,
+                     void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VIF_GRAD_H */

@@ -31,6 +31,7 @@ from ._lib import (  # noqa: F401
     vif_mlp_pair_loss,
     vif_neighbors,
     vif_nll,
+    vif_nll_grad,
     vif_nll_terms,
     vif_profile,
     vif_profile_read,

@@ -28,7 +28,8 @@ EXPORTS = ("vif_workspace_bytes", "vif_neighbors", "vif_factor", "vif_nll", "vif
            "vif_propose_neighbors", "vif_batch_create", "vif_batch_workspace_bytes",
            "vif_batch_enqueue", "vif_batch_graph_launch", "vif_batch_autotune",
            "vif_batch_schedule", "vif_batch_set_schedule", "vif_batch_status",
-           "vif_batch_destroy", "vif_residual_ws", "vif_residual_neighbors")
+           "vif_batch_destroy", "vif_residual_ws", "vif_residual_neighbors",
+           "vif_grad_params", "vif_grad_ws", "vif_nll_grad")
 BATCH_PLAN_SCRATCH = 16384
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 8, 64, 16, 9936
 STAGES = ("neighbors", "sigma_k", "crosscov", "trmm", "point_factor", "syrk", "assembly")
@@ -130,6 +131,12 @@ def load(path=LIB_PATH):
         lib.vif_residual_ws.restype = sz
         lib.vif_residual_neighbors.argtypes = [pP, pK, i32, pP, vp, vp, sz, vp]
         lib.vif_residual_neighbors.restype = i32
+        lib.vif_grad_params.argtypes = [i32]
+        lib.vif_grad_params.restype = i32
+        lib.vif_grad_ws.argtypes = [i64]
+        lib.vif_grad_ws.restype = sz
+        lib.vif_nll_grad.argtypes = [pP, vp, pK, i32, vp, pd, pd, vp, sz, vp]
+        lib.vif_nll_grad.restype = i32
         lib.vif_batch_destroy.argtypes = [vp]
         lib.vif_batch_destroy.restype = None
         _lib = lib
@@ -305,6 +312,32 @@ def vif_profile_read():
     calls = (ctypes.c_int32 * n)()
     _check(load().vif_profile_read(ms, calls, n))
     return {STAGES[i]: (ms[i], calls[i]) for i in range(n)}
+
+
+# ---------------------------------------------------------------- NLL gradient ----
+GRAD_PARAMS = {VIF_KERNEL_GNEITING: ("sigma2", "nugget", "a", "c", "alpha", "beta", "gamma", "tau"),
+               VIF_KERNEL_MATERN_ANISO: ("sigma2", "nugget", "range_s", "range_t")}
+
+
+def vif_nll_grad(sx, sy, t, y, kern, m, nbr, stream=None):
+    """(NLL, gradient list) of the plain Vecchia NLL (include/vif_grad.h); the
+    gradient follows GRAD_PARAMS[kern["kind"]]."""
+    torch = _torch()
+    lib = load()
+    n = sx.shape[0]
+    p = make_points(sx, sy, t)
+    K = make_kernel(kern)
+    P = int(lib.vif_grad_params(int(kern["kind"])))
+    nbytes = int(lib.vif_grad_ws(int(n)))
+    if nbytes == 0:
+        raise VifError(VIF_E_ARG, "invalid sizes")
+    ws = _scratch(("grad", str(sx.device)), nbytes, sx.device)
+    out = ctypes.c_double(0.0)
+    g = (ctypes.c_double * 8)()
+    _check(lib.vif_nll_grad(ctypes.byref(p), _dev_ptr(y, torch.float64, "y"), ctypes.byref(K),
+                            int(m), _dev_ptr(nbr, torch.int32, "nbr") if m > 0 else None,
+                            ctypes.byref(out), g, ws.data_ptr(), ws.numel(), _stream(stream)))
+    return out.value, [g[q] for q in range(P)]
 
 
 # ---------------------------------------------------------- residual neighbors ----

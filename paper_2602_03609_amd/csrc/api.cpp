@@ -17,6 +17,7 @@
 #include "vif_learn.h"
 #include "vif_batch.h"
 #include "vif_residual.h"
+#include "vif_grad.h"
 
 namespace {
 
@@ -955,6 +956,110 @@ int32_t vif_propose_neighbors(const vif_points* p, const vif_kernel* kern, int32
   return ok();
 }
 
+
+// --------------------------------------------------------------- NLL gradient ----
+}  // extern "C"
+
+namespace {
+
+struct GradLayout {
+  size_t flags, g, logD, z, part, sums, total;
+};
+
+GradLayout make_grad_layout(int64_t n) {
+  GradLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off += align256(bytes);
+    return at;
+  };
+  L.flags = take(kFlagBytes);
+  L.g = take(sizeof(double) * vif::kGradMaxParams * (size_t)n);
+  L.logD = take(sizeof(double) * (size_t)n);
+  L.z = take(sizeof(double) * (size_t)n);
+  L.part = take(sizeof(double) * 256);
+  L.sums = take(sizeof(double) * (vif::kGradMaxParams + 2));
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t vif_grad_params(int32_t kind) {
+  if (kind == VIF_KERNEL_GNEITING) return 8;
+  if (kind == VIF_KERNEL_MATERN_ANISO) return 4;
+  return 0;
+}
+
+size_t vif_grad_ws(int64_t n) {
+  if (n < 1 || n >= (int64_t)INT32_MAX) return 0;
+  return make_grad_layout(n).total;
+}
+
+int32_t vif_nll_grad(const vif_points* p, const double* y, const vif_kernel* kern, int32_t m,
+                     const int32_t* nbr, double* nll, double* grad, void* wsv, size_t ws_bytes,
+                     void* hip_stream) {
+  if (!p) return fail(VIF_E_ARG, "points is NULL");
+  const GradLayout L = make_grad_layout(p->n > 0 ? p->n : 1);
+  int32_t st = check_common(p, kern, m, wsv, ws_bytes, L.total);
+  if (st) return st;
+  const int P = vif_grad_params(kern->kind);
+  if (P == 0) return fail(VIF_E_UNSUPPORTED, "gradient not available for kernel kind %d", kern->kind);
+  if (!y) return fail(VIF_E_ARG, "y is NULL");
+  if (m > 0 && !nbr) return fail(VIF_E_ARG, "nbr is NULL");
+  if (!nll || !grad) return fail(VIF_E_ARG, "nll or grad is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  char* ws = reinterpret_cast<char*>(wsv);
+  HIPCHK(vif::launch_init_flags(ws + L.flags, s));
+  auto* fl = reinterpret_cast<unsigned long long*>(ws + L.flags);
+  vif::GradArgs a{};
+  a.n = p->n;
+  a.m = m;
+  a.P = P;
+  a.K = to_dev(kern);
+  a.G.kind = kern->kind;
+  a.G.nu_code = kern->kind == VIF_KERNEL_MATERN_ANISO ? nu_code(kern->nu) : 0;
+  a.G.sigma2 = kern->sigma2;
+  a.G.a = kern->a;
+  a.G.c = kern->c;
+  a.G.two_alpha = 2.0 * kern->alpha;
+  a.G.beta = kern->beta;
+  a.G.gamma = kern->gamma;
+  a.G.bg = kern->beta * kern->gamma;
+  a.G.tau = kern->tau;
+  if (kern->kind == VIF_KERNEL_MATERN_ANISO) {
+    a.G.ir_s2 = 1.0 / (kern->range_s * kern->range_s);
+    a.G.ir_t2 = 1.0 / (kern->range_t * kern->range_t);
+    a.G.inv_rs = 1.0 / kern->range_s;
+    a.G.inv_rt = 1.0 / kern->range_t;
+  }
+  a.nugget = kern->nugget;
+  a.sx = p->sx; a.sy = p->sy; a.t = p->t; a.y = y;
+  a.nbr = nbr;
+  a.g = reinterpret_cast<double*>(ws + L.g);
+  a.logD = reinterpret_cast<double*>(ws + L.logD);
+  a.z = reinterpret_cast<double*>(ws + L.z);
+  a.fail = fl;
+  a.bad_nbr = fl + 3;
+  HIPCHK(vif::launch_vecchia_grad(a, s));
+  double* sums = reinterpret_cast<double*>(ws + L.sums);
+  double* part = reinterpret_cast<double*>(ws + L.part);
+  HIPCHK(vif::launch_sum(p->n, a.logD, 0, part, sums + 0, s));
+  HIPCHK(vif::launch_sum(p->n, a.z, 1, part, sums + 1, s));
+  for (int q = 0; q < P; ++q) HIPCHK(vif::launch_sum(p->n, a.g + (int64_t)q * p->n, 0, part, sums + 2 + q, s));
+  Flags f;
+  double h[vif::kGradMaxParams + 2];
+  HIPCHK(hipMemcpyAsync(&f, ws + L.flags, sizeof(Flags), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(h, sums, sizeof(double) * (P + 2), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if ((st = report_flags(f))) return st;
+  *nll = 0.5 * (double)p->n * 1.8378770664093454836 + 0.5 * (h[0] + h[1]);
+  for (int q = 0; q < P; ++q) grad[q] = h[2 + q];
+  return ok();
+}
 
 // ------------------------------------------------------- residual neighbors ----
 size_t vif_residual_ws(int64_t n, int32_t k) {

@@ -1,0 +1,219 @@
+// Gradient of the Vecchia NLL with respect to the kernel hyperparameters (the
+// quantity the paper's quasi-Newton fit needs, Sec. "Estimation and
+// prediction"). Per point, with S = N(i) + {i} (i last), the NLL term is
+// 1/2 [l(S) - l(N)], l(T) = log det Sigma~_TT + y_T' Sigma~_TT^-1 y_T, so its
+// derivative is the difference of the Gaussian formula
+//     dl(T) = tr(Sigma~_TT^-1 dSigma~_TT) - alpha_T' dSigma~_TT alpha_T
+// on the two nested blocks. With L = chol(Sigma~_SS), the inverses differ by
+// the rank-one term v v' (v = last row of L^-1 = (-A_i, 1) / sqrt(D_i)), and
+// alpha_S = alpha_N + z_i v (z_i = (L^-1 y_S)_last, alpha_N = Sigma~_NN^-1 y_N
+// padded with a zero), which gives
+//     dNLL_i = 1/2 [(1 - z_i^2) v' dSigma~ v - 2 z_i v' dSigma~ alpha_N].
+//
+// gfx950 design: one wavefront per point, lane r holding row r of the block in
+// registers (QMAX = 32 or 64 rows). The block, its Cholesky factor (pivots and
+// multipliers through readlane), the forward solve for L^-1 y, and the two
+// backward solves (for v and alpha_N, whose column sums are wave reductions)
+// stay in registers; the derivative matrices are never formed: lane r
+// evaluates dC(r, s) for every parameter and s, and accumulates v_r dC v_s and
+// v_r dC alpha_s. Per-point results go to parameter-major arrays summed later
+// in a fixed order (deterministic).
+#include <math.h>
+
+#include "internal.hpp"
+
+namespace vif {
+namespace {
+
+__device__ __forceinline__ double rdl(double x, int lane) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+  return x;
+}
+
+// Latent covariance and its derivatives in the parameter order of the
+// gradient (GNEITING: sigma2, nugget, a, c, alpha, beta, gamma, tau;
+// MATERN_ANISO: sigma2, nugget, range_s, range_t); dC[1] (nugget) is zero.
+__device__ __forceinline__ double cov_and_grad(const GradKern& G, double dx, double dy, double dt,
+                                               double dC[kGradMaxParams]) {
+  const double h2 = dx * dx + dy * dy;
+  if (G.kind == 3) {
+    const double d = sqrt(h2 * G.ir_s2 + dt * dt * G.ir_t2);
+    const double e = exp(-d);
+    double g, fp;
+    if (G.nu_code == 0) {
+      g = e;
+      fp = -e;
+    } else if (G.nu_code == 1) {
+      g = (1.0 + d) * e;
+      fp = -d * e;
+    } else {
+      g = (1.0 + d + d * d * (1.0 / 3.0)) * e;
+      fp = -d * (1.0 + d) * e * (1.0 / 3.0);
+    }
+    const double C = G.sigma2 * g;
+    const double inv_d = d > 0.0 ? 1.0 / d : 0.0;
+    dC[0] = g;
+    dC[1] = 0.0;
+    dC[2] = G.sigma2 * fp * (-h2 * G.ir_s2 * G.inv_rs) * inv_d;
+    dC[3] = G.sigma2 * fp * (-dt * dt * G.ir_t2 * G.inv_rt) * inv_d;
+    return C;
+  }
+  const double adt = fabs(dt);
+  const double ldt = adt > 0.0 ? log(adt) : 0.0;
+  const double ta = adt > 0.0 ? exp(G.two_alpha * ldt) : 0.0;
+  const double psi = G.a * ta + 1.0;
+  const double lp = log(psi);
+  const double E = exp(-G.bg * lp);
+  const double lh2 = h2 > 0.0 ? log(h2) : 0.0;
+  const double g = h2 > 0.0 ? exp(G.gamma * lh2) : 0.0;
+  const double q = G.c * g * E;
+  const double C = G.sigma2 * exp(-G.tau * lp - q);
+  const double dlp = C * (-G.tau + G.bg * q) / psi;
+  dC[0] = C / G.sigma2;
+  dC[1] = 0.0;
+  dC[2] = dlp * ta;
+  dC[3] = -C * g * E;
+  dC[4] = dlp * G.a * ta * 2.0 * ldt;
+  dC[5] = C * q * G.gamma * lp;
+  dC[6] = -C * q * (lh2 - G.beta * lp);
+  dC[7] = -C * lp;
+  return C;
+}
+
+template <int QMAX>
+__global__ __launch_bounds__(256) void vecchia_grad_kernel(GradArgs A) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wave;
+  if (i >= A.n) return;  // whole wavefront; no workgroup barriers below
+  const int m = A.m, P = A.P;
+  const int r = lane;
+  // ---- conditioning set: valid neighbors are earlier points forming a prefix ----
+  int idx = -1;
+  if (r < m) idx = A.nbr[i * m + r];
+  const bool valid = r < m && idx >= 0 && (int64_t)idx < i;
+  const unsigned long long vb = __ballot(valid);
+  const unsigned long long mmask = m >= 64 ? ~0ull : ((1ull << m) - 1ull);
+  const int p = (int)__builtin_ctzll(~(vb & mmask));
+  const unsigned long long badb = __ballot(r < m && idx != -1 && !valid);
+  if (r == 0 && m > 0 && ((badb & mmask) != 0ull || ((vb & mmask) >> p) != 0ull))
+    flag_fail(A.bad_nbr, i);
+  const int q = p + 1;  // block size, i last
+  const int64_t row = r < p ? (int64_t)idx : i;  // lanes past the block: any valid row
+  const double xr = A.sx[row], yr = A.sy[row], tr = A.t[row];
+  const double yv = r < q ? A.y[row] : 0.0;
+  // ---- block Sigma~_SS, row r in registers (identity beyond q) ----
+  double a[QMAX];
+#pragma unroll
+  for (int s = 0; s < QMAX; ++s) {
+    const double xs = rdl(xr, s), ys = rdl(yr, s), ts = rdl(tr, s);
+    double c = cov_eval<double>(A.K, xr - xs, yr - ys, tr - ts);
+    if (r == s) c += A.nugget;
+    a[s] = (r < q && s < q) ? c : (r == s ? 1.0 : 0.0);
+  }
+  // ---- Cholesky, pivots and multipliers through readlane ----
+  bool okp = true;
+#pragma unroll
+  for (int kk = 0; kk < QMAX; ++kk) {
+    const double d = rdl(a[kk], kk);
+    const bool ok = d > 0.0 && d < INFINITY;
+    okp = okp && ok;
+    const double piv = ok ? sqrt(d) : 1.0;
+    const double lm = r > kk ? a[kk] / piv : 0.0;
+    if (r >= kk) a[kk] = r > kk ? lm : piv;
+#pragma unroll
+    for (int c = kk + 1; c < QMAX; ++c) a[c] -= lm * rdl(lm, c);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (r == 0 && !okp) flag_fail(A.fail, i);
+  // ---- u = L^-1 y (forward) ----
+  double u = 0.0, accf = 0.0;
+#pragma unroll
+  for (int k = 0; k < QMAX; ++k) {
+    const double val = (yv - accf) / a[k];
+    const double uk = rdl(val, k);
+    if (r == k) u = uk;
+    accf += r > k ? a[k] * uk : 0.0;
+  }
+  const double z = rdl(u, p);
+  // ---- v = last row of L^-1: L' v = e_p (backward, column sums by reduction) ----
+  double v = 0.0;
+#pragma unroll
+  for (int k = QMAX - 1; k >= 0; --k) {
+    if (k <= p) {
+      const double part = (r > k && r <= p) ? a[k] * v : 0.0;
+      const double sum = wave_sum(part);
+      const double lkk = rdl(a[k], k);
+      const double vk = ((k == p) ? 1.0 : 0.0) - sum;
+      if (r == k) v = vk / lkk;
+    }
+  }
+  // ---- alpha_N = L_N^-T u_N (backward over the first p rows) ----
+  double al = 0.0;
+#pragma unroll
+  for (int k = QMAX - 1; k >= 0; --k) {
+    if (k < p) {
+      const double part = (r > k && r < p) ? a[k] * al : 0.0;
+      const double sum = wave_sum(part);
+      const double lkk = rdl(a[k], k);
+      const double uk = rdl(u, k);
+      if (r == k) al = (uk - sum) / lkk;
+    }
+  }
+  // ---- derivative forms v' dS v and v' dS alpha_N ----
+  double t1[kGradMaxParams], t2[kGradMaxParams];
+#pragma unroll
+  for (int pp = 0; pp < kGradMaxParams; ++pp) t1[pp] = t2[pp] = 0.0;
+  for (int s = 0; s < q; ++s) {
+    const double xs = rdl(xr, s), ys = rdl(yr, s), ts = rdl(tr, s);
+    const double vs = rdl(v, s), as = rdl(al, s);
+    double dC[kGradMaxParams];
+    cov_and_grad(A.G, xr - xs, yr - ys, tr - ts, dC);
+    if (r < q) {
+      const double wv = v * vs, wa = v * as;
+#pragma unroll
+      for (int pp = 0; pp < kGradMaxParams; ++pp) {
+        t1[pp] += dC[pp] * wv;
+        t2[pp] += dC[pp] * wa;
+      }
+      if (r == s) {  // nugget: dSigma~ = I
+        t1[1] += wv;
+        t2[1] += wa;
+      }
+    }
+  }
+  // D_i = L_pp^2: log D_i = 2 log L_pp
+  double lpiv = 0.0;
+#pragma unroll
+  for (int k = 0; k < QMAX; ++k)
+    if (k == p) lpiv = rdl(a[k], k);
+  for (int pp = 0; pp < P; ++pp) {
+    const double s1 = wave_sum(t1[pp]);
+    const double s2 = wave_sum(t2[pp]);
+    if (r == 0) A.g[(int64_t)pp * A.n + i] = 0.5 * ((1.0 - z * z) * s1 - 2.0 * z * s2);
+  }
+  if (r == 0) {
+    A.logD[i] = 2.0 * log(lpiv);
+    A.z[i] = z;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_vecchia_grad(const GradArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)((a.n + 3) / 4));
+  if (a.m < 32)
+    hipLaunchKernelGGL(vecchia_grad_kernel<32>, grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(vecchia_grad_kernel<64>, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace vif

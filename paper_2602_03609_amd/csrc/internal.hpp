@@ -201,4 +201,26 @@ hipError_t launch_resid_var(int64_t n, int kpad, double sigma2, const double* U,
                             hipStream_t s);
 hipError_t launch_resid_topm(const ResidArgs& a, hipStream_t s);
 
+// Vecchia NLL gradient (gradient.hip).
+constexpr int kGradMaxParams = 8;
+struct GradKern {  // hyperparameters in the form the derivative code uses
+  int kind, nu_code;
+  double sigma2, a, c, two_alpha, beta, gamma, bg, tau, ir_s2, ir_t2, inv_rs, inv_rt;
+};
+struct GradArgs {
+  int64_t n;
+  int m, P;
+  KernDev K;
+  GradKern G;
+  double nugget;
+  const double *sx, *sy, *t, *y;
+  const int32_t* nbr;
+  double* g;     // [P, n] per-point gradient terms
+  double* logD;  // [n]
+  double* z;     // [n]
+  unsigned long long* fail;
+  unsigned long long* bad_nbr;
+};
+hipError_t launch_vecchia_grad(const GradArgs& a, hipStream_t s);
+
 }  // namespace vif

@@ -164,3 +164,21 @@ def test_residual_argument_errors():
     st = lib.vif_residual_neighbors(ctypes.byref(P), ctypes.byref(K), 5, None,
                                     ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), 16, None)
     assert st == L.VIF_E_WORKSPACE
+
+
+def test_gradient_argument_errors():
+    import paper_2602_03609_amd._lib as L
+    lib = L.load()
+    assert lib.vif_grad_params(1) == 8 and lib.vif_grad_params(3) == 4 and lib.vif_grad_params(2) == 0
+    assert lib.vif_grad_ws(0) == 0 and lib.vif_grad_ws(1000) > 0
+    K = L.make_kernel({"kind": 2, "sigma2": 1.0, "nugget": 0.1, "a": 0.5, "c": 20.0, "alpha": 0.4,
+                       "gamma": 0.4, "delta": 0.2, "nu": 1.5})
+    P = L.Points()
+    P.n = 10
+    P.sx = P.sy = P.t = ctypes.c_void_p(0x1000)
+    out = ctypes.c_double()
+    g = (ctypes.c_double * 8)()
+    st = lib.vif_nll_grad(ctypes.byref(P), ctypes.c_void_p(0x1000), ctypes.byref(K), 5,
+                          ctypes.c_void_p(0x1000), ctypes.byref(out), g, ctypes.c_void_p(0x1000),
+                          1 << 20, None)
+    assert st == L.VIF_E_UNSUPPORTED
