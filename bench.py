@@ -10,7 +10,7 @@ points, Gneiting kernel. Inputs are resident in HBM before the timed region.
 
 Prints ONE JSON line on stdout (progress goes to stderr).
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--prec bf16x6]
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--prec bf16x3]
 """
 from __future__ import annotations
 
@@ -41,7 +41,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--prec", default="bf16x6", choices=list(PREC_ES))
+    ap.add_argument("--prec", default="bf16x3", choices=list(PREC_ES),
+                    help="precision of the timed line (default: split-BF16 with three products, "
+                         "the mixed-precision configuration of the continental workload)")
+    ap.add_argument("--no-other-precisions", action="store_true",
+                    help="skip the short timing of the other precisions")
     ap.add_argument("--stations", type=int, default=3340)
     ap.add_argument("--days", type=int, default=365)
     ap.add_argument("--k", type=int, default=1000)
@@ -588,6 +592,24 @@ def main():
         "stages": stages,
         "roofline": roof,
     }
+    if not args.no_other_precisions:
+        # The same step in the other precisions (a few steps each, same inputs and
+        # neighbor sets), with each one's NLL error against FP64.
+        others = {}
+        for pr in ("bf16x6", "fp32", "bf16x3"):
+            if pr == args.prec:
+                continue
+            step(pr)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            for _ in range(3):
+                v = step(pr)
+            torch.cuda.synchronize()
+            msp = (time.perf_counter() - ta) * 1000.0 / 3
+            others[pr] = {"ms_per_step": msp, "steps_per_s": 1000.0 / msp, "nll": v,
+                          "nll_rel_err_vs_fp64": abs(v - nll64) / abs(nll64) if nll64 is not None else None}
+            log(f"{pr}: {msp:.2f} ms/step, nll rel err {others[pr]['nll_rel_err_vs_fp64']}")
+        out["other_precisions"] = others
     if args.learned:
         torch.cuda.synchronize()
         ts = []
