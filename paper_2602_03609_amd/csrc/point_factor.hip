@@ -234,7 +234,11 @@ struct GroupShape {
   static constexpr int NW0 = (int)(65536 / (PPW * ROWS * ROWS * sizeof(T)));
   static constexpr int NW1 = NW0 > 8 ? 8 : NW0;
   // At most 16 points: the W product runs the group as the 16 rows of an MFMA tile.
-  static constexpr int NW = NW1 * PPW > 16 ? 16 / PPW : NW1;  // wavefronts per workgroup
+  // At 32 rows per point, 8 points (4 wavefronts) per workgroup keep the LDS under
+  // 80 KB, so two workgroups share a CU and one's Gram or W pass overlaps the
+  // other's per-point phase (measured faster than 16 points in one workgroup,
+  // despite the larger unions).
+  static constexpr int NW = ROWS == 32 ? 4 : (NW1 * PPW > 16 ? 16 / PPW : NW1);  // wavefronts per workgroup
   static constexpr int GP = NW * PPW;            // points per workgroup
   static constexpr int NSLOT = GP * ROWS;        // conditioning rows (union upper bound)
 };
