@@ -352,7 +352,7 @@ def kernel_name(stage, prec, m):
         return f"syrk_split_kernel<{3 if c == 3 else 2}>" if c >= 2 else f"syrk_kernel<{c}>"
     if stage == "trmm":
         if c >= 2:
-            return f"lowrank_u_kernel<{3 if c == 3 else 2}>"
+            return "lowrank_u_kernel<3, 8>" if c == 3 else "lowrank_u_kernel<2, 4>"
         return "trmm_f64_kernel" if c == 0 else "trmm_f32_kernel<false>"
     if stage == "crosscov":
         return f"crosscov_kernel<{'double' if c == 0 else 'float'}>"

@@ -517,7 +517,7 @@ __device__ __forceinline__ void fill_c_planes(const LowRankArgs& A, int64_t i0, 
                                               int lbeg, int ncol, __bf16* C0, int pst, int ldc) {
   const int tid = threadIdx.x;
   const int ncg = ncol / 8;  // column groups
-  for (int task = tid; task < ncg * (URB / 8); task += 512) {
+  for (int task = tid; task < ncg * (URB / 8); task += (int)blockDim.x) {
     const int cg = task % ncg, rg = task / ncg;
     double zx[8], zy[8], zt[8];
 #pragma unroll
@@ -997,10 +997,10 @@ hipError_t launch_crosscov(const LowRankArgs& a, void* U, int prec, hipStream_t 
 // Output columns j < kpad / 2 need only the first half: they are finished and
 // written in the first phase. The upper columns keep their accumulators in
 // registers across the phases and are written after the second.
-constexpr int U6_MAXHI = 4;  // upper 32-column blocks per wave: kpad <= 2 * 8 * 32 * 4
+constexpr int U6_MAXHI = 4;  // upper 32-column blocks per wave: kpad <= 2 * NWV * 32 * 4
 
-template <int NS>
-__global__ __launch_bounds__(512) void lowrank_u_kernel(LowRankArgs A, const __bf16* __restrict__ Pb,
+template <int NS, int NWV>
+__global__ __launch_bounds__(64 * NWV) void lowrank_u_kernel(LowRankArgs A, const __bf16* __restrict__ Pb,
                                                         float* __restrict__ U) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int kpad = A.kpad;
@@ -1084,8 +1084,8 @@ __global__ __launch_bounds__(512) void lowrank_u_kernel(LowRankArgs A, const __b
   stage_rows(A, i0, sRow);
   fill_c_planes<NS>(A, i0, sRow, 0, kh, C0, pst, ldc);
   __syncthreads();
-  for (int pass = 0; pass * 8 < nlo; ++pass) {  // lower blocks, snake order for balance
-    const int pb = pass * 8 + ((pass & 1) ? 7 - wave : wave);
+  for (int pass = 0; pass * NWV < nlo; ++pass) {  // lower blocks, snake order for balance
+    const int pb = pass * NWV + ((pass & 1) ? NWV - 1 - wave : wave);
     if (pb >= nlo) continue;
     f4v acc[2][2];
 #pragma unroll
@@ -1098,7 +1098,7 @@ __global__ __launch_bounds__(512) void lowrank_u_kernel(LowRankArgs A, const __b
   for (int q = 0; q < U6_MAXHI; ++q) {
 #pragma unroll
     for (int r = 0; r < 2; ++r) hi[q][r][0] = hi[q][r][1] = f4v{0.f, 0.f, 0.f, 0.f};
-    const int hb = q * 8 + ((q & 1) ? 7 - wave : wave);
+    const int hb = q * NWV + ((q & 1) ? NWV - 1 - wave : wave);
     if (hb < nlo) contract(nlo + hb, 0, 0, kh, hi[q]);
   }
   __syncthreads();  // every read of the first half is done
@@ -1108,7 +1108,7 @@ __global__ __launch_bounds__(512) void lowrank_u_kernel(LowRankArgs A, const __b
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < U6_MAXHI; ++q) {
-    const int hb = q * 8 + ((q & 1) ? 7 - wave : wave);
+    const int hb = q * NWV + ((q & 1) ? NWV - 1 - wave : wave);
     if (hb >= nlo) continue;
     const int pb = nlo + hb;
     contract(pb, kh, kh, pb * 32 + 32, hi[q]);
@@ -1121,7 +1121,7 @@ size_t lowrank_fused_lds(int kpad, int prec) {
 }
 
 bool lowrank_fused_ok(int kpad, int prec) {
-  if (kpad > 2 * 8 * 32 * U6_MAXHI) return false;
+  if (kpad > 2 * 8 * 32 * U6_MAXHI) return false;  // the eight-wavefront launch
   return lowrank_fused_lds(kpad, prec) + 3 * URB * sizeof(double) <= 160 * 1024;
 }
 
@@ -1133,10 +1133,13 @@ hipError_t prepare_lowrank_fused() {
   if (e != hipSuccess) return e;
   if (dev >= 0 && dev < 64 && attr_dev[dev].load(std::memory_order_acquire)) return hipSuccess;
   const int dyn = 160 * 1024 - 3 * URB * (int)sizeof(double);  // beside the static row stage
-  e = hipFuncSetAttribute((const void*)lowrank_u_kernel<2>,
+  e = hipFuncSetAttribute((const void*)lowrank_u_kernel<2, 4>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)lowrank_u_kernel<3>,
+    e = hipFuncSetAttribute((const void*)lowrank_u_kernel<2, 8>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)lowrank_u_kernel<3, 8>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
   if (e == hipSuccess && dev >= 0 && dev < 64) attr_dev[dev].store(1, std::memory_order_release);
   return e;
@@ -1153,10 +1156,15 @@ hipError_t launch_lowrank_fused(const LowRankArgs& a, const double* P, void* Pb,
   const unsigned grid = (unsigned)((a.n + URB - 1) / URB);
   if (prec == 3) {
     hipLaunchKernelGGL(split_p_kernel<3>, gs, dim3(256), 0, s, kk, a.kpad, P, Ph);
-    hipLaunchKernelGGL(lowrank_u_kernel<3>, dim3(grid), dim3(512), lds, s, a, (const __bf16*)Ph, U);
+    hipLaunchKernelGGL((lowrank_u_kernel<3, 8>), dim3(grid), dim3(512), lds, s, a, (const __bf16*)Ph, U);
   } else {
     hipLaunchKernelGGL(split_p_kernel<2>, gs, dim3(256), 0, s, kk, a.kpad, P, Ph);
-    hipLaunchKernelGGL(lowrank_u_kernel<2>, dim3(grid), dim3(512), lds, s, a, (const __bf16*)Ph, U);
+    // Two terms: 67 KB of LDS, so with four wavefronts per workgroup two
+    // workgroups share a CU (their evaluation and product phases overlap).
+    if (a.kpad <= 2 * 4 * 32 * U6_MAXHI)
+      hipLaunchKernelGGL((lowrank_u_kernel<2, 4>), dim3(grid), dim3(256), lds, s, a, (const __bf16*)Ph, U);
+    else
+      hipLaunchKernelGGL((lowrank_u_kernel<2, 8>), dim3(grid), dim3(512), lds, s, a, (const __bf16*)Ph, U);
   }
   return hipGetLastError();
 }
