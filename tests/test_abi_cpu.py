@@ -182,3 +182,11 @@ def test_gradient_argument_errors():
                           ctypes.c_void_p(0x1000), ctypes.byref(out), g, ctypes.c_void_p(0x1000),
                           1 << 20, None)
     assert st == L.VIF_E_UNSUPPORTED
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU only" in r.stderr
