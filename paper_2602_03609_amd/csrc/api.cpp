@@ -181,6 +181,8 @@ Layout make_residual_layout(int64_t n, int k) {
   Layout L = make_layout(n, 0, k, VIF_PREC_FP64, VIF_OP_FACTOR);
   L.logD = L.total;  // residual variances r(j, j)
   L.total += align256(sizeof(double) * (size_t)n);
+  L.tab1 = L.total;  // per-lag factors of the Gneiting kernel
+  L.total += align256(sizeof(double) * 2 * VIF_MAX_LAGS);
   return L;
 }
 
@@ -1089,7 +1091,27 @@ int32_t vif_residual_neighbors(const vif_points* p, const vif_kernel* kern, int3
     U = reinterpret_cast<const double*>(ws + L.U);
   }
   HIPCHK(vif::launch_resid_var(p->n, L.kpad, kern->sigma2, U, d, s));
+  // Gneiting kernel with integer times: per-lag factors in a table.
+  const double* lagtab = nullptr;
+  if (kern->kind == VIF_KERNEL_GNEITING) {
+    Flags* dflags = reinterpret_cast<Flags*>(ws + L.flags);
+    HIPCHK(vif::launch_validate_times(p->n, p->t, &dflags->tflag, s));
+    Flags f;
+    double tt[2];
+    HIPCHK(hipMemcpyAsync(&f, ws + L.flags, sizeof(f), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&tt[0], p->t, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&tt[1], p->t + (p->n - 1), sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (f.tflag & 1u) return fail(VIF_E_ARG, "times must be finite");
+    const double span = tt[1] - tt[0];
+    if (!(f.tflag & 6u) && span >= 0 && span < (double)VIF_MAX_LAGS) {
+      double* tab = reinterpret_cast<double*>(ws + L.tab1);
+      HIPCHK(vif::launch_resid_lags(to_dev(kern), (int)span + 1, tab, s));
+      lagtab = tab;
+    }
+  }
   vif::ResidArgs a{};
+  a.lagtab = lagtab;
   a.n = p->n;
   a.m = m;
   a.kpad = L.kpad;

@@ -194,8 +194,11 @@ struct ResidArgs {
   const double *sx, *sy, *t;
   const double* U;  // [n, kpad] FP64 (NULL when kpad = 0)
   const double* d;  // residual variances [n]
+  const double* lagtab;  // GNEITING with integer times: (A, e) per lag (gneiting_lag), else NULL
   int32_t* nbr;     // [n, m]
 };
+// tab[2 l], tab[2 l + 1] = gneiting_lag(K, l) for l < nlag.
+hipError_t launch_resid_lags(const KernDev& K, int nlag, double* tab, hipStream_t s);
 // d[i] = sigma2 - |U_i|^2.
 hipError_t launch_resid_var(int64_t n, int kpad, double sigma2, const double* U, double* d,
                             hipStream_t s);

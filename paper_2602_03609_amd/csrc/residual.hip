@@ -16,7 +16,12 @@
 // then one lane per query merges the 64 candidates into its sorted list in LDS
 // (a candidate enters only if it beats the m-th key; blocks and columns are
 // visited in increasing index, so ties keep the earlier index). Workgroups are
-// launched heaviest (last) block first.
+// launched heaviest (last) block first. The global loads of the next K stage
+// are issued before the current stage's products. For the Gneiting kernel with
+// integer times the factors that depend on the time lag alone come from a
+// table per lag (gneiting_lag), and each entry costs one exponential
+// (gneiting_pair performs the same operations as cov_eval, so the values are
+// the same).
 #include <math.h>
 
 #include "internal.hpp"
@@ -28,6 +33,15 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 
 constexpr int RB = 64;    // queries per workgroup and candidates per tile
 constexpr int RBK = 16;   // K per LDS stage
+
+__global__ __launch_bounds__(256) void resid_lag_kernel(KernDev K, int nlag, double* __restrict__ tab) {
+  const int l = blockIdx.x * 256 + threadIdx.x;
+  if (l >= nlag) return;
+  double a, e;
+  gneiting_lag<double>(K, (double)l, a, e);
+  tab[2 * l] = a;
+  tab[2 * l + 1] = e;
+}
 
 __global__ __launch_bounds__(256) void resid_var_kernel(int64_t n, int kpad, double sigma2,
                                                         const double* __restrict__ U,
@@ -71,24 +85,27 @@ __global__ __launch_bounds__(256) void resid_topm_kernel(ResidArgs A) {
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b) acc[a][b] = d4v{0.0, 0.0, 0.0, 0.0};
+    // Stage k0's slice of U_I and U_J: 16 doubles per row, four per thread.
+    double2 u0 = {0.0, 0.0}, u1 = {0.0, 0.0}, v0 = {0.0, 0.0}, v1 = {0.0, 0.0};
+    auto fetch = [&](int k0) __attribute__((always_inline)) {
+      if (I0 + lr < A.n) {
+        const double2* src = reinterpret_cast<const double2*>(A.U + (I0 + lr) * A.kpad + k0 + lq);
+        u0 = src[0];
+        u1 = src[1];
+      }
+      if (J0 + lr < A.n) {
+        const double2* src = reinterpret_cast<const double2*>(A.U + (J0 + lr) * A.kpad + k0 + lq);
+        v0 = src[0];
+        v1 = src[1];
+      }
+    };
+    if (A.kpad > 0) fetch(0);
     for (int k0 = 0; k0 < A.kpad; k0 += RBK) {
       __syncthreads();
-      {
-        double2 u0 = {0.0, 0.0}, u1 = {0.0, 0.0}, v0 = {0.0, 0.0}, v1 = {0.0, 0.0};
-        if (I0 + lr < A.n) {
-          const double2* src = reinterpret_cast<const double2*>(A.U + (I0 + lr) * A.kpad + k0 + lq);
-          u0 = src[0];
-          u1 = src[1];
-        }
-        if (J0 + lr < A.n) {
-          const double2* src = reinterpret_cast<const double2*>(A.U + (J0 + lr) * A.kpad + k0 + lq);
-          v0 = src[0];
-          v1 = src[1];
-        }
-        As[lr][lq] = u0.x; As[lr][lq + 1] = u0.y; As[lr][lq + 2] = u1.x; As[lr][lq + 3] = u1.y;
-        Bs[lr][lq] = v0.x; Bs[lr][lq + 1] = v0.y; Bs[lr][lq + 2] = v1.x; Bs[lr][lq + 3] = v1.y;
-      }
+      As[lr][lq] = u0.x; As[lr][lq + 1] = u0.y; As[lr][lq + 2] = u1.x; As[lr][lq + 3] = u1.y;
+      Bs[lr][lq] = v0.x; Bs[lr][lq + 1] = v0.y; Bs[lr][lq + 2] = v1.x; Bs[lr][lq + 3] = v1.y;
       __syncthreads();
+      if (k0 + RBK < A.kpad) fetch(k0 + RBK);  // in flight during the products
 #pragma unroll
       for (int ks = 0; ks < RBK / 4; ++ks) {
         const int kk = ks * 4 + (lane >> 4);
@@ -120,7 +137,15 @@ __global__ __launch_bounds__(256) void resid_topm_kernel(ResidArgs A) {
           const int64_t i = I0 + row;
           double key = -INFINITY;  // not a candidate
           if (i < A.n && j < i) {
-            const double c = cov_eval<double>(A.K, A.sx[i] - xj, A.sy[i] - yj, A.t[i] - tj);
+            const double ti = A.t[i];
+            double c;
+            if (A.lagtab) {
+              const int lag = (int)fabs(ti - tj);
+              c = gneiting_pair<double>(A.K, A.sx[i] - xj, A.sy[i] - yj, A.lagtab[2 * lag],
+                                        A.lagtab[2 * lag + 1]);
+            } else {
+              c = cov_eval<double>(A.K, A.sx[i] - xj, A.sy[i] - yj, ti - tj);
+            }
             const double r = c - acc[a][b][e];
             key = dj > 0.0 ? r * r / dj : -1.0;
           }
@@ -161,6 +186,12 @@ hipError_t launch_resid_var(int64_t n, int kpad, double sigma2, const double* U,
                             hipStream_t s) {
   hipLaunchKernelGGL(resid_var_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, kpad,
                      sigma2, U, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_resid_lags(const KernDev& K, int nlag, double* tab, hipStream_t s) {
+  hipLaunchKernelGGL(resid_lag_kernel, dim3((unsigned)((nlag + 255) / 256)), dim3(256), 0, s, K,
+                     nlag, tab);
   return hipGetLastError();
 }
 
