@@ -965,7 +965,7 @@ int32_t vif_propose_neighbors(const vif_points* p, const vif_kernel* kern, int32
 namespace {
 
 struct GradLayout {
-  size_t flags, g, logD, z, part, sums, total;
+  size_t flags, g, logD, z, part, sums, tab, total;
 };
 
 GradLayout make_grad_layout(int64_t n) {
@@ -982,6 +982,7 @@ GradLayout make_grad_layout(int64_t n) {
   L.z = take(sizeof(double) * (size_t)n);
   L.part = take(sizeof(double) * 256);
   L.sums = take(sizeof(double) * (vif::kGradMaxParams + 2));
+  L.tab = take(sizeof(double) * vif::kGradLagVals * VIF_MAX_LAGS);
   L.total = off;
   return L;
 }
@@ -1046,6 +1047,25 @@ int32_t vif_nll_grad(const vif_points* p, const double* y, const vif_kernel* ker
   a.z = reinterpret_cast<double*>(ws + L.z);
   a.fail = fl;
   a.bad_nbr = fl + 3;
+  a.lagtab = nullptr;
+  if (kern->kind == VIF_KERNEL_GNEITING) {
+    // Integer, nondecreasing times: the lag-only factors from a table.
+    Flags* dflags = reinterpret_cast<Flags*>(ws + L.flags);
+    HIPCHK(vif::launch_validate_times(p->n, p->t, &dflags->tflag, s));
+    Flags f0;
+    double tt[2];
+    HIPCHK(hipMemcpyAsync(&f0, ws + L.flags, sizeof(f0), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&tt[0], p->t, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&tt[1], p->t + (p->n - 1), sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (f0.tflag & 1u) return fail(VIF_E_ARG, "times must be finite");
+    const double span = tt[1] - tt[0];
+    if (!(f0.tflag & 6u) && span >= 0 && span < (double)VIF_MAX_LAGS) {
+      double* tab = reinterpret_cast<double*>(ws + L.tab);
+      HIPCHK(vif::launch_grad_lags(a.G, (int)span + 1, tab, s));
+      a.lagtab = tab;
+    }
+  }
   HIPCHK(vif::launch_vecchia_grad(a, s));
   double* sums = reinterpret_cast<double*>(ws + L.sums);
   double* part = reinterpret_cast<double*>(ws + L.part);

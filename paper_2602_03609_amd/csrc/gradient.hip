@@ -19,7 +19,10 @@
 // derivative matrices are never formed: the lower pairs are spread over the
 // lanes again, each evaluating dC for every parameter and accumulating its
 // share of v' dC v and v' dC alpha_N. Per-point results go to parameter-major
-// arrays summed later in a fixed order (deterministic).
+// arrays summed later in a fixed order (deterministic). For the Gneiting kernel
+// with integer times, the quantities that depend on the time lag alone come
+// from a per-lag table (computed with the same operations), leaving one
+// logarithm and one or two exponentials per pair.
 #include <math.h>
 
 #include "internal.hpp"
@@ -98,6 +101,49 @@ __device__ __forceinline__ void pair_of(int e, int& r, int& s) {
   s = e - r * (r + 1) / 2;
 }
 
+// Per-lag quantities of the Gneiting kernel: A = -tau log psi, e = psi^(-beta gamma),
+// |dt|^(2 alpha), psi, log psi, log |dt|.
+constexpr int kLagVals = kGradLagVals;
+
+__global__ __launch_bounds__(256) void grad_lag_kernel(GradKern G, int nlag, double* __restrict__ tab) {
+  const int l = blockIdx.x * 256 + threadIdx.x;
+  if (l >= nlag) return;
+  const double adt = (double)l;
+  const double ldt = adt > 0.0 ? log(adt) : 0.0;
+  const double ta = adt > 0.0 ? exp(G.two_alpha * ldt) : 0.0;
+  const double psi = G.a * ta + 1.0;
+  const double lp = log(psi);
+  double* o = tab + (int64_t)kLagVals * l;
+  o[0] = -G.tau * lp;
+  o[1] = exp(-G.bg * lp);
+  o[2] = ta;
+  o[3] = psi;
+  o[4] = lp;
+  o[5] = ldt;
+}
+
+// cov_and_grad for the Gneiting kernel from a lag-table row (same operations).
+__device__ __forceinline__ double cov_and_grad_lag(const GradKern& G, double dx, double dy,
+                                                   const double* __restrict__ lt,
+                                                   double dC[kGradMaxParams]) {
+  const double h2 = dx * dx + dy * dy;
+  const double ta = lt[2], psi = lt[3], lp = lt[4], ldt = lt[5], E = lt[1];
+  const double lh2 = h2 > 0.0 ? log(h2) : 0.0;
+  const double g = h2 > 0.0 ? exp(G.gamma * lh2) : 0.0;
+  const double q = G.c * g * E;
+  const double C = G.sigma2 * exp(-G.tau * lp - q);
+  const double dlp = C * (-G.tau + G.bg * q) / psi;
+  dC[0] = C / G.sigma2;
+  dC[1] = 0.0;
+  dC[2] = dlp * ta;
+  dC[3] = -C * g * E;
+  dC[4] = dlp * G.a * ta * 2.0 * ldt;
+  dC[5] = C * q * G.gamma * lp;
+  dC[6] = -C * q * (lh2 - G.beta * lp);
+  dC[7] = -C * lp;
+  return C;
+}
+
 template <int QMAX>
 struct GradLds {
   double x[64], y[64], t[64], v[64], al[64];
@@ -140,7 +186,13 @@ __global__ __launch_bounds__(256) void vecchia_grad_kernel(GradArgs A) {
   for (int e = r; e < npair; e += 64) {
     int rr, ss;
     pair_of(e, rr, ss);
-    double c = cov_eval<double>(A.K, sx_[rr] - sx_[ss], sy_[rr] - sy_[ss], st_[rr] - st_[ss]);
+    double c;
+    if (A.lagtab) {
+      const double* lt = A.lagtab + (int64_t)kLagVals * (int)fabs(st_[rr] - st_[ss]);
+      c = gneiting_pair<double>(A.K, sx_[rr] - sx_[ss], sy_[rr] - sy_[ss], lt[0], lt[1]);
+    } else {
+      c = cov_eval<double>(A.K, sx_[rr] - sx_[ss], sy_[rr] - sy_[ss], st_[rr] - st_[ss]);
+    }
     if (rr == ss) c += A.nugget;
     blk[rr][ss] = c;
   }
@@ -211,7 +263,11 @@ __global__ __launch_bounds__(256) void vecchia_grad_kernel(GradArgs A) {
     const double vr = sw[wave].v[rr], vs = sw[wave].v[ss];
     const double ar = sw[wave].al[rr], as = sw[wave].al[ss];
     double dC[kGradMaxParams];
-    cov_and_grad(A.G, sx_[rr] - sx_[ss], sy_[rr] - sy_[ss], st_[rr] - st_[ss], dC);
+    if (A.lagtab)
+      cov_and_grad_lag(A.G, sx_[rr] - sx_[ss], sy_[rr] - sy_[ss],
+                       A.lagtab + (int64_t)kLagVals * (int)fabs(st_[rr] - st_[ss]), dC);
+    else
+      cov_and_grad(A.G, sx_[rr] - sx_[ss], sy_[rr] - sy_[ss], st_[rr] - st_[ss], dC);
     const bool diag = rr == ss;
     const double wv = diag ? vr * vs : 2.0 * vr * vs;
     const double wa = diag ? vr * as : vr * as + vs * ar;
@@ -242,6 +298,12 @@ __global__ __launch_bounds__(256) void vecchia_grad_kernel(GradArgs A) {
 }
 
 }  // namespace
+
+hipError_t launch_grad_lags(const GradKern& G, int nlag, double* tab, hipStream_t s) {
+  hipLaunchKernelGGL(grad_lag_kernel, dim3((unsigned)((nlag + 255) / 256)), dim3(256), 0, s, G,
+                     nlag, tab);
+  return hipGetLastError();
+}
 
 hipError_t launch_vecchia_grad(const GradArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)((a.n + 3) / 4));

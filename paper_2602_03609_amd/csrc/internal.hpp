@@ -221,9 +221,13 @@ struct GradArgs {
   double* g;     // [P, n] per-point gradient terms
   double* logD;  // [n]
   double* z;     // [n]
+  const double* lagtab;  // GNEITING with integer times: launch_grad_lags table, else NULL
   unsigned long long* fail;
   unsigned long long* bad_nbr;
 };
+// Six values per lag l < nlag (see gradient.hip) for the Gneiting kernel.
+constexpr int kGradLagVals = 6;
+hipError_t launch_grad_lags(const GradKern& G, int nlag, double* tab, hipStream_t s);
 hipError_t launch_vecchia_grad(const GradArgs& a, hipStream_t s);
 
 }  // namespace vif
