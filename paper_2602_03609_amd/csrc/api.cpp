@@ -1469,19 +1469,23 @@ int32_t vif_batch_autotune(vif_batch* b, void* ws, size_t ws_bytes, double* nll,
   HIPCHK(hipEventCreate(&ev.e1));
   hipEvent_t e0 = ev.e0, e1 = ev.e1;
   double best = INFINITY;
-  int bs = b->streams, bc = b->chunk_rows;
-  for (int a = 0; a < 3; ++a) {
-    for (int c = 0; c < nchunk_cand; ++c) {
+  const int s0 = b->streams, c0 = b->chunk_rows;  // restored if a candidate fails
+  int bs = s0, bc = c0;
+  auto dev_err = [&](hipError_t e) {
+    return e == hipSuccess ? VIF_OK : fail(VIF_E_DEVICE, "autotune: %s", hipGetErrorString(e));
+  };
+  for (int a = 0; a < 3 && !st; ++a) {
+    for (int c = 0; c < nchunk_cand && !st; ++c) {
       b->streams = cand_streams[a];
       b->chunk_rows = nchunk_cand == 2 ? cand_chunk[c] : 4096;
       if ((st = vif_batch_graph_launch(b, ws, ws_bytes, nll, hip_stream))) break;  // warm-up
-      HIPCHK(hipEventRecord(e0, s));
+      if ((st = dev_err(hipEventRecord(e0, s)))) break;
       for (int r = 0; r < reps && !st; ++r) st = vif_batch_graph_launch(b, ws, ws_bytes, nll, hip_stream);
       if (st) break;
-      HIPCHK(hipEventRecord(e1, s));
-      HIPCHK(hipEventSynchronize(e1));
       float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if ((st = dev_err(hipEventRecord(e1, s))) || (st = dev_err(hipEventSynchronize(e1))) ||
+          (st = dev_err(hipEventElapsedTime(&ms, e0, e1))))
+        break;
       const double per = ms / reps;
       if (per < best) {
         best = per;
@@ -1489,10 +1493,9 @@ int32_t vif_batch_autotune(vif_batch* b, void* ws, size_t ws_bytes, double* nll,
         bc = b->chunk_rows;
       }
     }
-    if (st) break;
   }
-  b->streams = bs;
-  b->chunk_rows = bc;
+  b->streams = st ? s0 : bs;
+  b->chunk_rows = st ? c0 : bc;
   drop_graph(b);
   if (st) return st;
   if (best_ms) *best_ms = best;

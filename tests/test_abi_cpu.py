@@ -155,11 +155,12 @@ def test_residual_argument_errors():
     P = L.Points()
     P.n = 10
     P.sx = P.sy = P.t = ctypes.c_void_p(0x1000)
+    big = lib.vif_residual_ws(10, 0)
     st = lib.vif_residual_neighbors(ctypes.byref(P), ctypes.byref(K), 0, None,
-                                    ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), 1 << 20, None)
+                                    ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), big, None)
     assert st == L.VIF_E_ARG and b"m must be" in lib.vif_last_error()
     st = lib.vif_residual_neighbors(ctypes.byref(P), ctypes.byref(K), 5, None, None,
-                                    ctypes.c_void_p(0x1000), 1 << 20, None)
+                                    ctypes.c_void_p(0x1000), big, None)
     assert st == L.VIF_E_ARG and b"nbr" in lib.vif_last_error()
     st = lib.vif_residual_neighbors(ctypes.byref(P), ctypes.byref(K), 5, None,
                                     ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), 16, None)
@@ -180,7 +181,7 @@ def test_gradient_argument_errors():
     g = (ctypes.c_double * 8)()
     st = lib.vif_nll_grad(ctypes.byref(P), ctypes.c_void_p(0x1000), ctypes.byref(K), 5,
                           ctypes.c_void_p(0x1000), ctypes.byref(out), g, ctypes.c_void_p(0x1000),
-                          1 << 20, None)
+                          lib.vif_grad_ws(10), None)
     assert st == L.VIF_E_UNSUPPORTED
 
 
