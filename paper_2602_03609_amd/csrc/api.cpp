@@ -94,6 +94,7 @@ int kpad_of(int k) { return k > 0 ? ((k + 1 + 63) / 64) * 64 : 0; }
 struct Layout {
   size_t c2 = 0, f2 = 0, b2 = 0, k2 = 0, px2 = 0, py2 = 0, pi2 = 0, pflag = 0, plist = 0,
          pcount = 0, pemb = 0;  // proposal search
+  size_t lag = 0;  // per-lag Gneiting factors (VIF per-point kernel)
   size_t flags = 0, out = 0, part = 0, sums = 0, logD = 0, z = 0, Sk = 0, P = 0, Pb = 0, U = 0, W = 0,
          syrk = 0, M = 0, q = 0, dscr = 0, tab1 = 0, tab2 = 0, bnd = 0, bbox = 0, counts = 0,
          fill = 0, bsum = 0, key = 0, px = 0, py = 0, pidx = 0, total = 0;
@@ -154,6 +155,7 @@ Layout make_layout(int64_t n, int m, int k, int prec, int op, int chunk_rows = 4
     L.P = take(sizeof(double) * kk);
     if (prec >= VIF_PREC_BF16X3) L.Pb = take((prec == VIF_PREC_BF16X6 ? 6 : 4) * kk);
     L.dscr = take(std::max(sizeof(double) * 64 * 64, vif::trinv_scratch_bytes(L.kpad)));
+    L.lag = take(sizeof(double) * 2 * VIF_MAX_LAGS);
     L.U = take(es * (size_t)n * L.kpad);
     if (op == VIF_OP_NLL) {
       if (prec >= VIF_PREC_BF16X3) {
@@ -332,7 +334,7 @@ int32_t report_flags(const Flags& f) {
 // then by the Z order of a fine spatial grid, so that consecutive points (and
 // the workgroups one XCD runs together) share most of their neighbors' U rows.
 int32_t build_order(const vif_points* p, char* ws, const Layout& L, hipStream_t s,
-                    const int32_t** ord) {
+                    const int32_t** ord, int* nlag) {
   Flags* dflags = reinterpret_cast<Flags*>(ws + L.flags);
   double* bbox = reinterpret_cast<double*>(ws + L.bbox);
   HIPCHK(vif::launch_validate_times(p->n, p->t, &dflags->tflag, s));
@@ -352,6 +354,7 @@ int32_t build_order(const vif_points* p, char* ws, const Layout& L, hipStream_t 
   int nslab = 1;
   const double span = tt[1] - tt[0];
   if (!(f.tflag & 6u) && span >= 0 && span < (double)VIF_MAX_LAGS) nslab = (int)span + 1;
+  *nlag = (!(f.tflag & 6u) && span >= 0 && span < (double)VIF_MAX_LAGS) ? nslab : 0;
   const double per = (double)p->n / nslab;
   int bits = 0;
   while (bits < 10 && (double)(1 << (2 * (bits + 1))) * 3.0 <= per &&
@@ -458,7 +461,12 @@ int32_t nll_impl(const vif_points* p, const double* y, const vif_kernel* kern, i
   fa.fail = fl;
   fa.bad_nbr = fl + 3;
   if (k > 0) {
-    if ((st = build_order(p, ws, L, s, &fa.ord))) return st;
+    int nlag = 0;
+    if ((st = build_order(p, ws, L, s, &fa.ord, &nlag))) return st;
+    if (kern->kind == VIF_KERNEL_GNEITING && nlag > 0) {
+      HIPCHK(vif::launch_lag_table(to_dev(kern), nlag, prec, ws + L.lag, s));
+      fa.lagtab = ws + L.lag;
+    }
     if ((st = run_lowrank(p, ind, kern, prec, ws, L, s))) return st;
     fa.U = ws + L.U;
     fa.W = ws + L.W;
@@ -748,7 +756,12 @@ int32_t vif_factor(const vif_points* p, const vif_kernel* kern, int32_t m, const
   fa.fail = fl;
   fa.bad_nbr = fl + 3;
   if (k > 0) {
-    if ((st = build_order(p, ws, L, s, &fa.ord))) return st;
+    int nlag = 0;
+    if ((st = build_order(p, ws, L, s, &fa.ord, &nlag))) return st;
+    if (kern->kind == VIF_KERNEL_GNEITING && nlag > 0) {
+      HIPCHK(vif::launch_lag_table(to_dev(kern), nlag, prec, ws + L.lag, s));
+      fa.lagtab = ws + L.lag;
+    }
     if ((st = run_lowrank(p, ind, kern, prec, ws, L, s))) return st;
     fa.U = ws + L.U;
   }
@@ -1164,6 +1177,7 @@ struct ProbPlan {
   size_t off = 0;
   vif::GridArgs og{};  // processing-order grid (k > 0)
   double t0 = 0.0;
+  int nlag = 0;  // > 0: integer, sorted times spanning nlag lags (Gneiting lag table)
 };
 
 constexpr int kBatchMaxStreams = 4;
@@ -1229,6 +1243,10 @@ int32_t enqueue_problem(const ProbPlan& P, int prec, int chunk_rows, char* wsb, 
                                   reinterpret_cast<int32_t*>(ws + L.key), nullptr, nullptr,
                                   reinterpret_cast<int32_t*>(ws + L.pidx), s));
     fa.ord = reinterpret_cast<const int32_t*>(ws + L.pidx);
+    if (P.kern.kind == VIF_KERNEL_GNEITING && P.nlag > 0) {
+      HIPCHK(vif::launch_lag_table(to_dev(&P.kern), P.nlag, prec, ws + L.lag, s));
+      fa.lagtab = ws + L.lag;
+    }
     int32_t st = run_lowrank(&P.p, &P.ind, &P.kern, prec, ws, L, s);
     if (st) return st;
     fa.U = ws + L.U;
@@ -1364,6 +1382,7 @@ vif_batch* vif_batch_create(const vif_problem* probs, int32_t count, int32_t pre
       int nslab = 1;
       const double span = tt[1] - tt[0];
       if (!(tf & 6u) && span >= 0 && span < (double)VIF_MAX_LAGS) nslab = (int)span + 1;
+      P.nlag = (!(tf & 6u) && span >= 0 && span < (double)VIF_MAX_LAGS) ? nslab : 0;
       const double per = (double)q.points.n / nslab;
       int bits = 0;
       while (bits < 10 && (double)(1 << (2 * (bits + 1))) * 3.0 <= per &&

@@ -62,7 +62,9 @@ __device__ __forceinline__ T cov_eval(const KernDev& K, T dx, T dy, T dt) {
 // The stretched-exponential Gneiting kernel (kind 1) factored for many pairs at
 // one time lag: gneiting_lag gives A = -tau log psi and e = exp(-beta gamma log psi)
 // for |dt|, gneiting_pair the covariance from them, with the operations of
-// cov_eval in the same order (so the values are identical).
+// cov_eval in the same order. The values agree with cov_eval to rounding: A is
+// rounded on its own here, where cov_eval may fuse -tau log psi into the
+// following subtraction.
 template <typename T>
 __device__ __forceinline__ void gneiting_lag(const KernDev& K, T dt, T& A, T& e) {
   T adt = dt < T(0) ? -dt : dt;

@@ -21,7 +21,7 @@
 // share of v' dC v and v' dC alpha_N. Per-point results go to parameter-major
 // arrays summed later in a fixed order (deterministic). For the Gneiting kernel
 // with integer times, the quantities that depend on the time lag alone come
-// from a per-lag table (computed with the same operations), leaving one
+// from a per-lag table (the operations of the direct evaluation), leaving one
 // logarithm and one or two exponentials per pair.
 #include <math.h>
 
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void grad_lag_kernel(GradKern G, int nlag, dou
   o[5] = ldt;
 }
 
-// cov_and_grad for the Gneiting kernel from a lag-table row (same operations).
+// cov_and_grad for the Gneiting kernel from a lag-table row (the same formulas).
 __device__ __forceinline__ double cov_and_grad_lag(const GradKern& G, double dx, double dy,
                                                    const double* __restrict__ lt,
                                                    double dC[kGradMaxParams]) {

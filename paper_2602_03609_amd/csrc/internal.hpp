@@ -112,10 +112,15 @@ struct FactorArgs {
   double *B, *D;  // factor outputs
   double *logD, *z;  // NLL outputs (per point)
   const int32_t* ord;           // processing order (a permutation of 0..n-1) or NULL
+  // GNEITING with integer, nondecreasing times: (A, e) of gneiting_lag per lag, in the
+  // precision of the covariance entries (launch_lag_table); NULL: direct evaluation.
+  const void* lagtab;
   unsigned long long* fail;     // smallest point index with a non-positive-definite block
   unsigned long long* bad_nbr;  // smallest point index with an invalid neighbor row
 };
 
+// tab[2 l], tab[2 l + 1] = gneiting_lag(K, l) for l < nlag, in FP64 (prec 0) or FP32.
+hipError_t launch_lag_table(const KernDev& K, int nlag, int prec, void* tab, hipStream_t s);
 // mode: 0 = NLL terms, 1 = factor (B, D). prec: 0 FP64, 1 FP32, 2 BF16X3.
 hipError_t launch_point_factor(const FactorArgs& a, int mode, int prec, hipStream_t s);
 

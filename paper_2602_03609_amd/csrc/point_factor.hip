@@ -629,6 +629,7 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
 
   // ---- per-point residual block, Cholesky, back-substitution (segment) ----
   T* M = sM + pl * ROWS * ROWS;
+  const T* lag_tab = reinterpret_cast<const T*>(A.lagtab);
   {
     const int h = (r >= ROWS / 2) ? 1 : 0;
     const int rp = r - h * (ROWS / 2);
@@ -644,7 +645,14 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
           const double dx = sX[pl][row] - sX[pl][col];
           const double dy = sY[pl][row] - sY[pl][col];
           const double dt = sT[pl][row] - sT[pl][col];
-          val = cov_eval<T>(A.K, (T)dx, (T)dy, (T)dt) - M[row * ROWS + col];
+          if (lag_tab) {
+            // the operations of cov_eval, the lag-only factors from the table
+            const int lg = (int)fabs(dt);
+            val = gneiting_pair<T>(A.K, (T)dx, (T)dy, lag_tab[2 * lg], lag_tab[2 * lg + 1]);
+          } else {
+            val = cov_eval<T>(A.K, (T)dx, (T)dy, (T)dt);
+          }
+          val -= M[row * ROWS + col];
         }
         M[row * ROWS + col] = val;
         M[col * ROWS + row] = val;
@@ -815,6 +823,25 @@ hipError_t launch_prec(const FactorArgs& a, int mode, hipStream_t s) {
 }
 
 }  // namespace
+
+template <typename T>
+__global__ __launch_bounds__(256) void lag_table_kernel(KernDev K, int nlag, T* __restrict__ tab) {
+  const int l = blockIdx.x * 256 + threadIdx.x;
+  if (l >= nlag) return;
+  T a, e;
+  gneiting_lag<T>(K, (T)l, a, e);
+  tab[2 * l] = a;
+  tab[2 * l + 1] = e;
+}
+
+hipError_t launch_lag_table(const KernDev& K, int nlag, int prec, void* tab, hipStream_t s) {
+  const dim3 grid((unsigned)((nlag + 255) / 256));
+  if (prec == 0)
+    hipLaunchKernelGGL(lag_table_kernel<double>, grid, dim3(256), 0, s, K, nlag, (double*)tab);
+  else
+    hipLaunchKernelGGL(lag_table_kernel<float>, grid, dim3(256), 0, s, K, nlag, (float*)tab);
+  return hipGetLastError();
+}
 
 hipError_t launch_point_factor(const FactorArgs& a, int mode, int prec, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;

@@ -20,8 +20,8 @@
 // are issued before the current stage's products. For the Gneiting kernel with
 // integer times the factors that depend on the time lag alone come from a
 // table per lag (gneiting_lag), and each entry costs one exponential
-// (gneiting_pair performs the same operations as cov_eval, so the values are
-// the same).
+// (gneiting_pair performs the operations of cov_eval; the values agree to
+// rounding).
 #include <math.h>
 
 #include "internal.hpp"
