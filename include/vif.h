@@ -79,7 +79,7 @@ enum { VIF_KERNEL_GNEITING = 1, VIF_KERNEL_GNEITING_MATERN = 2, VIF_KERNEL_MATER
  * M are combined in FP64 every 1024 rows. */
 enum { VIF_PREC_FP64 = 0, VIF_PREC_FP32 = 1, VIF_PREC_BF16X3 = 2, VIF_PREC_BF16X6 = 3 };
 
-enum { VIF_OP_NEIGHBORS = 0, VIF_OP_FACTOR = 1, VIF_OP_NLL = 2 };
+enum { VIF_OP_NEIGHBORS = 0, VIF_OP_FACTOR = 1, VIF_OP_NLL = 2, VIF_OP_NEIGHBORS_NLL = 3 };
 
 /* Hyperparameters (HOST struct; fields a kernel kind does not use are ignored).
  * nugget >= 0 is the noise variance of Eq. (Model). jitter >= 0 is added to the
@@ -149,6 +149,18 @@ int32_t vif_nll(const vif_points* p, const double* y, const vif_kernel* kern, in
 int32_t vif_nll_terms(const vif_points* p, const double* y, const vif_kernel* kern, int32_t m,
                       const int32_t* nbr, const vif_points* ind, int32_t prec, double* nll,
                       double* terms, void* ws, size_t ws_bytes, void* hip_stream);
+
+/* vif_neighbors followed by vif_nll on its output, in one call: the neighbor
+ * search (Alg. 2) runs on a library-owned non-blocking stream of the current
+ * device (default priority) while hip_stream builds Sigma_k and U, and the
+ * per-point stage waits for it. nbr (DEVICE int32 [n*m], written) and the NLL
+ * are bit-identical to the two separate calls. Workspace:
+ * vif_workspace_bytes(n, m, k, prec, VIF_OP_NEIGHBORS_NLL). Returns after both
+ * streams have drained, also on error. Calls on one device from several host
+ * threads run one at a time (they share that stream). */
+int32_t vif_neighbors_nll(const vif_points* p, const double* y, const vif_kernel* kern, int32_t m,
+                          int32_t* nbr, const vif_points* ind, int32_t prec, double* nll, void* ws,
+                          size_t ws_bytes, void* hip_stream);
 
 /* Message for the last error on the calling thread ("" after success). The
  * pointer stays valid until the next call on this thread. */

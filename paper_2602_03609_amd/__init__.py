@@ -15,6 +15,7 @@ from ._lib import (  # noqa: F401
     VIF_KERNEL_MATERN_ANISO,
     VIF_OP_FACTOR,
     VIF_OP_NEIGHBORS,
+    VIF_OP_NEIGHBORS_NLL,
     VIF_OP_NLL,
     VIF_PREC_BF16X3,
     VIF_PREC_BF16X6,
@@ -30,6 +31,7 @@ from ._lib import (  # noqa: F401
     vif_mlp_forward,
     vif_mlp_pair_loss,
     vif_neighbors,
+    vif_neighbors_nll,
     vif_nll,
     vif_nll_grad,
     vif_nll_terms,

@@ -17,11 +17,12 @@ LIB_PATH = os.path.join(PKG, "libvif.so")
 VIF_OK, VIF_E_ARG, VIF_E_NOT_PD, VIF_E_DEVICE, VIF_E_WORKSPACE, VIF_E_UNSUPPORTED = range(6)
 VIF_KERNEL_GNEITING, VIF_KERNEL_GNEITING_MATERN, VIF_KERNEL_MATERN_ANISO = 1, 2, 3
 VIF_PREC_FP64, VIF_PREC_FP32, VIF_PREC_BF16X3, VIF_PREC_BF16X6 = 0, 1, 2, 3
-VIF_OP_NEIGHBORS, VIF_OP_FACTOR, VIF_OP_NLL = 0, 1, 2
+VIF_OP_NEIGHBORS, VIF_OP_FACTOR, VIF_OP_NLL, VIF_OP_NEIGHBORS_NLL = 0, 1, 2, 3
 PREC_NAMES = {"fp64": VIF_PREC_FP64, "fp32": VIF_PREC_FP32, "bf16x3": VIF_PREC_BF16X3,
               "bf16x6": VIF_PREC_BF16X6}
 
 EXPORTS = ("vif_workspace_bytes", "vif_neighbors", "vif_factor", "vif_nll", "vif_nll_terms",
+           "vif_neighbors_nll",
            "vif_last_error", "vif_profile", "vif_profile_read",
            "vif_mlp_features", "vif_mlp_forward", "vif_mlp_backward_ws", "vif_mlp_backward",
            "vif_mlp_pair_loss", "vif_mlp_adam", "vif_mlp_batch", "vif_propose_ws",
@@ -84,6 +85,8 @@ def load(path=LIB_PATH):
         lib.vif_nll.restype = i32
         lib.vif_nll_terms.argtypes = [pP, vp, pK, i32, vp, pP, i32, pd, pd, vp, sz, vp]
         lib.vif_nll_terms.restype = i32
+        lib.vif_neighbors_nll.argtypes = [pP, vp, pK, i32, vp, pP, i32, pd, vp, sz, vp]
+        lib.vif_neighbors_nll.restype = i32
         lib.vif_last_error.argtypes = []
         lib.vif_last_error.restype = ctypes.c_char_p
         lib.vif_profile.argtypes = [i32]
@@ -298,6 +301,26 @@ def vif_nll(sx, sy, t, y, kern, m, nbr, ind=None, prec="fp64", stream=None):
                        ctypes.byref(ip) if ip is not None else None, _prec(prec),
                        ctypes.byref(out), ws.data_ptr(), ws.numel(), _stream(stream)))
     return out.value
+
+
+def vif_neighbors_nll(sx, sy, t, y, kern, m, nbr=None, ind=None, prec="fp64", stream=None):
+    """Neighbor search and NLL in one call (the search overlaps the low-rank
+    stages); returns (nll, nbr int32 [n, m])."""
+    torch = _torch()
+    lib = load()
+    n = sx.shape[0]
+    if nbr is None:
+        nbr = torch.empty((n, m), dtype=torch.int32, device=sx.device)
+    p = make_points(sx, sy, t)
+    K = make_kernel(kern)
+    ip, k = _ind(ind)
+    ws = workspace(n, m, k, _prec(prec), VIF_OP_NEIGHBORS_NLL, sx.device)
+    out = ctypes.c_double(0.0)
+    _check(lib.vif_neighbors_nll(ctypes.byref(p), _dev_ptr(y, torch.float64, "y"), ctypes.byref(K),
+                                 int(m), _dev_ptr(nbr, torch.int32, "nbr") if m > 0 else None,
+                                 ctypes.byref(ip) if ip is not None else None, _prec(prec),
+                                 ctypes.byref(out), ws.data_ptr(), ws.numel(), _stream(stream)))
+    return out.value, nbr
 
 
 def vif_profile(enable):

@@ -9,7 +9,9 @@
 
 #include <string>
 #include <algorithm>
+#include <functional>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "internal.hpp"
@@ -427,9 +429,18 @@ int32_t check_ind(const vif_points* ind, int* k) {
   return VIF_OK;
 }
 
+// Work that another stream runs while the NLL builds its low-rank factor: start()
+// queues it behind the NLL stream's work so far, and `done` is recorded after it;
+// the NLL stream waits on `done` before the per-point kernel reads the neighbors.
+struct SideWork {
+  std::function<int32_t(hipStream_t)> start;
+  hipEvent_t done = nullptr;
+};
+
 int32_t nll_impl(const vif_points* p, const double* y, const vif_kernel* kern, int32_t m,
                  const int32_t* nbr, const vif_points* ind, int32_t prec, double* nll,
-                 double* terms, void* wsv, size_t ws_bytes, void* hip_stream) {
+                 double* terms, void* wsv, size_t ws_bytes, void* hip_stream,
+                 const SideWork* side = nullptr) {
   int k = 0;
   int32_t st = check_ind(ind, &k);
   if (st) return st;
@@ -467,7 +478,9 @@ int32_t nll_impl(const vif_points* p, const double* y, const vif_kernel* kern, i
       HIPCHK(vif::launch_lag_table(to_dev(kern), nlag, prec, ws + L.lag, s));
       fa.lagtab = ws + L.lag;
     }
+    if (side && (st = side->start(s))) return st;
     if ((st = run_lowrank(p, ind, kern, prec, ws, L, s))) return st;
+    if (side) HIPCHK(hipStreamWaitEvent(s, side->done, 0));
     fa.U = ws + L.U;
     fa.W = ws + L.W;
     fa.z = reinterpret_cast<double*>(ws + L.z);
@@ -492,6 +505,10 @@ int32_t nll_impl(const vif_points* p, const double* y, const vif_kernel* kern, i
     HIPCHK(vif::launch_finalize(p->n, k, L.kpad, M, sums + 0, sums + 1, out, s));
     PROF(VIF_STAGE_ASSEMBLY, true);
   } else {
+    if (side) {
+      if ((st = side->start(s))) return st;
+      HIPCHK(hipStreamWaitEvent(s, side->done, 0));
+    }
     fa.z = reinterpret_cast<double*>(ws + L.z);
     PROF(VIF_STAGE_POINT_FACTOR, false);
     HIPCHK(vif::launch_point_factor(fa, 0, prec, s));
@@ -672,12 +689,48 @@ int32_t exact_grid(const vif_points* p, char* ws, const Layout& L, hipStream_t s
   return VIF_OK;
 }
 
+// One non-blocking stream at the default priority and two events per device, for
+// the neighbor search that vif_neighbors_nll runs beside the low-rank stages. The
+// lock serialises such calls on one device, which share the stream and events.
+struct SideStream {
+  std::mutex mu;
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, done = nullptr;
+};
+
+constexpr int kMaxDevices = 64;
+
+// The current device's side stream and events, created on first use.
+int32_t side_stream(SideStream** out) {
+  static SideStream slots[kMaxDevices];
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(VIF_E_UNSUPPORTED, "device index %d", dev);
+  SideStream* ss = &slots[dev];
+  std::lock_guard<std::mutex> lock(ss->mu);
+  if (!ss->s) {
+    hipStream_t st = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&a, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&b, hipEventDisableTiming));
+    ss->s = st;
+    ss->fork = a;
+    ss->done = b;
+  }
+  *out = ss;
+  return VIF_OK;
+}
+
 extern "C" {
 
 size_t vif_workspace_bytes(int64_t n, int32_t m, int32_t k, int32_t prec, int32_t op) {
   if (n < 1 || m < 0 || m > VIF_MAX_M || k < 0 || k > VIF_MAX_K) return 0;
   if (prec < VIF_PREC_FP64 || prec > VIF_PREC_BF16X6) return 0;
-  if (op < VIF_OP_NEIGHBORS || op > VIF_OP_NLL) return 0;
+  if (op < VIF_OP_NEIGHBORS || op > VIF_OP_NEIGHBORS_NLL) return 0;
+  if (op == VIF_OP_NEIGHBORS_NLL)
+    return align256(make_layout(n, m, 0, VIF_PREC_FP64, VIF_OP_NEIGHBORS).total) +
+           make_layout(n, m, k, prec, VIF_OP_NLL).total;
   return make_layout(n, m, k, prec, op).total;
 }
 
@@ -723,6 +776,56 @@ int32_t vif_neighbors(const vif_points* p, const vif_kernel* kern, int32_t m, in
   // The host tables must outlive the copies above.
   HIPCHK(hipStreamSynchronize(s));
   prof_collect();
+  return ok();
+}
+
+int32_t vif_neighbors_nll(const vif_points* p, const double* y, const vif_kernel* kern, int32_t m,
+                          int32_t* nbr, const vif_points* ind, int32_t prec, double* nll, void* wsv,
+                          size_t ws_bytes, void* hip_stream) {
+  int k = 0;
+  int32_t st = check_ind(ind, &k);
+  if (st) return st;
+  if (prec < VIF_PREC_FP64 || prec > VIF_PREC_BF16X6) return fail(VIF_E_ARG, "unknown precision %d", prec);
+  if (!p) return fail(VIF_E_ARG, "points is NULL");
+  const Layout Ln = make_layout(p->n, m, 0, VIF_PREC_FP64, VIF_OP_NEIGHBORS);
+  const size_t off = align256(Ln.total);
+  const size_t need = off + make_layout(p->n, m, k, prec, VIF_OP_NLL).total;
+  if ((st = check_common(p, kern, m, wsv, ws_bytes, need))) return st;
+  if (!y) return fail(VIF_E_ARG, "y is NULL");
+  if (m > 0 && !nbr) return fail(VIF_E_ARG, "nbr is NULL");
+  if (!nll) return fail(VIF_E_ARG, "nll is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  char* ws = reinterpret_cast<char*>(wsv);
+  if (m == 0)
+    return nll_impl(p, y, kern, 0, nullptr, ind, prec, nll, nullptr, ws + off, ws_bytes - off, hip_stream);
+  SideStream* ss = nullptr;
+  if ((st = side_stream(&ss))) return st;
+  std::lock_guard<std::mutex> lock(ss->mu);
+  SearchSetup S;
+  if ((st = search_setup(p, kern, m, nbr, ws, Ln, s, &S))) return st;
+  SideWork side;
+  side.done = ss->done;
+  side.start = [&](hipStream_t main) -> int32_t {
+    HIPCHK(hipEventRecord(ss->fork, main));
+    HIPCHK(hipStreamWaitEvent(ss->s, ss->fork, 0));
+    int32_t r = prof_mark(VIF_STAGE_NEIGHBORS, false, ss->s);
+    if (r) return r;
+    vif::GridArgs g{};
+    if ((r = exact_grid(p, ws, Ln, ss->s, S, &g))) return r;
+    HIPCHK(vif::launch_neighbors(S.a, g, ss->s));
+    if ((r = prof_mark(VIF_STAGE_NEIGHBORS, true, ss->s))) return r;
+    HIPCHK(hipEventRecord(ss->done, ss->s));
+    return VIF_OK;
+  };
+  st = nll_impl(p, y, kern, m, nbr, ind, prec, nll, nullptr, ws + off, ws_bytes - off, hip_stream,
+                &side);
+  // The search's host tables and the workspace are in use until both streams drain,
+  // also when the NLL stopped early with an error.
+  const hipError_t e_side = hipStreamSynchronize(ss->s);
+  const hipError_t e_main = hipStreamSynchronize(s);
+  if (st) return st;
+  if (e_side != hipSuccess) return fail(VIF_E_DEVICE, "side stream: %s", hipGetErrorString(e_side));
+  if (e_main != hipSuccess) return fail(VIF_E_DEVICE, "stream: %s", hipGetErrorString(e_main));
   return ok();
 }
 

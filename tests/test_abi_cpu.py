@@ -88,6 +88,40 @@ def test_argument_errors_before_any_launch():
     assert st == L.VIF_E_UNSUPPORTED
 
 
+def test_neighbors_nll_argument_errors():
+    """The combined search + NLL entry point: workspace is the search's (256-byte
+    aligned) followed by the NLL's; host-side validation precedes any launch."""
+    import paper_2602_03609_amd._lib as L
+    lib = L.load()
+    n, m, k = 5000, 30, 200
+    for prec in (0, 2, 3):
+        a = L.vif_workspace_bytes(n, m, 0, 0, L.VIF_OP_NEIGHBORS)
+        b = L.vif_workspace_bytes(n, m, k, prec, L.VIF_OP_NLL)
+        assert L.vif_workspace_bytes(n, m, k, prec, L.VIF_OP_NEIGHBORS_NLL) == ((a + 255) // 256) * 256 + b
+    assert lib.vif_workspace_bytes(n, m, k, 0, 4) == 0
+    K = L.make_kernel({"kind": 1, "sigma2": 1.0, "nugget": 0.1, "a": 0.5, "c": 20.0, "alpha": 0.75,
+                       "beta": 0.5, "gamma": 0.5, "tau": 1.0})
+    P = L.Points()
+    P.n = n
+    P.sx = P.sy = P.t = ctypes.c_void_p(0x1000)
+    Z = L.Points()
+    Z.n = k
+    Z.sx = Z.sy = Z.t = ctypes.c_void_p(0x2000)
+    dev, big = ctypes.c_void_p(0x1000), 1 << 40
+    out = ctypes.c_double()
+    need = L.vif_workspace_bytes(n, m, k, 2, L.VIF_OP_NEIGHBORS_NLL)
+
+    def call(y=dev, nbr=dev, prec=2, res=ctypes.byref(out), ws_bytes=big):
+        return lib.vif_neighbors_nll(ctypes.byref(P), y, ctypes.byref(K), m, nbr, ctypes.byref(Z), prec,
+                                     res, ctypes.c_void_p(0x100000), ws_bytes, None)
+
+    assert call(ws_bytes=need - 1) == L.VIF_E_WORKSPACE
+    assert call(y=None) == L.VIF_E_ARG and b"y is NULL" in lib.vif_last_error()
+    assert call(nbr=None) == L.VIF_E_ARG and b"nbr is NULL" in lib.vif_last_error()
+    assert call(res=None) == L.VIF_E_ARG and b"nll is NULL" in lib.vif_last_error()
+    assert call(prec=7) == L.VIF_E_ARG and b"precision" in lib.vif_last_error()
+
+
 def test_learned_proposal_argument_errors():
     import paper_2602_03609_amd._lib as L
     lib = L.load()

@@ -78,3 +78,17 @@ def test_mixed_precision_nll_vs_fp64(big):
     assert errs["fp32"] <= 1e-5
     assert errs["bf16x6"] <= 1e-5
     assert errs["bf16x3"] <= 1e-4
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x6"])
+def test_combined_call_matches_separate_calls(big, prec):
+    """vif_neighbors_nll, the call bench.py times: neighbor lists and NLL
+    bit-identical to the two separate calls at full size."""
+    torch = torch_cuda()
+    vif = lib()
+    d, Xd, yd, Zd, nbr = big
+    nll, nb = vif.vif_neighbors_nll(*Xd, yd, d["kern"], d["m"], ind=Zd, prec=prec)
+    want = vif.vif_nll(*Xd, yd, d["kern"], d["m"], nbr, ind=Zd, prec=prec)
+    log(f"[scale] combined {prec}: nll {nll:.12g} (separate {want:.12g})")
+    assert torch.equal(nb, nbr)
+    assert nll == want
