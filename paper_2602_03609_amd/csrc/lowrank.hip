@@ -48,16 +48,18 @@ __global__ void cov_kk_kernel(LowRankArgs A, double* __restrict__ S) {
 }
 
 // ---------------------------------------------------------------- Cholesky ---
-// Solves T y = b (T lower triangular 64 x 64 in LDS) for 64 right-hand sides at
-// once, all in registers: lanes 4s..4s+3 hold right-hand side s, lane 4s + g
-// holding entries g, g + 4, ..., g + 60 in v[]. Column r of the elimination is
-// broadcast from its owner lane with a shuffle; no barriers.
-__device__ __forceinline__ void tri_solve_regs(double v[16], const double (*T)[NB + 1], int g,
-                                               int lane) {
+// Solves T y = b (T lower triangular 64 x 64 in LDS, rd[r] = 1 / T[r][r] in LDS)
+// for 64 right-hand sides at once, all in registers: lanes 4s..4s+3 hold
+// right-hand side s, lane 4s + g holding entries g, g + 4, ..., g + 60 in v[].
+// Column r of the elimination is broadcast from its owner lane with a shuffle;
+// no barriers. Multiplying by the stored reciprocal keeps the division off the
+// serial chain of the 64 columns.
+__device__ __forceinline__ void tri_solve_regs(double v[16], const double (*T)[NB + 1],
+                                               const double* rd, int g, int lane) {
 #pragma unroll
   for (int r = 0; r < NB; ++r) {
     const int go = r & 3, io = r >> 2;
-    double y = v[io] / T[r][r];
+    double y = v[io] * rd[r];
     y = __shfl(y, (lane & ~3) | go);
     if (g == go) v[io] = y;
 #pragma unroll
@@ -81,6 +83,7 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(int N, double* __restri
                                                          unsigned long long* fail,
                                                          double* __restrict__ dscr) {
   __shared__ double Ld[NB][NB + 1];
+  __shared__ double rd[NB];
   __shared__ int bad;
   const int tid = threadIdx.x;
   const int w = blockIdx.x;
@@ -90,7 +93,11 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(int N, double* __restri
   // lane r holds row r; the pivot and each multiplier l_c are read from their
   // owner lane with readlane (scalar registers), so there is no LDS traffic and
   // no synchronisation until the factor is stored. Entries above the diagonal
-  // are never touched: the multiplier of rows r <= kk is zero.
+  // are never touched: the multiplier of rows r <= kk is zero. The multipliers
+  // are a[kk] / sqrt(d) formed as a[kk] * rs with rs = 1 / sqrt(d) from the
+  // hardware estimate and two Newton steps (rs += rs (1 - d rs^2) / 2), which
+  // keeps the serial chain from one column to the next short; the diagonal
+  // itself is the correctly rounded sqrt(d), computed beside the chain.
   if (tid < NB) {
     const int r = tid;
     double a[NB];
@@ -102,8 +109,12 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(int N, double* __restri
       const double d = readlane_f64(a[kk], kk);
       const bool okp = d > 0.0 && d < INFINITY;
       const double piv = okp ? sqrt(d) : 1.0;
+      double rs = __builtin_amdgcn_rsq(okp ? d : 1.0);
+#pragma unroll
+      for (int it = 0; it < 2; ++it) rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
+      rs = okp ? rs : 1.0;
       if (!okp && badl < 0) badl = kk;
-      const double lm = r > kk ? a[kk] / piv : 0.0;
+      const double lm = r > kk ? a[kk] * rs : 0.0;
       if (r >= kk) a[kk] = r > kk ? lm : piv;
 #pragma unroll
       for (int c = kk + 1; c < NB; ++c) a[c] -= lm * readlane_f64(lm, c);
@@ -111,6 +122,7 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(int N, double* __restri
     }
 #pragma unroll
     for (int c = 0; c < NB; ++c) Ld[r][c] = (c <= r) ? a[c] : 0.0;
+    rd[r] = 1.0 / Ld[r][r];
     if (r == 0) bad = badl;
   }
   __syncthreads();
@@ -130,7 +142,7 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(int N, double* __restri
   double v[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) v[i] = A[(r0 + s) * N + d0 + g + 4 * i];
-  tri_solve_regs(v, Ld, g, lane);
+  tri_solve_regs(v, Ld, rd, g, lane);
 #pragma unroll
   for (int i = 0; i < 16; ++i) A[(r0 + s) * N + d0 + g + 4 * i] = v[i];
 }
@@ -194,6 +206,7 @@ __global__ __launch_bounds__(256) void chol_update_kernel(int N, double* __restr
 __global__ __launch_bounds__(256) void trinv_diag_kernel(int N, const double* __restrict__ L,
                                                          double* __restrict__ P) {
   __shared__ double Ta[NB][NB + 1];
+  __shared__ double rd[NB];
   const int t = blockIdx.x;
   const int NT = N / NB;
   const int tid = threadIdx.x;
@@ -202,11 +215,13 @@ __global__ __launch_bounds__(256) void trinv_diag_kernel(int N, const double* __
     for (int e = tid; e < NB * NB; e += 256) P[(r0 + e / NB) * N + (int64_t)cb * NB + e % NB] = 0.0;
   for (int e = tid; e < NB * NB; e += 256) Ta[e / NB][e % NB] = L[(r0 + e / NB) * N + r0 + e % NB];
   __syncthreads();
+  if (tid < NB) rd[tid] = 1.0 / Ta[tid][tid];
+  __syncthreads();
   const int lane = tid & 63, sc = tid >> 2, g = tid & 3;
   double v[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) v[i] = (g + 4 * i == sc) ? 1.0 : 0.0;
-  tri_solve_regs(v, Ta, g, lane);
+  tri_solve_regs(v, Ta, rd, g, lane);
 #pragma unroll
   for (int i = 0; i < 16; ++i) P[(r0 + g + 4 * i) * N + r0 + sc] = v[i];
 }
