@@ -14,11 +14,13 @@ term the Gaussian formula above on one small block. This module computes
 exactly that, block by block, with dense inverses.
 
 Parameters, in this order:
-  GNEITING:     sigma2, nugget, a, c, alpha, beta, gamma, tau
-  MATERN_ANISO: sigma2, nugget, range_s, range_t   (nu fixed)
+  GNEITING:        sigma2, nugget, a, c, alpha, beta, gamma, tau
+  GNEITING_MATERN: sigma2, nugget, a, c, alpha, gamma, delta   (nu fixed)
+  MATERN_ANISO:    sigma2, nugget, range_s, range_t   (nu fixed)
 The covariance derivatives below follow from the kernel definitions by the
 chain rule (psi = a |dt|^(2 alpha) + 1, g = (|ds|^2)^gamma, E = psi^(-beta gamma),
-C = sigma2 psi^-tau exp(-c g E); Matern: C = sigma2 g_nu(d),
+C = sigma2 psi^-tau exp(-c g E); Gneiting-Matern: x = c |ds| psi^(-gamma/2),
+C = sigma2 psi^-(delta + gamma) g_nu(x); Matern: C = sigma2 g_nu(d),
 d = sqrt(|ds|^2 / range_s^2 + dt^2 / range_t^2)).
 """
 from __future__ import annotations
@@ -27,12 +29,25 @@ import math
 
 import numpy as np
 
-from .kernels import GNEITING, MATERN_ANISO, cov
+from .kernels import GNEITING, GNEITING_MATERN, MATERN_ANISO, cov, matern_closed
 
 LOG2PI = math.log(2.0 * math.pi)
 
 PARAMS = {GNEITING: ("sigma2", "nugget", "a", "c", "alpha", "beta", "gamma", "tau"),
+          GNEITING_MATERN: ("sigma2", "nugget", "a", "c", "alpha", "gamma", "delta"),
           MATERN_ANISO: ("sigma2", "nugget", "range_s", "range_t")}
+
+
+def _matern_dx(nu, x):
+    """Derivative of the closed-form Matern correlation g_nu with respect to x."""
+    e = np.exp(-x)
+    if nu == 0.5:
+        return -e
+    if nu == 1.5:
+        return -x * e
+    if nu == 2.5:
+        return -x * (1.0 + x) * e / 3.0
+    raise ValueError("nu in {0.5, 1.5, 2.5}")
 
 
 def dcov(kern, dx, dy, dt):
@@ -62,6 +77,24 @@ def dcov(kern, dx, dy, dt):
                 C * q * ga * lp,                       # beta
                 -C * q * (lh2 - be * lp),              # gamma
                 -C * lp]                               # tau
+    if kern["kind"] == GNEITING_MATERN:
+        a, c, al, ga, de, nu = (kern[k] for k in ("a", "c", "alpha", "gamma", "delta", "nu"))
+        adt = np.abs(dt)
+        ta = adt ** (2.0 * al)
+        psi = a * ta + 1.0
+        lp = np.log(psi)
+        amp = kern["sigma2"] * psi ** (-(de + ga))     # C = amp g(x)
+        x = c * np.sqrt(h2) * psi ** (-ga / 2.0)
+        gx = x * _matern_dx(nu, x)                     # x g'(x): dC/dlog x = amp gx
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ldt = np.where(adt > 0, np.log(np.where(adt > 0, adt, 1.0)), 0.0)
+        dpsi = (-(de + ga) * C - 0.5 * ga * amp * gx) / psi   # dC/dpsi
+        return [C / kern["sigma2"], zero,
+                dpsi * ta,                             # a
+                amp * gx / c,                          # c
+                dpsi * a * ta * 2.0 * ldt,             # alpha
+                -C * lp - 0.5 * amp * gx * lp,         # gamma
+                -C * lp]                               # delta
     if kern["kind"] == MATERN_ANISO:
         rs, rt, nu = kern["range_s"], kern["range_t"], kern["nu"]
         d = np.sqrt(h2 / (rs * rs) + dt * dt / (rt * rt))
@@ -80,7 +113,7 @@ def dcov(kern, dx, dy, dt):
         return [C / s2, zero,
                 s2 * fp * (-h2 / (rs ** 3)) * inv_d,
                 s2 * fp * (-dt * dt / (rt ** 3)) * inv_d]
-    raise ValueError("gradient implemented for GNEITING and MATERN_ANISO")
+    raise ValueError("gradient implemented for GNEITING, GNEITING_MATERN and MATERN_ANISO")
 
 
 def _block(kern, X, idx):

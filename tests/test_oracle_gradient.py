@@ -1,7 +1,8 @@
 """Pins for the oracle's Vecchia NLL gradient (CPU only).
 
 * each covariance derivative equals a central finite difference of the oracle's
-  covariance (a separately pinned function) in that parameter;
+  covariance (a separately pinned function) in that parameter, for the three
+  kernel families (Gneiting-Matern with each closed-form smoothness);
 * the gradient equals central finite differences of the oracle's Vecchia NLL
   (pinned against the dense exact likelihood);
 * with m = n - 1 the Vecchia likelihood is exact, so the gradient equals the
@@ -20,10 +21,17 @@ from oracle import likelihood as LK
 from oracle import neighbors as NB
 
 
-def _kern(kind):
-    if kind == 1:
+KINDS = {"gneiting": 1, "gm_nu05": 2, "gm_nu15": 2, "gm_nu25": 2, "aniso": 3}
+
+
+def _kern(name):
+    if name == "gneiting":
         return synth.kern_gneiting(sigma2=1.3, a=0.7, c=15.0, alpha=0.6, beta=0.4, gamma=0.45,
                                    tau=1.2, nugget=0.08)
+    if name.startswith("gm_"):
+        nu = {"gm_nu05": 0.5, "gm_nu15": 1.5, "gm_nu25": 2.5}[name]
+        return synth.kern_gneiting_matern(sigma2=1.1, a=0.6, c=8.0, alpha=0.45, gamma=0.35,
+                                          delta=0.3, nu=nu, nugget=0.06)
     return synth.kern_matern_aniso(range_s=0.25, range_t=2.5, sigma2=0.9, nugget=0.07, nu=1.5)
 
 
@@ -33,22 +41,23 @@ def _bump(kern, name, h):
     return out
 
 
-@pytest.mark.parametrize("kind", [1, 3])
-def test_covariance_derivatives_match_finite_differences(kind):
-    kern = _kern(kind)
-    rng = np.random.default_rng(kind)
+@pytest.mark.parametrize("name", list(KINDS))
+def test_covariance_derivatives_match_finite_differences(name):
+    kern = _kern(name)
+    kind = KINDS[name]
+    rng = np.random.default_rng(len(name) + kind)
     dx, dy = rng.normal(scale=0.2, size=200), rng.normal(scale=0.2, size=200)
     dt = rng.integers(-4, 5, size=200).astype(float)
     dx[:5] = dy[:5] = 0.0      # same place
     dt[5:10] = 0.0             # same time
     D = GR.dcov(kern, dx, dy, dt)
-    for p, name in enumerate(GR.PARAMS[kind]):
-        if name == "nugget":
+    for p, par in enumerate(GR.PARAMS[kind]):
+        if par == "nugget":
             assert np.all(D[p] == 0.0)
             continue
-        h = 1e-6 * max(abs(kern[name]), 1e-3)
-        fd = (K.cov(_bump(kern, name, h), dx, dy, dt) - K.cov(_bump(kern, name, -h), dx, dy, dt)) / (2 * h)
-        assert np.allclose(D[p], fd, rtol=1e-5, atol=1e-8), name
+        h = 1e-6 * max(abs(kern[par]), 1e-3)
+        fd = (K.cov(_bump(kern, par, h), dx, dy, dt) - K.cov(_bump(kern, par, -h), dx, dy, dt)) / (2 * h)
+        assert np.allclose(D[p], fd, rtol=1e-5, atol=1e-8), par
 
 
 def _fd_grad(f, kern, names):
@@ -59,10 +68,11 @@ def _fd_grad(f, kern, names):
     return np.array(g)
 
 
-@pytest.mark.parametrize("kind", [1, 3])
-def test_gradient_matches_finite_differences_of_the_nll(kind):
+@pytest.mark.parametrize("name", list(KINDS))
+def test_gradient_matches_finite_differences_of_the_nll(name):
+    kind = KINDS[name]
     d = synth.config_small(seed=10 + kind, n_sites=40, n_times=4, k=0, m=6, kind=kind)
-    kern = _kern(kind)
+    kern = _kern(name)
     X = (d["sx"], d["sy"], d["t"])
     nbr = NB.brute_force(kern, *X, 6)
     nll, g = GR.vecchia_grad(kern, X, d["y"], nbr)
@@ -71,10 +81,11 @@ def test_gradient_matches_finite_differences_of_the_nll(kind):
     assert np.allclose(g, fd, rtol=1e-5, atol=1e-6 * np.abs(fd).max())
 
 
-@pytest.mark.parametrize("kind", [1, 3])
-def test_full_conditioning_gives_the_exact_gradient(kind):
+@pytest.mark.parametrize("name", list(KINDS))
+def test_full_conditioning_gives_the_exact_gradient(name):
+    kind = KINDS[name]
     d = synth.config_small(seed=20 + kind, n_sites=15, n_times=3, k=0, m=6, kind=kind)
-    kern = _kern(kind)
+    kern = _kern(name)
     X = (d["sx"], d["sy"], d["t"])
     n = d["n"]
     nbr = NB.brute_force(kern, *X, n - 1)
