@@ -11,9 +11,10 @@
  * over the two nested blocks of every point.
  *
  * Parameters, in this order (the gradient array holds vif_grad_params(kind)):
- *   VIF_KERNEL_GNEITING:     sigma2, nugget, a, c, alpha, beta, gamma, tau
- *   VIF_KERNEL_MATERN_ANISO: sigma2, nugget, range_s, range_t   (nu fixed)
- * VIF_KERNEL_GNEITING_MATERN and inducing points (VIF) are not supported.
+ *   VIF_KERNEL_GNEITING:        sigma2, nugget, a, c, alpha, beta, gamma, tau
+ *   VIF_KERNEL_GNEITING_MATERN: sigma2, nugget, a, c, alpha, gamma, delta   (nu fixed)
+ *   VIF_KERNEL_MATERN_ANISO:    sigma2, nugget, range_s, range_t   (nu fixed)
+ * Inducing points (VIF) are not supported.
  *
  * Conventions as in vif.h: DEVICE arrays owned by the caller, work on the
  * caller's HIP stream, VIF_* status, argument errors found before any launch.

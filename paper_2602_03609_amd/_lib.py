@@ -339,6 +339,7 @@ def vif_profile_read():
 
 # ---------------------------------------------------------------- NLL gradient ----
 GRAD_PARAMS = {VIF_KERNEL_GNEITING: ("sigma2", "nugget", "a", "c", "alpha", "beta", "gamma", "tau"),
+               VIF_KERNEL_GNEITING_MATERN: ("sigma2", "nugget", "a", "c", "alpha", "gamma", "delta"),
                VIF_KERNEL_MATERN_ANISO: ("sigma2", "nugget", "range_s", "range_t")}
 
 

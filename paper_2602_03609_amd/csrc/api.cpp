@@ -1109,6 +1109,7 @@ extern "C" {
 
 int32_t vif_grad_params(int32_t kind) {
   if (kind == VIF_KERNEL_GNEITING) return 8;
+  if (kind == VIF_KERNEL_GNEITING_MATERN) return 7;
   if (kind == VIF_KERNEL_MATERN_ANISO) return 4;
   return 0;
 }
@@ -1140,7 +1141,7 @@ int32_t vif_nll_grad(const vif_points* p, const double* y, const vif_kernel* ker
   a.P = P;
   a.K = to_dev(kern);
   a.G.kind = kern->kind;
-  a.G.nu_code = kern->kind == VIF_KERNEL_MATERN_ANISO ? nu_code(kern->nu) : 0;
+  a.G.nu_code = kern->kind != VIF_KERNEL_GNEITING ? nu_code(kern->nu) : 0;
   a.G.sigma2 = kern->sigma2;
   a.G.a = kern->a;
   a.G.c = kern->c;
@@ -1149,6 +1150,7 @@ int32_t vif_nll_grad(const vif_points* p, const double* y, const vif_kernel* ker
   a.G.gamma = kern->gamma;
   a.G.bg = kern->beta * kern->gamma;
   a.G.tau = kern->tau;
+  a.G.delta = kern->delta;
   if (kern->kind == VIF_KERNEL_MATERN_ANISO) {
     a.G.ir_s2 = 1.0 / (kern->range_s * kern->range_s);
     a.G.ir_t2 = 1.0 / (kern->range_t * kern->range_t);

@@ -213,7 +213,7 @@ hipError_t launch_resid_topm(const ResidArgs& a, hipStream_t s);
 constexpr int kGradMaxParams = 8;
 struct GradKern {  // hyperparameters in the form the derivative code uses
   int kind, nu_code;
-  double sigma2, a, c, two_alpha, beta, gamma, bg, tau, ir_s2, ir_t2, inv_rs, inv_rt;
+  double sigma2, a, c, two_alpha, beta, gamma, bg, tau, delta, ir_s2, ir_t2, inv_rs, inv_rt;
 };
 struct GradArgs {
   int64_t n;

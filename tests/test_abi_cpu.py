@@ -204,19 +204,24 @@ def test_residual_argument_errors():
 def test_gradient_argument_errors():
     import paper_2602_03609_amd._lib as L
     lib = L.load()
-    assert lib.vif_grad_params(1) == 8 and lib.vif_grad_params(3) == 4 and lib.vif_grad_params(2) == 0
+    assert lib.vif_grad_params(1) == 8 and lib.vif_grad_params(2) == 7
+    assert lib.vif_grad_params(3) == 4 and lib.vif_grad_params(9) == 0
     assert lib.vif_grad_ws(0) == 0 and lib.vif_grad_ws(1000) > 0
     K = L.make_kernel({"kind": 2, "sigma2": 1.0, "nugget": 0.1, "a": 0.5, "c": 20.0, "alpha": 0.4,
-                       "gamma": 0.4, "delta": 0.2, "nu": 1.5})
+                       "gamma": 0.4, "delta": 0.2, "nu": 1.0})
     P = L.Points()
     P.n = 10
     P.sx = P.sy = P.t = ctypes.c_void_p(0x1000)
     out = ctypes.c_double()
     g = (ctypes.c_double * 8)()
-    st = lib.vif_nll_grad(ctypes.byref(P), ctypes.c_void_p(0x1000), ctypes.byref(K), 5,
-                          ctypes.c_void_p(0x1000), ctypes.byref(out), g, ctypes.c_void_p(0x1000),
-                          lib.vif_grad_ws(10), None)
-    assert st == L.VIF_E_UNSUPPORTED
+
+    def call(y=ctypes.c_void_p(0x1000)):
+        return lib.vif_nll_grad(ctypes.byref(P), y, ctypes.byref(K), 5, ctypes.c_void_p(0x1000),
+                                ctypes.byref(out), g, ctypes.c_void_p(0x1000), lib.vif_grad_ws(10), None)
+
+    assert call() == L.VIF_E_UNSUPPORTED          # nu without a closed form
+    K.nu = 1.5
+    assert call(y=None) == L.VIF_E_ARG
 
 
 def test_bench_refuses_more_than_one_gpu():

@@ -1,5 +1,6 @@
 """Gradient of the Vecchia NLL (include/vif_grad.h) against the FP64 oracle.
 
+Cases cover the three kernel families (Gneiting-Matern at nu = 1/2, 3/2, 5/2).
 Bars (all arithmetic is FP64 on both sides; only the order of operations
 differs): NLL within 1e-10 relative of the oracle and of vif_nll; every
 gradient entry within 1e-8 of the largest entry's magnitude. Repeated calls
@@ -16,10 +17,13 @@ from tests.gpu_util import dev, lib, log, problem_on_device, rel, torch_cuda
 pytestmark = pytest.mark.gpu
 
 
-def _kern(kind):
+def _kern(kind, nu=1.5):
     if kind == 1:
         return synth.kern_gneiting(sigma2=1.3, a=0.7, c=15.0, alpha=0.6, beta=0.4, gamma=0.45,
                                    tau=1.2, nugget=0.08)
+    if kind == 2:
+        return synth.kern_gneiting_matern(sigma2=1.1, a=0.6, c=8.0, alpha=0.45, gamma=0.35,
+                                          delta=0.3, nu=nu, nugget=0.06)
     return synth.kern_matern_aniso(range_s=0.25, range_t=2.5, sigma2=0.9, nugget=0.07, nu=1.5)
 
 
@@ -27,6 +31,9 @@ CASES = {
     "gneit_m6": (1, dict(seed=51, n_sites=150, n_times=5, k=0, m=6, kind=1)),
     "gneit_m30": (1, dict(seed=52, n_sites=200, n_times=5, k=0, m=30, kind=1)),
     "gneit_m40": (1, dict(seed=53, n_sites=120, n_times=6, k=0, m=40, kind=1)),
+    "gm_nu05_m12": ((2, 0.5), dict(seed=57, n_sites=150, n_times=5, k=0, m=12, kind=2)),
+    "gm_nu15_m30": ((2, 1.5), dict(seed=58, n_sites=160, n_times=6, k=0, m=30, kind=2)),
+    "gm_nu25_m50": ((2, 2.5), dict(seed=59, n_sites=110, n_times=6, k=0, m=50, kind=2)),
     "aniso_m10": (3, dict(seed=54, n_sites=200, n_times=6, k=0, m=10, kind=3)),
     "aniso_m63": (3, dict(seed=55, n_sites=100, n_times=7, k=0, m=63, kind=3)),
 }
@@ -38,7 +45,7 @@ def test_gradient_matches_oracle(name):
     vif = lib()
     kind, cfg = CASES[name]
     d = synth.config_small(**cfg)
-    kern = _kern(kind)
+    kern = _kern(*kind) if isinstance(kind, tuple) else _kern(kind)
     X = (d["sx"], d["sy"], d["t"])
     m = cfg["m"]
     nbr = NB.brute_force(kern, *X, m)
