@@ -351,27 +351,57 @@ __device__ __forceinline__ void offer(double key, int j, bool valid, double& K, 
   }
 }
 
-// Key and offer the candidates of cells xa..xb of row cy (one CSR range).
+// Key and offer the candidates of ring r around cell (qcx, qcy) of one slab: the
+// top and bottom rows of the ring as one CSR range each, the rows between as
+// their two end cells. The ranges (wave-uniform bounds) fill 64-lane chunks one
+// after another, a chunk spanning several ranges, and the last chunk of the ring
+// is offered partly filled, so the ring's candidates take as few offers as their
+// count allows.
 template <int MODE>
-__device__ __forceinline__ void scan_run(const NbrArgs& A, const GridArgs& G, const int32_t* off,
-                                         int cy, int xa, int xb, double qx, double qy, double t1,
-                                         double t2, int jmax, double& K, int& I, int& cnt,
-                                         double& thr, int& thr_i, int lane, int m) {
-  const int beg = off[cy * G.gx + xa];
-  const int end = off[cy * G.gx + xb + 1];
-  for (int base = beg; base < end; base += 64) {
-    const int p = base + lane;
-    const bool inrun = p < end;
+__device__ __forceinline__ void scan_ring(const NbrArgs& A, const GridArgs& G, const int32_t* off,
+                                          int qcx, int qcy, int r, double qx, double qy, double t1,
+                                          double t2, int jmax, double& K, int& I, int& cnt,
+                                          double& thr, int& thr_i, int lane, int m) {
+  int p = -1;      // this lane's candidate position in the CSR arrays, -1 if none
+  int filled = 0;  // lanes of the current chunk already assigned
+  auto flush = [&]() {
+    const bool inrun = p >= 0;
     const int j = inrun ? G.pidx[p] : INT_MAX;
     const bool valid = inrun && j < jmax;
     double key = -INFINITY;
     if (valid) key = rank_key<MODE>(G.px[p] - qx, G.py[p] - qy, t1, t2, A);
     offer(key, j, valid, K, I, cnt, thr, thr_i, lane, m);
+    p = -1;
+    filled = 0;
+  };
+  auto add = [&](int beg, int end) {
+    while (beg < end) {
+      const int take = end - beg < 64 - filled ? end - beg : 64 - filled;
+      if (lane >= filled && lane < filled + take) p = beg + (lane - filled);
+      filled += take;
+      beg += take;
+      if (filled == 64) flush();
+    }
+  };
+  const int y0 = qcy - r, y1 = qcy + r;
+  const int ya = y0 < 0 ? 0 : y0, yb = y1 >= G.gy ? G.gy - 1 : y1;
+  const int xa = qcx - r < 0 ? 0 : qcx - r, xb = qcx + r >= G.gx ? G.gx - 1 : qcx + r;
+  for (int cy = ya; cy <= yb; ++cy) {
+    const int32_t* o = off + cy * G.gx;
+    if (cy == y0 || cy == y1) {
+      add(o[xa], o[xb + 1]);  // top or bottom row of the ring: one contiguous run
+    } else {
+      if (qcx - r >= 0) add(o[qcx - r], o[qcx - r + 1]);
+      if (qcx + r < G.gx) add(o[qcx + r], o[qcx + r + 1]);
+    }
   }
+  if (filled > 0) flush();
 }
 
+// One wavefront per query; the register budget is held to seven waves per SIMD
+// (measured faster than six, and eight spills).
 template <int MODE>
-__global__ __launch_bounds__(256) void neighbors_grid_kernel(NbrArgs A, GridArgs G) {
+__global__ __launch_bounds__(256, 7) void neighbors_grid_kernel(NbrArgs A, GridArgs G) {
   const int lane = threadIdx.x & 63;
   const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (w >= A.n) return;  // uniform per wave
@@ -409,24 +439,8 @@ __global__ __launch_bounds__(256) void neighbors_grid_kernel(NbrArgs A, GridArgs
           if (bound_key<MODE>(ds, t1, t2, A) < thr) break;
         }
       }
-      const int y0 = qcy - r, y1 = qcy + r;
-      const int ya = y0 < 0 ? 0 : y0, yb = y1 >= G.gy ? G.gy - 1 : y1;
-      for (int cy = ya; cy <= yb; ++cy) {
-        if (cy == y0 || cy == y1) {
-          // top or bottom row of the ring: one contiguous run of cells
-          scan_run<MODE>(A, G, off, cy, qcx - r < 0 ? 0 : qcx - r,
-                         qcx + r >= G.gx ? G.gx - 1 : qcx + r, qx, qy, t1, t2, jmax, K, I, cnt, thr,
-                         thr_i, lane, m);
-        } else {
-          // rows in between: the two cells at the ring's left and right ends
-          if (qcx - r >= 0)
-            scan_run<MODE>(A, G, off, cy, qcx - r, qcx - r, qx, qy, t1, t2, jmax, K, I, cnt, thr,
-                           thr_i, lane, m);
-          if (qcx + r < G.gx)
-            scan_run<MODE>(A, G, off, cy, qcx + r, qcx + r, qx, qy, t1, t2, jmax, K, I, cnt, thr,
-                           thr_i, lane, m);
-        }
-      }
+      scan_ring<MODE>(A, G, off, qcx, qcy, r, qx, qy, t1, t2, jmax, K, I, cnt, thr, thr_i, lane,
+                      m);
     }
   }
   if (lane < m) A.nbr[i * m + lane] = lane < cnt ? I : -1;
