@@ -107,8 +107,10 @@ struct Layout {
 // [4] time flags (uint32).
 constexpr size_t kFlagBytes = 256;
 
-// Average number of points of one time slab per grid cell of the neighbor index.
-constexpr double kCellTarget = 32.0;
+// Average number of points of one time slab per grid cell of the neighbor index
+// (search time on a 1.1M-point network of 365 daily slabs: 16 -> 4.62 ms, 24 -> 4.65,
+// 32 -> 4.74, 64 -> 5.22).
+constexpr double kCellTarget = 16.0;
 
 Layout make_layout(int64_t n, int m, int k, int prec, int op, int chunk_rows = 4096) {
   Layout L;
