@@ -924,14 +924,21 @@ __global__ __launch_bounds__(256) void syrk_split_reduce_kernel(int k, int kpad,
   int TI, TJ;
   tile_of(t, TI, TJ);
   const int er = e / TB, ec = e - (e / TB) * TB;
-  const int es = (TI == TJ && er < ec) ? ec * TB + er : e;
-  const float* src = part + (int64_t)t * (TB * TB) + es;
+  // A diagonal tile's upper triangle (its upper-right quarter is not computed) is
+  // written by the thread of the mirrored lower entry, so every thread reads its
+  // own entry's partials, contiguous across the block.
+  const bool diag = TI == TJ;
+  if (diag && er < ec) return;
+  const float* src = part + (int64_t)t * (TB * TB) + e;
   const int64_t stride = (int64_t)ntile * (TB * TB);
   double s = 0.0;
 #pragma unroll 8
   for (int cc = 0; cc < nchunk; ++cc) s += (double)src[cc * stride];
   const int r = TI * TB + er, col = TJ * TB + ec;
-  if (r < kpad && col < kpad) M[(int64_t)r * kpad + col] = augmented_entry(r, col, k, s);
+  if (r < kpad && col < kpad) {
+    M[(int64_t)r * kpad + col] = augmented_entry(r, col, k, s);
+    if (diag && er > ec) M[(int64_t)col * kpad + r] = augmented_entry(col, r, k, s);
+  }
   if (r == k && col < k) q[col] = s;
   if (r == k && col == k) *zz = s;
 }
