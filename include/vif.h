@@ -151,7 +151,7 @@ int32_t vif_nll_terms(const vif_points* p, const double* y, const vif_kernel* ke
                       double* terms, void* ws, size_t ws_bytes, void* hip_stream);
 
 /* vif_neighbors followed by vif_nll on its output, in one call: the neighbor
- * search (Alg. 2) runs on a library-owned non-blocking stream of the current
+ * search (Alg. 2) runs on a library-owned non-blocking stream of hip_stream's
  * device (default priority) while hip_stream builds Sigma_k and U, and the
  * per-point stage waits for it. nbr (DEVICE int32 [n*m], written) and the NLL
  * are bit-identical to the two separate calls. Workspace:

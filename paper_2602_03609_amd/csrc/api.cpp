@@ -702,20 +702,37 @@ struct SideStream {
 
 constexpr int kMaxDevices = 64;
 
-// The current device's side stream and events, created on first use.
-int32_t side_stream(SideStream** out) {
+// The side stream and events of the device that runs `main` (the current device
+// for the null stream), created on first use with that device current.
+int32_t side_stream(hipStream_t main, SideStream** out) {
   static SideStream slots[kMaxDevices];
   int dev = 0;
-  HIPCHK(hipGetDevice(&dev));
+  if (main) {
+    hipDevice_t d = 0;
+    HIPCHK(hipStreamGetDevice(main, &d));
+    dev = (int)d;
+  } else {
+    HIPCHK(hipGetDevice(&dev));
+  }
   if (dev < 0 || dev >= kMaxDevices) return fail(VIF_E_UNSUPPORTED, "device index %d", dev);
   SideStream* ss = &slots[dev];
   std::lock_guard<std::mutex> lock(ss->mu);
   if (!ss->s) {
+    int cur = 0;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != dev) HIPCHK(hipSetDevice(dev));
     hipStream_t st = nullptr;
     hipEvent_t a = nullptr, b = nullptr;
-    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&a, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&b, hipEventDisableTiming));
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&a, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      if (b) (void)hipEventDestroy(b);
+      if (a) (void)hipEventDestroy(a);
+      if (st) (void)hipStreamDestroy(st);
+    }
+    if (cur != dev) HIPCHK(hipSetDevice(cur));
+    if (e != hipSuccess) return fail(VIF_E_DEVICE, "side stream set-up: %s", hipGetErrorString(e));
     ss->s = st;
     ss->fork = a;
     ss->done = b;
@@ -801,7 +818,7 @@ int32_t vif_neighbors_nll(const vif_points* p, const double* y, const vif_kernel
   if (m == 0)
     return nll_impl(p, y, kern, 0, nullptr, ind, prec, nll, nullptr, ws + off, ws_bytes - off, hip_stream);
   SideStream* ss = nullptr;
-  if ((st = side_stream(&ss))) return st;
+  if ((st = side_stream(s, &ss))) return st;
   std::lock_guard<std::mutex> lock(ss->mu);
   SearchSetup S;
   if ((st = search_setup(p, kern, m, nbr, ws, Ln, s, &S))) return st;
