@@ -66,8 +66,6 @@ __device__ __forceinline__ void matern_g_xdg(int nu_code, double x, double& g, d
 __device__ __forceinline__ double cov_and_grad(const GradKern& G, double dx, double dy, double dt,
                                                double dC[kGradMaxParams]) {
   const double h2 = dx * dx + dy * dy;
-#pragma unroll
-  for (int pp = 0; pp < kGradMaxParams; ++pp) dC[pp] = 0.0;
   if (G.kind == 2) {
     // C = amp g(x), amp = sigma2 psi^-(delta + gamma), x = c |ds| psi^(-gamma/2);
     // with X = x g'(x): dC/dc = amp X / c, dC/dgamma = -C log psi - amp X log psi / 2,
@@ -84,11 +82,13 @@ __device__ __forceinline__ double cov_and_grad(const GradKern& G, double dx, dou
     const double C = amp * g;
     const double dpsi = (-(G.delta + G.gamma) * C - 0.5 * G.gamma * amp * X) / psi;
     dC[0] = C / G.sigma2;
+    dC[1] = 0.0;
     dC[2] = dpsi * ta;
     dC[3] = amp * X / G.c;
     dC[4] = dpsi * G.a * ta * 2.0 * ldt;
     dC[5] = -C * lp - 0.5 * amp * X * lp;
     dC[6] = -C * lp;
+    dC[7] = 0.0;
     return C;
   }
   if (G.kind == 3) {
@@ -111,6 +111,8 @@ __device__ __forceinline__ double cov_and_grad(const GradKern& G, double dx, dou
     dC[1] = 0.0;
     dC[2] = G.sigma2 * fp * (-h2 * G.ir_s2 * G.inv_rs) * inv_d;
     dC[3] = G.sigma2 * fp * (-dt * dt * G.ir_t2 * G.inv_rt) * inv_d;
+#pragma unroll
+    for (int pp = 4; pp < kGradMaxParams; ++pp) dC[pp] = 0.0;
     return C;
   }
   const double adt = fabs(dt);
