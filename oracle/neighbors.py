@@ -24,9 +24,15 @@ Readings taken where the paper is silent:
         MATERN_ANISO      key = -((u*u + v*v) + w*w),  u = dx/range_s, ...
                           (minus the squared anisotropic distance; the Matern
                           correlation is decreasing in the distance)
-    with psi_l = a * l^(2 alpha) + 1 at integer lag l = t_i - t_j.
+    with psi_l = a * l^(2 alpha) + 1 at the time lag l = t_i - t_j >= 0.
     The key equals log rho (or a monotone function of it at fixed lag), so
     ranking by key ranks by |rho| for these positive kernels.
+
+Times t_i are real (Sec. "Spatio-temporal Gaussian process model"). The two
+lag-only factors of the key depend on the pair only through l; they come from
+the C math library once per distinct lag -- a table over l = 0, 1, ... when
+every time is an integer, otherwise per distinct value of t_i - t_j (the FP64
+difference), with the same operations.
 """
 from __future__ import annotations
 
@@ -47,48 +53,62 @@ def key_is_exact(kern):
     return True
 
 
-def lag_tables(kern, max_lag):
-    """Per-lag factors (tab1, tab2) for l = 0..max_lag, from the C math library."""
+def lag_factors(kern, lag):
+    """Lag-only factors (f1, f2) of the key at time lag `lag` >= 0, from the C
+    math library (Python's math module)."""
     kind = kern["kind"]
-    tab1 = np.zeros(max_lag + 1)
-    tab2 = np.zeros(max_lag + 1)
     if kind == MATERN_ANISO:
         ir_t = 1.0 / kern["range_t"]
-        for lag in range(max_lag + 1):
-            w = float(lag) * ir_t
-            tab1[lag] = w * w
-        return tab1, tab2
-    a, two_alpha = kern["a"], 2.0 * kern["alpha"]
+        w = float(lag) * ir_t
+        return w * w, 0.0
+    psi = kern["a"] * math.pow(float(lag), 2.0 * kern["alpha"]) + 1.0
+    if kind == GNEITING:
+        return kern["tau"] * math.log(psi), kern["c"] * math.pow(psi, -(kern["beta"] * kern["gamma"]))
+    if kind == GNEITING_MATERN:
+        return ((kern["delta"] + kern["gamma"]) * math.log(psi),
+                kern["c"] * math.pow(psi, -(kern["gamma"] / 2.0)))
+    raise ValueError(kind)
+
+
+def lag_tables(kern, max_lag):
+    """Per-lag factors (tab1, tab2) for the integer lags l = 0..max_lag."""
+    tab1 = np.zeros(max_lag + 1)
+    tab2 = np.zeros(max_lag + 1)
     for lag in range(max_lag + 1):
-        psi = a * math.pow(float(lag), two_alpha) + 1.0
-        if kind == GNEITING:
-            tab1[lag] = kern["tau"] * math.log(psi)
-            tab2[lag] = kern["c"] * math.pow(psi, -(kern["beta"] * kern["gamma"]))
-        elif kind == GNEITING_MATERN:
-            tab1[lag] = (kern["delta"] + kern["gamma"]) * math.log(psi)
-            tab2[lag] = kern["c"] * math.pow(psi, -(kern["gamma"] / 2.0))
-        else:
-            raise ValueError(kind)
+        tab1[lag], tab2[lag] = lag_factors(kern, lag)
     return tab1, tab2
 
 
+def integer_times(t):
+    return bool(np.all(t == np.round(t)))
+
+
 def keys(kern, tabs, sx, sy, t, i, js):
-    """Ranking keys of candidates js for query i (larger = more correlated)."""
-    tab1, tab2 = tabs
+    """Ranking keys of candidates js for query i (larger = more correlated).
+
+    tabs = (tab1, tab2) indexed by integer lag, or None: factors per distinct
+    lag value (real times)."""
     dx = sx[js] - sx[i]
     dy = sy[js] - sy[i]
-    lag = (t[i] - t[js]).astype(np.int64)
+    tau = t[i] - t[js]
+    if tabs is None:
+        lags, inv = np.unique(tau, return_inverse=True)
+        f = np.array([lag_factors(kern, v) for v in lags], dtype=np.float64).reshape(-1, 2)
+        f1, f2 = f[inv.reshape(-1), 0], f[inv.reshape(-1), 1]
+    else:
+        lag = tau.astype(np.int64)
+        f1, f2 = tabs[0][lag], tabs[1][lag]
     kind = kern["kind"]
     if kind == MATERN_ANISO:
         ir_s = 1.0 / kern["range_s"]
         u = dx * ir_s
         v = dy * ir_s
-        return -(tab1[lag] + (u * u + v * v))
+        return -(f1 + (u * u + v * v))
     h2 = dx * dx + dy * dy
     if kind == GNEITING:
         g = np.sqrt(h2) if kern["gamma"] == 0.5 else np.power(h2, kern["gamma"])
-        return -(tab1[lag] + g * tab2[lag])
-    x = np.sqrt(h2) * tab2[lag]
+        return -(f1 + g * f2)
+    x = np.sqrt(h2) * f2
     nu = kern["nu"]
     if nu == 0.5:
         s = x
@@ -98,14 +118,16 @@ def keys(kern, tabs, sx, sy, t, i, js):
         s = np.maximum(x - np.log1p(x + x * x / 3.0), 0.0)
     else:
         raise ValueError("nu must be 0.5, 1.5 or 2.5")
-    return -(tab1[lag] + s)
+    return -(f1 + s)
 
 
-def _check_times(t):
+def _check_times(t, integer=False):
+    if not np.all(np.isfinite(t)):
+        raise ValueError("times must be finite")
     if np.any(np.diff(t) < 0):
         raise ValueError("times must be nondecreasing in index")
-    if np.any(t != np.round(t)):
-        raise ValueError("neighbor search requires integer-valued times")
+    if integer and not integer_times(t):
+        raise ValueError("the lag-pruned search takes integer-valued times")
 
 
 def _rank(keys_, js, m):
@@ -113,13 +135,16 @@ def _rank(keys_, js, m):
     return js[order[:m]], keys_[order[:m]]
 
 
-def brute_force(kern, sx, sy, t, m, rows=None):
-    """Rank all j < i for each query row; returns int32 [len(rows), m] with -1 padding."""
+def brute_force(kern, sx, sy, t, m, rows=None, general=False):
+    """Rank all j < i for each query row; returns int32 [len(rows), m] with -1 padding.
+
+    general=True takes the per-distinct-lag factors even for integer times."""
     _check_times(t)
     n = sx.shape[0]
     rows = np.arange(n) if rows is None else np.asarray(rows)
-    max_lag = int(t[-1] - t[0]) if n else 0
-    tabs = lag_tables(kern, max_lag)
+    tabs = None
+    if n and not general and integer_times(t):
+        tabs = lag_tables(kern, int(t[-1] - t[0]))
     out = np.full((rows.shape[0], m), -1, dtype=np.int32)
     for r, i in enumerate(rows):
         if i == 0 or m == 0:
@@ -138,8 +163,9 @@ def lag_pruned(kern, sx, sy, t, m, rows=None):
     nonnegative and IEEE addition is monotone), so after suffix maximisation the
     bound holds for every larger lag as well. Scanning continues while the bound
     equals the m-th key, since a lower index could still win the tie.
+    Integer times only (slabs are the integer time points).
     """
-    _check_times(t)
+    _check_times(t, integer=True)
     n = sx.shape[0]
     rows = np.arange(n) if rows is None else np.asarray(rows)
     out = np.full((rows.shape[0], m), -1, dtype=np.int32)
