@@ -71,6 +71,9 @@ enum { VIF_KERNEL_GNEITING = 1, VIF_KERNEL_GNEITING_MATERN = 2, VIF_KERNEL_MATER
  * BF16X3: as FP32, but the three contractions run on BF16 MFMA with each FP32
  *   operand split in two bf16 terms, x = h + l, and the products
  *   h*h + h*l + l*h accumulated in FP32 (about 16 significant bits per product).
+ *   The diagonal 16x16 tiles of the Gram U_S U_S' and the diagonal tiles of M
+ *   add l*l: on a diagonal it is a sum of squares, and dropping it would bias
+ *   every squared row norm low and every residual variance high.
  * BF16X6: as BF16X3 for U; the Gram and M, whose results enter the likelihood
  *   through cancellation (C - U_S U_S' and z'z - q'M^-1 q), split each operand
  *   in three bf16 terms and accumulate the six products down to 2^-24.

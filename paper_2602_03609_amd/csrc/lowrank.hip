@@ -870,6 +870,11 @@ __global__ __launch_bounds__(256, 2) void syrk_split_kernel(int64_t nrows, int k
             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a][2], bv[b][0], acc[a][b], 0, 0, 0);
             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a][1], bv[b][1], acc[a][b], 0, 0, 0);
             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a][0], bv[b][2], acc[a][b], 0, 0, 0);
+          } else if (diag) {
+            // Diagonal tiles keep the low-by-low product: on the diagonal it
+            // is a sum of squares, so dropping it would bias every column
+            // norm of W low.
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a][1], bv[b][1], acc[a][b], 0, 0, 0);
           }
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a][1], bv[b][0], acc[a][b], 0, 0, 0);
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a][0], bv[b][1], acc[a][b], 0, 0, 0);

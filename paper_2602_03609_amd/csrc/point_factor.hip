@@ -579,6 +579,12 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
                 acc[s2][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][2], part[tj][0], acc[s2][t], 0, 0, 0);
                 acc[s2][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][1], part[tj][1], acc[s2][t], 0, 0, 0);
                 acc[s2][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][0], part[tj][2], acc[s2][t], 0, 0, 0);
+              } else if (ti == tj) {
+                // The dropped low-by-low product is a sum of squares on the
+                // diagonal (it would bias every |U_r|^2 low by about 2^-18
+                // relative, and with it every residual variance high); the
+                // diagonal tiles keep it, so their entries are (h + l)(h + l).
+                acc[s2][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][1], part[tj][1], acc[s2][t], 0, 0, 0);
               }
               acc[s2][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][1], part[tj][0], acc[s2][t], 0, 0, 0);
               acc[s2][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][0], part[tj][1], acc[s2][t], 0, 0, 0);

@@ -19,8 +19,7 @@ from tests.gpu_util import dev, lib, log, problem_on_device, rel, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
-# BF16X3 misses 1e-5 on some problems (a known, documented miss); 1e-4 is its bar.
-NLL_TOL = {"fp64": 1e-8, "fp32": 1e-5, "bf16x6": 1e-5, "bf16x3": 1e-4}
+NLL_TOL = {"fp64": 1e-8, "fp32": 1e-5, "bf16x6": 1e-5, "bf16x3": 1e-5}
 
 
 def _small_problems():

@@ -20,7 +20,7 @@ from tests.gpu_util import lib, log, problem_on_device, rel, torch_cuda
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_cfg3.json")
-NLL_TOL = {"fp64": 1e-8, "fp32": 1e-5, "bf16x6": 1e-5, "bf16x3": 1e-4}
+NLL_TOL = {"fp64": 1e-8, "fp32": 1e-5, "bf16x6": 1e-5, "bf16x3": 1e-5}
 
 
 def _golden():
