@@ -165,6 +165,24 @@ int32_t vif_neighbors_nll(const vif_points* p, const double* y, const vif_kernel
                           int32_t* nbr, const vif_points* ind, int32_t prec, double* nll, void* ws,
                           size_t ws_bytes, void* hip_stream);
 
+/* Bytes of the device array that vif_neighbors_noalloc uses as its workspace
+ * (64 MiB; enough for the neighbor search of about 1.3 million points). */
+#define VIF_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* vif_neighbors without a workspace argument, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc). Same arguments, result and errors as
+ * vif_neighbors, bit-identical output. Its workspace is a file-scope device
+ * array of VIF_NOALLOC_SCRATCH_BYTES that every GPU the library runs on holds
+ * from the first call on that GPU until the process ends; the call allocates
+ * nothing. Returns VIF_E_WORKSPACE, before any launch, when
+ * vif_workspace_bytes(n, m, 0, VIF_PREC_FP64, VIF_OP_NEIGHBORS) exceeds that
+ * size. All calls on one GPU share the array: calls that overlap in time on
+ * one GPU (several host threads, or several streams) race and must not be
+ * issued. */
+int32_t vif_neighbors_noalloc(const vif_points* p, const vif_kernel* kern, int32_t m, int32_t* nbr,
+                              void* hip_stream);
+
 /* Message for the last error on the calling thread ("" after success). The
  * pointer stays valid until the next call on this thread. */
 const char* vif_last_error(void);

@@ -32,6 +32,7 @@ from ._lib import (  # noqa: F401
     vif_mlp_pair_loss,
     vif_neighbors,
     vif_neighbors_nll,
+    vif_neighbors_noalloc,
     vif_nll,
     vif_nll_grad,
     vif_nll_terms,

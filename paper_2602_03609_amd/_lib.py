@@ -30,7 +30,7 @@ EXPORTS = ("vif_workspace_bytes", "vif_neighbors", "vif_factor", "vif_nll", "vif
            "vif_batch_enqueue", "vif_batch_graph_launch", "vif_batch_autotune",
            "vif_batch_schedule", "vif_batch_set_schedule", "vif_batch_status",
            "vif_batch_destroy", "vif_residual_ws", "vif_residual_neighbors",
-           "vif_grad_params", "vif_grad_ws", "vif_nll_grad")
+           "vif_grad_params", "vif_grad_ws", "vif_nll_grad", "vif_neighbors_noalloc")
 BATCH_PLAN_SCRATCH = 16384
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 8, 64, 16, 9936
 STAGES = ("neighbors", "sigma_k", "crosscov", "trmm", "point_factor", "syrk", "assembly")
@@ -140,6 +140,8 @@ def load(path=LIB_PATH):
         lib.vif_grad_ws.restype = sz
         lib.vif_nll_grad.argtypes = [pP, vp, pK, i32, vp, pd, pd, vp, sz, vp]
         lib.vif_nll_grad.restype = i32
+        lib.vif_neighbors_noalloc.argtypes = [pP, pK, i32, vp, vp]
+        lib.vif_neighbors_noalloc.restype = i32
         lib.vif_batch_destroy.argtypes = [vp]
         lib.vif_batch_destroy.restype = None
         _lib = lib
@@ -239,6 +241,19 @@ def vif_neighbors(sx, sy, t, kern, m, nbr=None, stream=None):
     _check(lib.vif_neighbors(ctypes.byref(p), ctypes.byref(K), int(m),
                              _dev_ptr(nbr, torch.int32, "nbr") if m > 0 else None,
                              ws.data_ptr(), ws.numel(), _stream(stream)))
+    return nbr
+
+
+def vif_neighbors_noalloc(sx, sy, t, kern, m, nbr, stream=None):
+    """vif_neighbors with the library's static device scratch as workspace (no
+    allocation inside the call); nbr: int32 [n, m] CUDA tensor, written."""
+    torch = _torch()
+    lib = load()
+    p = make_points(sx, sy, t)
+    K = make_kernel(kern)
+    _check(lib.vif_neighbors_noalloc(ctypes.byref(p), ctypes.byref(K), int(m),
+                                     _dev_ptr(nbr, torch.int32, "nbr") if m > 0 else None,
+                                     _stream(stream)))
     return nbr
 
 

@@ -46,6 +46,14 @@ int32_t ok() {
     if (e_ != hipSuccess) return fail(VIF_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
+}  // namespace
+
+namespace vif {
+int32_t report_error(int32_t code, const char* msg) { return fail(code, "%s", msg); }
+}  // namespace vif
+
+namespace {
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // ---- optional stage timing: HIP events on the caller's stream ----------------

@@ -8,6 +8,9 @@
 
 namespace vif {
 
+// Records `msg` as the calling thread's last error (vif_last_error) and returns code.
+int32_t report_error(int32_t code, const char* msg);
+
 // ---- neighbor search --------------------------------------------------------
 // Key modes: 0 = -(tab1 + sqrt(h2)*tab2) (GNEITING gamma=1/2, GNEITING_MATERN nu=1/2)
 //            1 = -(tab1 + (u*u + v*v))     (MATERN_ANISO, u = dx/range_s)

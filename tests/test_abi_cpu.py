@@ -230,3 +230,22 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU only" in r.stderr
+
+
+def test_noalloc_neighbors_rejects_sizes_beyond_its_scratch():
+    """vif_neighbors_noalloc refuses, before any launch, an n whose search
+    workspace exceeds its static device scratch."""
+    import paper_2602_03609_amd._lib as L
+    lib = L.load()
+    K = L.make_kernel({"kind": 1, "sigma2": 1.0, "nugget": 0.1, "a": 0.5, "c": 20.0, "alpha": 0.75,
+                       "beta": 0.5, "gamma": 0.5, "tau": 1.0})
+    P = L.Points()
+    P.n = 50_000_000
+    P.sx = P.sy = P.t = ctypes.c_void_p(0x1000)
+    st = lib.vif_neighbors_noalloc(ctypes.byref(P), ctypes.byref(K), 10, ctypes.c_void_p(0x1000), None)
+    assert st == L.VIF_E_WORKSPACE and b"static scratch" in lib.vif_last_error()
+    st = lib.vif_neighbors_noalloc(None, ctypes.byref(K), 10, ctypes.c_void_p(0x1000), None)
+    assert st == L.VIF_E_ARG
+    P.n = 100
+    st = lib.vif_neighbors_noalloc(ctypes.byref(P), ctypes.byref(K), 64, ctypes.c_void_p(0x1000), None)
+    assert st == L.VIF_E_UNSUPPORTED
