@@ -244,7 +244,7 @@ struct GroupShape {
 };
 
 template <int ROWS, bool WANT_B, int PREC>
-__global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_kernel(FactorArgs A) {
+__global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 : 1)) void vif_group_kernel(FactorArgs A) {
   using Sh = GroupShape<ROWS, PREC>;
   using T = typename PrecT<PREC>::T;
   using UT = typename PrecT<PREC>::UT;
@@ -618,15 +618,13 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
   }
   __syncthreads();
 
-  // W-pass geometry (FP32 staging after the selection matrix S) and the loads of
-  // its first chunk, in flight during the per-point phase.
-  const int nup = (nu + 15) & ~15;
-  const int sst = nup + 1;
-  UT* sel = reinterpret_cast<UT*>(sBig);
+  // W-pass geometry (FP32 staging after the result tile of the split modes) and
+  // the loads of its first chunk, in flight during the per-point phase.
+  UT* wt = reinterpret_cast<UT*>(sBig);
   if constexpr (!WANT_B) {
     split_stage = false;
-    stage = sel + ((16 * sst + VPE - 1) / VPE) * VPE;
-    cw = pick_width(CAPB - (int)(stage - sel), nup);
+    stage = wt + ((GP * (4 * KC + VPE) + VPE - 1) / VPE) * VPE;
+    cw = pick_width(CAPB - (int)(stage - wt), nu);
     sld = cw + VPE;
     lppr = __builtin_ctz(cw / VPE);
     npieces = nu << lppr;
@@ -711,71 +709,81 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW)) void vif_group_k
     if (r == 0) sZ[pl] = active ? zi : T(0);
     __syncthreads();
 
-    // ---- W rows: W_group = S * U_union on MFMA ----
-    // S (16 x nu, zero beyond the group's points and the rows they use) holds each
-    // point's b_r at its rows' union slots; its row stride is odd against LDS banks.
-    for (int e = tid; e < 16 * sst; e += NTH) sel[e] = UT(0);
-    for (int e = tid; e < (nup - nu) * sld; e += NTH) stage[nu * sld + e] = UT(0);
+    // ---- W rows: W_i = sum_r b_r U_{S_r}, gathered from the staged union rows ----
+    // An item is one point and one 16-byte piece of the staged chunk; each term is
+    // one LDS read of a staged piece and VPE fused multiply-adds in the precision
+    // of U (no products with the zeros of a dense selection matrix). The term's
+    // row offset and b_r are read from LDS (the same address for the lanes of one
+    // point); rows a point does not use have b_r = 0 and offset 0.
+    constexpr int JI = (GP * (4 * KC / VPE) + NTH - 1) / NTH;  // items per thread, widest chunk
+    typedef UT piece_t __attribute__((ext_vector_type(VPE)));
+    const int nq = cw / VPE;
+    const int items = GP * nq;
+    {
+      const int sl = sSlot[pl][r];
+      sSlot[pl][r] = sl >= 0 ? sl * sld : 0;
+      if (sl < 0) sBv[pl][r] = T(0);
+    }
     __syncthreads();
-    if (active && r < q) sel[pl * sst + sSlot[pl][r]] = (UT)sBv[pl][r];
     UT* W = reinterpret_cast<UT*>(A.W);
+    const int wst = cw + VPE;  // row stride of the result tile
     auto w_chunk = [&](int kc) __attribute__((always_inline)) {
-      const int ncb = cw >> 4;
-      for (int cb = wave; cb < ncb; cb += NW) {
-        // union rows padded to a multiple of 16 with zeros (S and the staged rows),
-        // four K steps per iteration on two independent accumulators
-        AccT aw0 = AccT{0, 0, 0, 0}, aw1 = AccT{0, 0, 0, 0};
-        const int col = cb * 16 + rr16;
-        for (int u0 = 0; u0 < nup; u0 += 16) {
-          UT av[4], bv[4];
 #pragma unroll
-          for (int q4 = 0; q4 < 4; ++q4) {
-            const int u = u0 + 4 * q4 + kq;
-            av[q4] = sel[rr16 * sst + u];
-            bv[q4] = stage[u * sld + col];
+      for (int j = 0; j < JI; ++j) {
+        const int it = tid + j * NTH;
+        if (it < items) {
+          const int pp = it / nq, cq = it - pp * nq;
+          piece_t acc = piece_t{};
+          const UT* src = stage + cq * VPE;
+          // eight terms at a time: their reads in flight together
+#pragma unroll
+          for (int r0 = 0; r0 < ROWS; r0 += 8) {
+            piece_t v[8];
+            UT bb[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              v[e] = *reinterpret_cast<const piece_t*>(src + sSlot[pp][r0 + e]);
+              bb[e] = (UT)sBv[pp][r0 + e];
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc += bb[e] * v[e];
           }
+          if constexpr (SPLIT) {
+            *reinterpret_cast<piece_t*>(wt + pp * wst + cq * VPE) = acc;
+          } else {
+            const int64_t ip = sI[pp];
+            if (ip >= 0) {
 #pragma unroll
-          for (int q4 = 0; q4 < 4; q4 += 2) {
-            if constexpr (PREC == 0) {
-              aw0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q4], bv[q4], aw0, 0, 0, 0);
-              aw1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q4 + 1], bv[q4 + 1], aw1, 0, 0, 0);
-            } else {
-              aw0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q4], bv[q4], aw0, 0, 0, 0);
-              aw1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q4 + 1], bv[q4 + 1], aw1, 0, 0, 0);
+              for (int e = 0; e < VPE; ++e)
+                if (kc + cq * VPE + e == A.k) acc[e] = (UT)sZ[pp];
+              *reinterpret_cast<piece_t*>(W + ip * A.ldu + kc + cq * VPE) = acc;
             }
           }
         }
-        const AccT aw = aw0 + aw1;
-        if constexpr (SPLIT) {
-          // Lane holds rows 4kq..4kq+3 of column col: one 8-byte piece per term plane.
-          if (4 * kq < GP) {
-            const int64_t row0 = g * GP + 4 * kq;
-            f4v v;
+      }
+      if constexpr (SPLIT) {
+        // Rows 4h .. 4h + 3 of one column from the tile: one 8-byte piece per term plane
+        // in the 8-row blocks of the W planes (rows in processing order).
+        __syncthreads();
+        __bf16* Wp = reinterpret_cast<__bf16*>(A.W);
+        for (int e = tid; e < cw * (GP / 4); e += NTH) {
+          const int col = e % cw, h = e / cw;
+          const int64_t row0 = g * GP + 4 * h;
+          f4v v;
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-              v[e] = (kc + col == A.k) ? (float)sZ[4 * kq + e] : (float)aw[e];
-            __bf16* Wp = reinterpret_cast<__bf16*>(A.W);
+          for (int q4 = 0; q4 < 4; ++q4)
+            v[q4] = (kc + col == A.k) ? (float)sZ[4 * h + q4] : (float)wt[(4 * h + q4) * wst + col];
 #pragma unroll
-            for (int sp = 0; sp < NSP; ++sp) {
-              bf4v hv;
+          for (int sp = 0; sp < NSP; ++sp) {
+            bf4v hv;
 #pragma unroll
-              for (int e = 0; e < 4; ++e) {
-                const __bf16 h = (__bf16)v[e];
-                hv[e] = h;
-                v[e] -= (float)h;
-              }
-              *reinterpret_cast<bf4v*>(
-                  Wp + ((sp * A.wrb + (row0 >> 3)) * A.ldu + kc + col) * 8 + (row0 & 7)) = hv;
+            for (int q4 = 0; q4 < 4; ++q4) {
+              const __bf16 hb = (__bf16)v[q4];
+              hv[q4] = hb;
+              v[q4] -= (float)hb;
             }
-          }
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int pp = PREC == 0 ? mfma16_row_f64(lane, e) : mfma16_row_f32acc(lane, e);
-            if (pp < GP) {
-              const int64_t ip = sI[pp];
-              if (ip >= 0) W[ip * A.ldu + kc + col] = (kc + col == A.k) ? (UT)sZ[pp] : (UT)aw[e];
-            }
+            *reinterpret_cast<bf4v*>(
+                Wp + ((sp * A.wrb + (row0 >> 3)) * A.ldu + kc + col) * 8 + (row0 & 7)) = hv;
           }
         }
       }
