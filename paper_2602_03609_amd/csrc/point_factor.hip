@@ -273,6 +273,7 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
   __shared__ int sSort[NSLOT];
   __shared__ int sUniq[NSLOT];
   __shared__ int sNU;
+  __shared__ int sLoHi[2];
   __shared__ double sX[GP][ROWS], sY[GP][ROWS], sT[GP][ROWS];
   __shared__ T sCol[GP][4 * (ROWS + 1)];
   __shared__ T sBv[GP][ROWS];
@@ -345,54 +346,131 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
   sIdx[pl][r] = (int)srow;
   sSort[pl * ROWS + r] = srow >= 0 ? (int)srow : INT_MAX;
   if (r == 0) sI[pl] = active ? i : -1;
+  if (tid == 0) {
+    sLoHi[0] = INT_MAX;
+    sLoHi[1] = -1;
+  }
   __syncthreads();
 
-  // ---- union of the group's conditioning rows: bitonic sort, dedup ----
-  for (int kk = 2; kk <= NSLOT; kk <<= 1) {
-    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-      for (int e = tid; e < NSLOT; e += NTH) {
-        const int ptn = e ^ jj;
-        if (ptn > e) {
-          const int a0 = sSort[e], a1 = sSort[ptn];
-          const bool up = (e & kk) == 0;
-          if ((a0 > a1) == up) {
-            sSort[e] = a1;
-            sSort[ptn] = a0;
+  // ---- union of the group's conditioning rows, sorted, and each row's slot ----
+  // The rows of a group lie in one or two time slabs, so their index range is
+  // usually narrow: a bitmap over [lo, hi] marks them, and a prefix count over its
+  // words gives the sorted union and every row's slot in a few barriers. Wider
+  // ranges take a bitonic sort of the NSLOT entries and a binary search.
+  {
+    int vmin = srow >= 0 ? (int)srow : INT_MAX, vmax = srow >= 0 ? (int)srow : -1;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      vmin = min(vmin, __shfl_xor(vmin, o));
+      vmax = max(vmax, __shfl_xor(vmax, o));
+    }
+    if (lane == 0) {
+      atomicMin(&sLoHi[0], vmin);
+      atomicMax(&sLoHi[1], vmax);
+    }
+  }
+  __syncthreads();
+  constexpr int BMW = 512;  // bitmap words (16384 rows of index range)
+  static_assert(BMW % NTH == 0 && 2 * BMW * sizeof(int) <= BIG_B, "bitmap in the staging area");
+  constexpr int WPT = BMW / NTH;
+  const int ulo = sLoHi[0], uhi = sLoHi[1];
+  const bool use_bm = uhi < ulo || uhi - ulo < BMW * 32;
+  if (use_bm) {
+    unsigned* bm = reinterpret_cast<unsigned*>(sBig);
+    int* pre = reinterpret_cast<int*>(sBig) + BMW;
+    for (int w = tid; w < BMW; w += NTH) bm[w] = 0u;
+    __syncthreads();
+    if (srow >= 0) {
+      const int off = (int)srow - ulo;
+      atomicOr(&bm[off >> 5], 1u << (off & 31));
+    }
+    __syncthreads();
+    // block-wide exclusive prefix of the word counts (WPT consecutive words per thread)
+    unsigned wv[WPT];
+    int cnt = 0;
+#pragma unroll
+    for (int e = 0; e < WPT; ++e) {
+      wv[e] = bm[tid * WPT + e];
+      cnt += __popc(wv[e]);
+    }
+    int inc = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int up = __shfl_up(inc, o);
+      if (lane >= o) inc += up;
+    }
+    if (lane == 63) sSort[wave] = inc;  // wave totals (sSort is free on this path)
+    __syncthreads();
+    int base = inc - cnt;
+    for (int w2 = 0; w2 < wave; ++w2) base += sSort[w2];
+    if (tid == NTH - 1) sNU = base + cnt;
+#pragma unroll
+    for (int e = 0; e < WPT; ++e) {
+      const int wi = tid * WPT + e;
+      pre[wi] = base;
+      unsigned b = wv[e];
+      while (b) {
+        const int bit = __builtin_ctz(b);
+        b &= b - 1u;
+        sUniq[base++] = ulo + wi * 32 + bit;
+      }
+    }
+    __syncthreads();
+    int slot = -1;
+    if (srow >= 0) {
+      const int off = (int)srow - ulo;
+      slot = pre[off >> 5] + __popc(bm[off >> 5] & ((1u << (off & 31)) - 1u));
+    }
+    sSlot[pl][r] = slot;
+    __syncthreads();
+  }
+  if (!use_bm) {
+    for (int kk = 2; kk <= NSLOT; kk <<= 1) {
+      for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+        for (int e = tid; e < NSLOT; e += NTH) {
+          const int ptn = e ^ jj;
+          if (ptn > e) {
+            const int a0 = sSort[e], a1 = sSort[ptn];
+            const bool up = (e & kk) == 0;
+            if ((a0 > a1) == up) {
+              sSort[e] = a1;
+              sSort[ptn] = a0;
+            }
           }
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
-  }
-  if (wave == 0) {
-    int base = 0;
-    for (int c0 = 0; c0 < NSLOT; c0 += 64) {
-      const int e = c0 + lane;
-      const int v = sSort[e];
-      const bool f = v != INT_MAX && (e == 0 || sSort[e - 1] != v);
-      const unsigned long long bm = __ballot(f);
-      const int at = base + __popcll(bm & ((1ull << lane) - 1ull));
-      if (f) sUniq[at] = v;
-      base += __popcll(bm);
+    if (wave == 0) {
+      int base = 0;
+      for (int c0 = 0; c0 < NSLOT; c0 += 64) {
+        const int e = c0 + lane;
+        const int v = sSort[e];
+        const bool f = v != INT_MAX && (e == 0 || sSort[e - 1] != v);
+        const unsigned long long bm = __ballot(f);
+        const int at = base + __popcll(bm & ((1ull << lane) - 1ull));
+        if (f) sUniq[at] = v;
+        base += __popcll(bm);
+      }
+      if (lane == 0) sNU = base;
     }
-    if (lane == 0) sNU = base;
+    __syncthreads();
+    for (int e = tid; e < NSLOT; e += NTH) {
+      const int v = sIdx[e / ROWS][e % ROWS];
+      int slot = -1;
+      if (v >= 0) {
+        int lo = 0, hi = sNU - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (sUniq[mid] < v) lo = mid + 1; else hi = mid;
+        }
+        slot = lo;
+      }
+      sSlot[e / ROWS][e % ROWS] = slot;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const int nu = sNU;
-  for (int e = tid; e < NSLOT; e += NTH) {
-    const int v = sIdx[e / ROWS][e % ROWS];
-    int slot = -1;
-    if (v >= 0) {
-      int lo = 0, hi = nu - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (sUniq[mid] < v) lo = mid + 1; else hi = mid;
-      }
-      slot = lo;
-    }
-    sSlot[e / ROWS][e % ROWS] = slot;
-  }
-  __syncthreads();
 
   // Staged chunk width: as many columns as the union size allows in the staging
   // area (wider chunks mean fewer barriers), and a divisor of the row length.
@@ -406,7 +484,10 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
     if (rows * (2 * KC + VPE) <= cap && A.ldu % (4 * KC) == 0) return 2 * KC;
     return KC;  // rows <= NSLOT + 15 always fits; ldu is a multiple of 64 >= 2 KC
   };
-  // Split staging: nu rows of NSP planes of (width + BPAD) bfloat16.
+  // Split staging: NSP planes of nu rows of (width + BPAD) bfloat16, plane-major. A
+  // row is an odd number of 16-byte units long, so the 16 rows one fragment read
+  // gathers fall on different LDS banks unless their slots coincide modulo 16
+  // (rows of interleaved planes, an even number of units apart, collided modulo 8).
   auto pick_width_split = [&]() {
     const int capb = (int)(BIG_B / 2);
     const int capp = MAXP * NTH * VPE;
@@ -451,7 +532,7 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
               hv[c] = h;
               rem[c] -= (float)h;
             }
-            *reinterpret_cast<bf4v*>(splane + (row * NSP + sp) * sld + piece * 4) = hv;
+            *reinterpret_cast<bf4v*>(splane + (sp * nu + row) * sld + piece * 4) = hv;
           }
         } else {
           *reinterpret_cast<f4v*>(stage + row * sld + piece * VPE) = pre[j];
@@ -565,7 +646,7 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
 #pragma unroll
             for (int sp = 0; sp < NS; ++sp) {
               if (sl >= 0)
-                part[ti][sp] = *reinterpret_cast<const bf8v*>(splane + (sl * NS + sp) * sld + sub + kq * 8);
+                part[ti][sp] = *reinterpret_cast<const bf8v*>(splane + (sp * nu + sl) * sld + sub + kq * 8);
               else
                 part[ti][sp] = bf8v{};
             }
