@@ -1,5 +1,7 @@
-"""Gradient of the Vecchia NLL with respect to the kernel hyperparameters
-(oracle; test infrastructure only).
+"""Gradient of the Vecchia and VIF NLLs with respect to the kernel
+hyperparameters (oracle; test infrastructure only). vecchia_grad works block by
+block (below); vif_grad differentiates the VIF covariance in dense form (its
+docstring).
 
 The paper fits the hyperparameters by minimising the NLL with a quasi-Newton
 method driven by its gradient (Sec. "Estimation and prediction"). For a
@@ -29,7 +31,7 @@ import math
 
 import numpy as np
 
-from .kernels import GNEITING, GNEITING_MATERN, MATERN_ANISO, cov, matern_closed
+from .kernels import GNEITING, GNEITING_MATERN, MATERN_ANISO, cov, cov_matrix, matern_closed
 
 LOG2PI = math.log(2.0 * math.pi)
 
@@ -167,4 +169,86 @@ def vecchia_grad(kern, X, y, nbr):
             dN = [D[:, :p, :p] for D in dS]
             nll += 0.5 * float((_l(S, yS) - _l(N, yS[:, :p])).sum())
             grad += 0.5 * (_dl(S, dS, yS) - _dl(N, dN, yS[:, :p])).sum(0)
+    return nll, grad
+
+
+def _dmats(kern, P, Q):
+    """Covariance derivative matrices between point sets P and Q, one per parameter."""
+    return dcov(kern, P[0][:, None] - Q[0][None, :], P[1][:, None] - Q[1][None, :],
+                P[2][:, None] - Q[2][None, :])
+
+
+def vif_grad(kern, X, y, nbr, Z, jitter=0.0):
+    """(NLL, gradient [P]) of the VIF NLL (Sec. "The Vecchia-inducing-point
+    full-scale approximation"), from the VIF covariance in dense form.
+
+    The likelihood oracle's VIF is the Gaussian likelihood of
+        Sigma_VIF = Sl + B^-1 D B^-T,   Sl = C_nk C_k^-1 C_kn,  C_k = C(Z,Z) + jitter I,
+    with B, D the Vecchia factor (neighbor sets nbr) of the residual covariance
+        R = C(X,X) + nugget I - Sl.
+    Its gradient is the Gaussian formula 1/2 tr(Sigma_VIF^-1 dS) - 1/2 alpha' dS alpha,
+    alpha = Sigma_VIF^-1 y, with dS = dSl + d(B^-1 D B^-T) by the chain rule:
+        dSl = dC_nk C_k^-1 C_kn + C_nk C_k^-1 dC_kn - C_nk C_k^-1 dC_k C_k^-1 C_kn,
+        dR  = dC + dnugget I - dSl,
+        dA_i = R_NN^-1 (dR_Ni - dR_NN A_i),   dD_i = dR_ii - 2 A_i . dR_Ni + A_i' dR_NN A_i,
+        d(B^-1 D B^-T) = -B^-1 dB V + B^-1 dD B^-T - V dB' B^-T,   V = B^-1 D B^-T,
+    where row i of dB holds -dA_i at N(i). Dense n x n algebra: small n only.
+    """
+    n = X[0].shape[0]
+    k = Z[0].shape[0]
+    kind = kern["kind"]
+    names = PARAMS[kind]
+    P = len(names)
+    nug = kern["nugget"]
+    C = cov_matrix(kern, X, X)
+    dC = _dmats(kern, X, X)
+    if k > 0:
+        Cnk = cov_matrix(kern, X, Z)
+        Ck = cov_matrix(kern, Z, Z) + jitter * np.eye(k)
+        Cki = np.linalg.inv(Ck)
+        dCnk = _dmats(kern, X, Z)
+        dCk = _dmats(kern, Z, Z)
+        T = Cnk @ Cki                                        # C_nk C_k^-1
+        Sl = T @ Cnk.T
+        dSl = [dCnk[p] @ T.T + T @ dCnk[p].T - T @ dCk[p] @ T.T for p in range(P)]
+    else:
+        Sl = np.zeros((n, n))
+        dSl = [np.zeros((n, n)) for _ in range(P)]
+    R = C + nug * np.eye(n) - Sl
+    dR = [dC[p] - dSl[p] for p in range(P)]
+    dR[names.index("nugget")] = dR[names.index("nugget")] + np.eye(n)
+    # Vecchia factor of R and its derivatives, point by point
+    B = np.eye(n)
+    D = np.empty(n)
+    dB = [np.zeros((n, n)) for _ in range(P)]
+    dD = np.empty((P, n))
+    for i in range(n):
+        N = nbr[i][nbr[i] >= 0].astype(np.int64)
+        if N.shape[0] == 0:
+            D[i] = R[i, i]
+            dD[:, i] = [dR[p][i, i] for p in range(P)]
+            continue
+        RNN = R[np.ix_(N, N)]
+        RNi = R[N, i]
+        Ai = np.linalg.solve(RNN, RNi)
+        B[i, N] = -Ai
+        D[i] = R[i, i] - Ai @ RNi
+        for p in range(P):
+            dNN = dR[p][np.ix_(N, N)]
+            dNi = dR[p][N, i]
+            dAi = np.linalg.solve(RNN, dNi - dNN @ Ai)
+            dB[p][i, N] = -dAi
+            dD[p, i] = dR[p][i, i] - 2.0 * Ai @ dNi + Ai @ dNN @ Ai
+    Bi = np.linalg.inv(B)
+    V = Bi @ np.diag(D) @ Bi.T
+    S = Sl + V
+    L = np.linalg.cholesky(S)
+    al = np.linalg.solve(S, y)
+    nll = 0.5 * n * LOG2PI + float(np.log(np.diag(L)).sum()) + 0.5 * float(y @ al)
+    Si = np.linalg.inv(S)
+    grad = np.empty(P)
+    for p in range(P):
+        dV = -Bi @ dB[p] @ V + Bi @ np.diag(dD[p]) @ Bi.T - V @ dB[p].T @ Bi.T
+        dS = dSl[p] + dV
+        grad[p] = 0.5 * np.einsum("ij,ji->", Si, dS) - 0.5 * float(al @ dS @ al)
     return nll, grad

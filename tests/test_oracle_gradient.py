@@ -92,3 +92,49 @@ def test_full_conditioning_gives_the_exact_gradient(name):
     _, g = GR.vecchia_grad(kern, X, d["y"], nbr)
     fd = _fd_grad(lambda k: DN.exact_nll(k, X, d["y"]), kern, GR.PARAMS[kind])
     assert np.allclose(g, fd, rtol=1e-5, atol=1e-6 * np.abs(fd).max())
+
+
+@pytest.mark.parametrize("name", list(KINDS))
+def test_vif_gradient_matches_finite_differences_of_the_vif_nll(name):
+    """The VIF gradient (dense chain rule) against central differences of the
+    pinned VIF likelihood oracle (Woodbury form), inducing points and
+    neighbor sets held fixed; its NLL equals the likelihood oracle's."""
+    kind = KINDS[name]
+    d = synth.config_small(seed=30 + kind, n_sites=30, n_times=4, k=12, m=5, kind=kind)
+    kern = _kern(name)
+    X = (d["sx"], d["sy"], d["t"])
+    Z = (d["zx"], d["zy"], d["zt"])
+    nbr = NB.brute_force(kern, *X, 5)
+    nll, g = GR.vif_grad(kern, X, d["y"], nbr, Z)
+    ref = LK.vif(kern, X, d["y"], nbr, Z)["nll"]
+    assert abs(nll - ref) < 1e-10 * abs(ref)
+    fd = _fd_grad(lambda k: LK.vif(k, X, d["y"], nbr, Z)["nll"], kern, GR.PARAMS[kind])
+    assert np.allclose(g, fd, rtol=1e-5, atol=1e-6 * np.abs(fd).max())
+
+
+def test_vif_gradient_without_inducing_points_is_the_vecchia_gradient():
+    d = synth.config_small(seed=41, n_sites=30, n_times=3, k=0, m=6, kind=1)
+    kern = _kern("gneiting")
+    X = (d["sx"], d["sy"], d["t"])
+    nbr = NB.brute_force(kern, *X, 6)
+    empty = (np.zeros(0), np.zeros(0), np.zeros(0))
+    nll, g = GR.vif_grad(kern, X, d["y"], nbr, empty)
+    nll_v, g_v = GR.vecchia_grad(kern, X, d["y"], nbr)
+    assert abs(nll - nll_v) < 1e-10 * abs(nll_v)
+    assert np.allclose(g, g_v, rtol=1e-9, atol=1e-10 * np.abs(g_v).max())
+
+
+@pytest.mark.parametrize("name", ["gneiting", "gm_nu25", "aniso"])
+def test_vif_gradient_with_full_conditioning_is_the_exact_gradient(name):
+    """m = n - 1: VIF is exact for any inducing points, so its gradient is the
+    gradient of the dense exact NLL (finite differences)."""
+    kind = KINDS[name]
+    d = synth.config_small(seed=50 + kind, n_sites=12, n_times=3, k=7, m=4, kind=kind)
+    kern = _kern(name)
+    X = (d["sx"], d["sy"], d["t"])
+    Z = (d["zx"], d["zy"], d["zt"])
+    n = d["n"]
+    nbr = NB.brute_force(kern, *X, n - 1)
+    _, g = GR.vif_grad(kern, X, d["y"], nbr, Z)
+    fd = _fd_grad(lambda k: DN.exact_nll(k, X, d["y"]), kern, GR.PARAMS[kind])
+    assert np.allclose(g, fd, rtol=1e-5, atol=1e-6 * np.abs(fd).max())
