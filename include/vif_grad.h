@@ -14,7 +14,8 @@
  *   VIF_KERNEL_GNEITING:        sigma2, nugget, a, c, alpha, beta, gamma, tau
  *   VIF_KERNEL_GNEITING_MATERN: sigma2, nugget, a, c, alpha, gamma, delta   (nu fixed)
  *   VIF_KERNEL_MATERN_ANISO:    sigma2, nugget, range_s, range_t   (nu fixed)
- * Inducing points (VIF) are not supported.
+ * vif_nll_grad covers plain Vecchia; vif_nll_grad_vif the VIF approximation
+ * (inducing points).
  *
  * Conventions as in vif.h: DEVICE arrays owned by the caller, work on the
  * caller's HIP stream, VIF_* status, argument errors found before any launch.
@@ -45,6 +46,28 @@ size_t vif_grad_ws(int64_t n);
 int32_t vif_nll_grad(const vif_points* points, const double* y, const vif_kernel* kern, int32_t m,
                      const int32_t* nbr, double* nll, double* grad, void* ws, size_t ws_bytes,
                      void* hip_stream);
+
+/* Workspace bytes for vif_nll_grad_vif (0 for invalid sizes; k >= 1). */
+size_t vif_grad_vif_ws(int64_t n, int32_t m, int32_t k);
+
+/* *nll (HOST) and grad (HOST, vif_grad_params(kern->kind) values, the order
+ * above) of the VIF NLL (Sec. "The Vecchia-inducing-point full-scale
+ * approximation"; the fit of Sec. "Estimation and prediction"), in FP64, for
+ * neighbor rows nbr (as for vif_nll) and k = ind->n >= 1 inducing points; the
+ * NLL equals vif_nll's in VIF_PREC_FP64. With W = D^-1/2 B U, z = D^-1/2 B y,
+ * M = I + W'W, v = M^-1 W'z, e = z - W v and H = W M^-1 - e v', the derivative
+ * is the sum over points of <Lambda_i, dC_S + dnugget I> (Lambda_i from the
+ * point's residual-block factor, b = last row of its inverse, g_i = e_i y_S +
+ * U_S H_i, w_i = R_S^-1 g_i: 1/2 (1 + b.g_i) b b' - 1/2 (b w_i' + w_i b')), plus
+ * <Gamma L_k^-1, dC_nk> - <Phi(L_k^-1 dSigma_k L_k^-T), Gamma' U>, where Gamma
+ * gathers b_r H_i - 2 (Lambda_i U_S)_r on the rows of U and Phi takes the lower
+ * triangle with half the diagonal. Gamma is accumulated with FP64 atomics, so
+ * the last bits can vary between calls. Workspace: vif_grad_vif_ws(n, m, k)
+ * (about 5 n kpad + n q^2 doubles, kpad = k + 1 rounded up to 64, q = 32 for
+ * m < 32, else 64). Synchronises the stream. */
+int32_t vif_nll_grad_vif(const vif_points* points, const double* y, const vif_kernel* kern,
+                         int32_t m, const int32_t* nbr, const vif_points* ind, double* nll,
+                         double* grad, void* ws, size_t ws_bytes, void* hip_stream);
 
 #ifdef __cplusplus
 }

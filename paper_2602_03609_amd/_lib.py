@@ -30,7 +30,8 @@ EXPORTS = ("vif_workspace_bytes", "vif_neighbors", "vif_factor", "vif_nll", "vif
            "vif_batch_enqueue", "vif_batch_graph_launch", "vif_batch_autotune",
            "vif_batch_schedule", "vif_batch_set_schedule", "vif_batch_status",
            "vif_batch_destroy", "vif_residual_ws", "vif_residual_neighbors",
-           "vif_grad_params", "vif_grad_ws", "vif_nll_grad", "vif_neighbors_noalloc")
+           "vif_grad_params", "vif_grad_ws", "vif_nll_grad", "vif_neighbors_noalloc",
+           "vif_grad_vif_ws", "vif_nll_grad_vif")
 BATCH_PLAN_SCRATCH = 16384
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 8, 64, 16, 9936
 STAGES = ("neighbors", "sigma_k", "crosscov", "trmm", "point_factor", "syrk", "assembly")
@@ -71,6 +72,15 @@ def load(path=LIB_PATH):
             return _lib
         if not os.path.exists(path):
             raise ImportError(f"{path} is not built; run `python -m paper_2602_03609_amd.build`")
+        # The library has to run on the HIP runtime that owns the device memory and the
+        # streams it is given. PyTorch ships its own libamdhip64 under the system's soname:
+        # mapped first, it is the one libvif.so binds to; mapped after libvif.so, it would
+        # be a second runtime in the process, sharing no devices, streams or memory with
+        # the library's (whose first call then finds no device).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(path)
         vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
         pP, pK = ctypes.POINTER(Points), ctypes.POINTER(Kernel)
@@ -140,6 +150,10 @@ def load(path=LIB_PATH):
         lib.vif_grad_ws.restype = sz
         lib.vif_nll_grad.argtypes = [pP, vp, pK, i32, vp, pd, pd, vp, sz, vp]
         lib.vif_nll_grad.restype = i32
+        lib.vif_grad_vif_ws.argtypes = [i64, i32, i32]
+        lib.vif_grad_vif_ws.restype = sz
+        lib.vif_nll_grad_vif.argtypes = [pP, vp, pK, i32, vp, pP, pd, pd, vp, sz, vp]
+        lib.vif_nll_grad_vif.restype = i32
         lib.vif_neighbors_noalloc.argtypes = [pP, pK, i32, vp, vp]
         lib.vif_neighbors_noalloc.restype = i32
         lib.vif_batch_destroy.argtypes = [vp]
@@ -380,6 +394,29 @@ def vif_nll_grad(sx, sy, t, y, kern, m, nbr, stream=None):
 
 
 # ---------------------------------------------------------- residual neighbors ----
+def vif_nll_grad_vif(sx, sy, t, y, kern, m, nbr, ind, stream=None):
+    """(NLL, gradient as a numpy array) of the VIF NLL in FP64; ind = (zx, zy, zt)."""
+    import numpy as np
+    torch = _torch()
+    lib = load()
+    n = sx.shape[0]
+    p = make_points(sx, sy, t)
+    K = make_kernel(kern)
+    ip, k = _ind(ind)
+    P = int(lib.vif_grad_params(int(kern["kind"])))
+    nbytes = int(lib.vif_grad_vif_ws(int(n), int(m), int(k)))
+    if nbytes == 0:
+        raise VifError(VIF_E_ARG, "invalid workspace request")
+    ws = _scratch(("grad_vif", str(sx.device)), nbytes, sx.device)
+    nll = ctypes.c_double()
+    g = (ctypes.c_double * max(P, 1))()
+    _check(lib.vif_nll_grad_vif(ctypes.byref(p), _dev_ptr(y, torch.float64, "y"), ctypes.byref(K),
+                                int(m), _dev_ptr(nbr, torch.int32, "nbr") if m > 0 else None,
+                                ctypes.byref(ip) if ip is not None else None, ctypes.byref(nll), g,
+                                ws.data_ptr(), ws.numel(), _stream(stream)))
+    return nll.value, np.array([g[i] for i in range(P)])
+
+
 def vif_residual_neighbors(sx, sy, t, kern, m, ind=None, nbr=None, stream=None):
     """Residual-correlation neighbors for VIF (include/vif_residual.h); int32 [n, m]."""
     torch = _torch()

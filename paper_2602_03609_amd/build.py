@@ -20,7 +20,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libvif.so")
 ARCH = "gfx950"
 
-SOURCES = ["neighbors.hip", "point_factor.hip", "lowrank.hip", "reduce.hip", "learn.hip", "residual.hip", "gradient.hip", "noalloc.hip", "api.cpp"]
+SOURCES = ["neighbors.hip", "point_factor.hip", "lowrank.hip", "reduce.hip", "learn.hip", "residual.hip", "gradient.hip", "grad_vif.hip", "noalloc.hip", "api.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

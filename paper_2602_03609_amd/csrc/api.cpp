@@ -120,6 +120,9 @@ constexpr size_t kFlagBytes = 256;
 // 32 -> 4.74, 64 -> 5.22).
 constexpr double kCellTarget = 16.0;
 
+// Real-valued times: the search's time bins hold about this many points each.
+constexpr int64_t kBinPoints = 2048;
+
 Layout make_layout(int64_t n, int m, int k, int prec, int op, int chunk_rows = 4096) {
   Layout L;
   size_t off = 0;
@@ -450,7 +453,7 @@ struct SideWork {
 int32_t nll_impl(const vif_points* p, const double* y, const vif_kernel* kern, int32_t m,
                  const int32_t* nbr, const vif_points* ind, int32_t prec, double* nll,
                  double* terms, void* wsv, size_t ws_bytes, void* hip_stream,
-                 const SideWork* side = nullptr) {
+                 const SideWork* side = nullptr, double* lout = nullptr) {
   int k = 0;
   int32_t st = check_ind(ind, &k);
   if (st) return st;
@@ -481,6 +484,7 @@ int32_t nll_impl(const vif_points* p, const double* y, const vif_kernel* kern, i
   fa.logD = reinterpret_cast<double*>(ws + L.logD);
   fa.fail = fl;
   fa.bad_nbr = fl + 3;
+  fa.Lout = lout;
   if (k > 0) {
     int nlag = 0;
     if ((st = build_order(p, ws, L, s, &fa.ord, &nlag))) return st;
@@ -546,12 +550,89 @@ int32_t nll_impl(const vif_points* p, const double* y, const vif_kernel* kern, i
 
 }  // namespace
 
+namespace vif {
+// Host tables of the neighbor search (pure host code): Lmax + 1 entries each of
+// tab1, tab2 and bnd in *tab, the key mode and, for real-valued times
+// (general), the time-bin width. Integer times: one slab per time value.
+int32_t search_tables(const vif_kernel* kern, bool general, double span, int64_t n,
+                      std::vector<double>* tab, int* Lmax_out, double* width_out, int* mode_out) {
+  int Lmax = 0;
+  double width = 1.0;  // slab width in time
+  if (!general) {
+    if (!(span >= 0) || span >= (double)VIF_MAX_LAGS)
+      return fail(VIF_E_UNSUPPORTED, "time span %g exceeds VIF_MAX_LAGS - 1", span);
+    Lmax = (int)span;
+  } else if (span > 0) {
+    // time bins of about kBinPoints points (at most VIF_MAX_LAGS of them)
+    const int64_t nb = std::min<int64_t>(std::max<int64_t>(n / kBinPoints, 1), VIF_MAX_LAGS);
+    Lmax = (int)nb - 1;
+    width = span / (double)nb;
+  }
+
+  // Per-lag factors from the host C math library, in the operation order the
+  // ranking key specifies; bnd is the suffix maximum of -tab1. For real-valued
+  // times, entry L holds f1 at the smallest and f2 at the largest lag of two
+  // bins L apart (widened by a relative 1e-9), the bounds the search needs.
+  tab->assign((size_t)3 * (Lmax + 1), 0.0);
+  double* tab1 = tab->data();
+  double* tab2 = tab1 + (Lmax + 1);
+  double* bnd = tab2 + (Lmax + 1);
+  auto lag_lo = [&](int l) {
+    return general ? std::max(0.0, (double)(l - 1) * width * (1.0 - 1e-9)) : (double)l;
+  };
+  auto lag_hi = [&](int l) { return general ? (double)(l + 1) * width * (1.0 + 1e-9) : (double)l; };
+  int mode;
+  const vif::KernDev kd = to_dev(kern);
+  if (kern->kind == VIF_KERNEL_MATERN_ANISO) {
+    mode = 1;
+    const double ir_t = 1.0 / kern->range_t;
+    for (int l = 0; l <= Lmax; ++l) {
+      const double w = lag_lo(l) * ir_t;
+      tab1[l] = w * w;
+    }
+  } else {
+    const double two_alpha = 2.0 * kern->alpha;
+    auto factors = [&](double lag, double* f1, double* f2) {
+      const double pw = pow(lag, two_alpha);
+      const double psi = kern->a * pw + 1.0;
+      if (kern->kind == VIF_KERNEL_GNEITING) {
+        *f1 = kern->tau * log(psi);
+        *f2 = kern->c * pow(psi, -(kern->beta * kern->gamma));
+      } else {
+        *f1 = (kern->delta + kern->gamma) * log(psi);
+        *f2 = kern->c * pow(psi, -(kern->gamma / 2.0));
+      }
+    };
+    for (int l = 0; l <= Lmax; ++l) {
+      double f2 = 0.0;
+      factors(lag_lo(l), &tab1[l], &f2);
+      if (general) factors(lag_hi(l), &f2, &tab2[l]); else tab2[l] = f2;
+    }
+    if (kern->kind == VIF_KERNEL_GNEITING)
+      mode = kern->gamma == 0.5 ? 0 : 2;
+    else
+      mode = kd.nu_code == 0 ? 0 : 3;
+  }
+  double run = -INFINITY;
+  for (int l = Lmax; l >= 0; --l) {
+    const double b = -tab1[l];
+    run = b > run ? b : run;
+    bnd[l] = run;
+  }
+  *Lmax_out = Lmax;
+  *width_out = width;
+  *mode_out = mode;
+  return VIF_OK;
+}
+}  // namespace vif
+
 // Shared by the exact and the proposal search: validates times, reads the
 // bounding box, uploads the per-lag tables and fills the search arguments.
 struct SearchSetup {
   double tt[2], bb[4];
   int Lmax = 0;
   int mode = 0;
+  bool general = false;  // real-valued times: slabs are time bins
   std::vector<double> tab;  // host tables; must outlive the copies (caller syncs)
   vif::NbrArgs a{};
 };
@@ -573,53 +654,17 @@ int32_t search_setup(const vif_points* p, const vif_kernel* kern, int32_t m, int
   if (!isfinite(S->bb[0]) || !isfinite(S->bb[1]) || !isfinite(S->bb[2]) || !isfinite(S->bb[3]))
     return fail(VIF_E_ARG, "coordinates must be finite");
   if (f.tflag & 1u) return fail(VIF_E_ARG, "times must be finite");
-  if (f.tflag & 2u) return fail(VIF_E_UNSUPPORTED, "neighbor search requires integer-valued times");
   if (f.tflag & 4u) return fail(VIF_E_ARG, "times must be nondecreasing in index");
+  const bool general = (f.tflag & 2u) != 0;  // some time is not an integer
   const double span = S->tt[1] - S->tt[0];
-  if (!(span >= 0) || span >= (double)VIF_MAX_LAGS)
-    return fail(VIF_E_UNSUPPORTED, "time span %g exceeds VIF_MAX_LAGS - 1", span);
-  const int Lmax = (int)span;
+  int Lmax = 0, mode = 0;
+  double width = 1.0;
+  if ((st = vif::search_tables(kern, general, span, p->n, &S->tab, &Lmax, &width, &mode))) return st;
   S->Lmax = Lmax;
-
-  // Per-lag factors from the host C math library, in the operation order the
-  // ranking key specifies; bnd is the suffix maximum of -tab1.
-  S->tab.assign((size_t)3 * (Lmax + 1), 0.0);
-  double* tab1 = S->tab.data();
-  double* tab2 = tab1 + (Lmax + 1);
-  double* bnd = tab2 + (Lmax + 1);
-  int mode;
-  const vif::KernDev kd = to_dev(kern);
-  if (kern->kind == VIF_KERNEL_MATERN_ANISO) {
-    mode = 1;
-    const double ir_t = 1.0 / kern->range_t;
-    for (int l = 0; l <= Lmax; ++l) {
-      const double w = (double)l * ir_t;
-      tab1[l] = w * w;
-    }
-  } else {
-    const double two_alpha = 2.0 * kern->alpha;
-    for (int l = 0; l <= Lmax; ++l) {
-      const double pw = pow((double)l, two_alpha);
-      const double psi = kern->a * pw + 1.0;
-      if (kern->kind == VIF_KERNEL_GNEITING) {
-        tab1[l] = kern->tau * log(psi);
-        tab2[l] = kern->c * pow(psi, -(kern->beta * kern->gamma));
-      } else {
-        tab1[l] = (kern->delta + kern->gamma) * log(psi);
-        tab2[l] = kern->c * pow(psi, -(kern->gamma / 2.0));
-      }
-    }
-    if (kern->kind == VIF_KERNEL_GNEITING)
-      mode = kern->gamma == 0.5 ? 0 : 2;
-    else
-      mode = kd.nu_code == 0 ? 0 : 3;
-  }
-  double run = -INFINITY;
-  for (int l = Lmax; l >= 0; --l) {
-    const double b = -tab1[l];
-    run = b > run ? b : run;
-    bnd[l] = run;
-  }
+  S->general = general;
+  const double* tab1 = S->tab.data();
+  const double* tab2 = tab1 + (Lmax + 1);
+  const double* bnd = tab2 + (Lmax + 1);
   HIPCHK(hipMemcpyAsync(ws + L.tab1, tab1, sizeof(double) * (Lmax + 1), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ws + L.tab2, tab2, sizeof(double) * (Lmax + 1), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ws + L.bnd, bnd, sizeof(double) * (Lmax + 1), hipMemcpyHostToDevice, s));
@@ -628,10 +673,23 @@ int32_t search_setup(const vif_points* p, const vif_kernel* kern, int32_t m, int
   a.n = p->n;
   a.m = m;
   a.mode = mode;
-  a.nu_code = kd.nu_code;
+  a.nu_code = to_dev(kern).nu_code;
   a.ir_s = kern->kind == VIF_KERNEL_MATERN_ANISO ? 1.0 / kern->range_s : 0.0;
   a.gamma = kern->gamma;
   a.t0 = S->tt[0];
+  a.general = general ? 1 : 0;
+  a.islab = general ? (span > 0 ? 1.0 / width : 0.0) : 1.0;
+  a.a = kern->a;
+  a.two_alpha = 2.0 * kern->alpha;
+  a.c = kern->c;
+  if (kern->kind == VIF_KERNEL_GNEITING) {
+    a.c1 = kern->tau;
+    a.e2 = -(kern->beta * kern->gamma);
+  } else {
+    a.c1 = kern->delta + kern->gamma;
+    a.e2 = -(kern->gamma / 2.0);
+  }
+  a.ir_t = kern->kind == VIF_KERNEL_MATERN_ANISO ? 1.0 / kern->range_t : 0.0;
   a.sx = p->sx; a.sy = p->sy; a.t = p->t;
   a.tab1 = reinterpret_cast<const double*>(ws + L.tab1);
   a.tab2 = reinterpret_cast<const double*>(ws + L.tab2);
@@ -674,6 +732,7 @@ int32_t exact_grid(const vif_points* p, char* ws, const Layout& L, hipStream_t s
     g.gy = gy;
     g.ncell = gx * gy;
     g.nslab = nslab;
+    g.islab = S.a.islab;
     g.xmin = bb[0];
     g.ymin = bb[2];
     g.cw = w > 0 ? w / gx : 1.0;
@@ -1035,6 +1094,10 @@ int32_t vif_propose_neighbors(const vif_points* p, const vif_kernel* kern, int32
   char* ws = reinterpret_cast<char*>(wsv);
   SearchSetup S;
   if ((st = search_setup(p, kern, m, nbr, ws, L, s, &S))) return st;
+  if (S.general) {
+    HIPCHK(hipStreamSynchronize(s));  // the host tables outlive their copies
+    return fail(VIF_E_UNSUPPORTED, "the proposal search requires integer-valued times");
+  }
   // proposal grid: square cells of side `cell`
   const double ih = 1.0 / cell;
   const double gxd = (S.bb[1] - S.bb[0]) * ih + 1.0, gyd = (S.bb[3] - S.bb[2]) * ih + 1.0;
@@ -1128,6 +1191,75 @@ GradLayout make_grad_layout(int64_t n) {
   L.tab = take(sizeof(double) * vif::kGradLagVals * VIF_MAX_LAGS);
   L.total = off;
   return L;
+}
+
+}  // namespace
+
+namespace {
+
+// ------------------------------------------------------------ VIF gradient ----
+// Workspace of vif_nll_grad_vif: the FP64 VIF NLL's, then the gradient's buffers.
+struct VifGradLayout {
+  size_t lfac = 0, e = 0, H = 0, Gam = 0, LMi = 0, Minv = 0, v = 0, psi = 0, part = 0, dSk = 0,
+         T = 0, X = 0, blk = 0, cross = 0, phi = 0, sums = 0, total = 0;
+  int Q = 16, splits = 1;
+  Layout fwd;
+};
+
+VifGradLayout make_vif_grad_layout(int64_t n, int m, int k) {
+  VifGradLayout G;
+  G.fwd = make_layout(n, m, k, VIF_PREC_FP64, VIF_OP_NLL);
+  size_t off = G.fwd.total;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off += align256(bytes);
+    return at;
+  };
+  const size_t kp = (size_t)G.fwd.kpad, kk = kp * kp, P = vif::kGradMaxParams;
+  // the per-point kernel's block width (rows of q = m + 1 lanes: 16, 32 or 64)
+  G.Q = m < 16 ? 16 : (m < 32 ? 32 : 64);
+  // split K of Gamma' U: about 64k rows per split, at most 64 splits
+  G.splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, n / 65536));
+  G.lfac = take(sizeof(double) * (size_t)n * G.Q * G.Q);
+  G.e = take(sizeof(double) * (size_t)n);
+  G.H = take(sizeof(double) * (size_t)n * kp);
+  G.Gam = take(sizeof(double) * (size_t)n * kp);
+  G.LMi = take(sizeof(double) * kk);
+  G.Minv = take(sizeof(double) * kk);
+  G.v = take(sizeof(double) * kp);
+  G.psi = take(sizeof(double) * kk);
+  G.part = take(sizeof(double) * kk * G.splits);
+  G.dSk = take(sizeof(double) * kk * P);
+  G.T = take(sizeof(double) * kk);
+  G.X = take(sizeof(double) * kk * P);
+  G.blk = take(sizeof(double) * (size_t)n * P);
+  G.cross = take(sizeof(double) * (size_t)n * P);
+  G.phi = take(sizeof(double) * (size_t)vif::phi_dot_blocks(G.fwd.kpad) * P);
+  G.sums = take(sizeof(double) * 3 * P);
+  G.total = off;
+  return G;
+}
+
+vif::GradKern grad_kern(const vif_kernel* kern) {
+  vif::GradKern G{};
+  G.kind = kern->kind;
+  G.nu_code = kern->kind != VIF_KERNEL_GNEITING ? nu_code(kern->nu) : 0;
+  G.sigma2 = kern->sigma2;
+  G.a = kern->a;
+  G.c = kern->c;
+  G.two_alpha = 2.0 * kern->alpha;
+  G.beta = kern->beta;
+  G.gamma = kern->gamma;
+  G.bg = kern->beta * kern->gamma;
+  G.tau = kern->tau;
+  G.delta = kern->delta;
+  if (kern->kind == VIF_KERNEL_MATERN_ANISO) {
+    G.ir_s2 = 1.0 / (kern->range_s * kern->range_s);
+    G.ir_t2 = 1.0 / (kern->range_t * kern->range_t);
+    G.inv_rs = 1.0 / kern->range_s;
+    G.inv_rt = 1.0 / kern->range_t;
+  }
+  return G;
 }
 
 }  // namespace
@@ -1229,6 +1361,119 @@ int32_t vif_nll_grad(const vif_points* p, const double* y, const vif_kernel* ker
 }
 
 // ------------------------------------------------------- residual neighbors ----
+size_t vif_grad_vif_ws(int64_t n, int32_t m, int32_t k) {
+  if (n < 1 || m < 0 || m > VIF_MAX_M || k < 1 || k > VIF_MAX_K) return 0;
+  return make_vif_grad_layout(n, m, k).total;
+}
+
+int32_t vif_nll_grad_vif(const vif_points* p, const double* y, const vif_kernel* kern, int32_t m,
+                         const int32_t* nbr, const vif_points* ind, double* nll, double* grad,
+                         void* wsv, size_t ws_bytes, void* hip_stream) {
+  if (!p) return fail(VIF_E_ARG, "points is NULL");
+  int k = 0;
+  int32_t st = check_ind(ind, &k);
+  if (st) return st;
+  if (k < 1) return fail(VIF_E_ARG, "inducing points required (vif_nll_grad covers k = 0)");
+  const VifGradLayout G = make_vif_grad_layout(p->n > 0 ? p->n : 1, m, k);
+  if ((st = check_common(p, kern, m, wsv, ws_bytes, G.total))) return st;
+  const int P = vif_grad_params(kern->kind);
+  if (P == 0) return fail(VIF_E_UNSUPPORTED, "gradient not available for kernel kind %d", kern->kind);
+  if (!y) return fail(VIF_E_ARG, "y is NULL");
+  if (m > 0 && !nbr) return fail(VIF_E_ARG, "nbr is NULL");
+  if (!nll || !grad) return fail(VIF_E_ARG, "nll or grad is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  char* ws = reinterpret_cast<char*>(wsv);
+  const Layout& L = G.fwd;
+  const int kpad = L.kpad;
+  const int64_t n = p->n;
+  const int64_t kk = (int64_t)kpad * kpad;
+  auto D = [&](size_t off) { return reinterpret_cast<double*>(ws + off); };
+  // forward: the FP64 VIF NLL, keeping each point's residual-block factor
+  double terms[4];
+  if ((st = nll_impl(p, y, kern, m, nbr, ind, VIF_PREC_FP64, nll, terms, wsv, ws_bytes, hip_stream,
+                     nullptr, D(G.lfac))))
+    return st;
+  double* U = D(L.U);
+  double* W = D(L.W);
+  double* z = D(L.z);
+  double* q = D(L.q);
+  double* Pk = D(L.P);  // L_k^-1, identity on the padding
+  // M^-1 from the factor of the augmented Woodbury matrix (its leading k x k block)
+  HIPCHK(vif::launch_lead_block(k, kpad, D(L.M), D(G.T), s));
+  HIPCHK(vif::launch_trinv(kpad, D(G.T), D(G.LMi), D(L.dscr), s));
+  auto gemm = [&](int64_t M_, int N_, int64_t K_, const double* A_, int64_t lda, int ta,
+                  const double* B_, int64_t ldb, int tb, double* C_, int64_t ldc, const double* eu,
+                  const double* ev, double gam, int splits, int64_t cstride) {
+    vif::GemmF64 g{};
+    g.M = M_; g.N = N_; g.K = K_;
+    g.A = A_; g.lda = lda; g.ta = ta;
+    g.B = B_; g.ldb = ldb; g.tb = tb;
+    g.C = C_; g.ldc = ldc;
+    g.alpha = 1.0;
+    g.eu = eu; g.ev = ev; g.gamma = gam;
+    g.kchunk = ((K_ + splits - 1) / splits + 15) / 16 * 16;
+    g.cstride = cstride;
+    return vif::launch_gemm_f64(g, splits, s);
+  };
+  HIPCHK(gemm(kpad, kpad, kpad, D(G.LMi), kpad, 1, D(G.LMi), kpad, 0, D(G.Minv), kpad, nullptr,
+              nullptr, 0.0, 1, 0));
+  HIPCHK(vif::launch_clip_kk(k, kpad, D(G.Minv), s));
+  HIPCHK(vif::launch_fill_f64(q + k, kpad - k, 0.0, s));
+  HIPCHK(vif::launch_matvec(kpad, D(G.Minv), q, D(G.v), s));          // v = M^-1 q
+  HIPCHK(vif::launch_resid_e(n, k, kpad, W, z, D(G.v), D(G.e), s));  // e = z - W v
+  // H = W M^-1 - e v'
+  HIPCHK(gemm(n, kpad, kpad, W, kpad, 0, D(G.Minv), kpad, 0, D(G.H), kpad, D(G.e), D(G.v), -1.0, 1, 0));
+  // per-point terms and Gamma
+  HIPCHK(vif::launch_fill_f64(D(G.Gam), n * (int64_t)kpad, 0.0, s));
+  vif::VifGradArgs a{};
+  a.n = n;
+  a.m = m;
+  a.k = k;
+  a.kpad = kpad;
+  a.P = P;
+  a.G = grad_kern(kern);
+  a.sx = p->sx; a.sy = p->sy; a.st = p->t; a.y = y;
+  a.nbr = nbr;
+  a.lrows = G.Q;
+  a.Lfac = D(G.lfac);
+  a.U = U;
+  a.H = D(G.H);
+  a.e = D(G.e);
+  a.Gam = D(G.Gam);
+  a.blk = D(G.blk);
+  HIPCHK(vif::launch_vif_grad_points(a, s));
+  // <Gamma L_k^-1, dC_nk>: Gamma L_k^-1 into H's buffer
+  double* Gt = D(G.H);
+  HIPCHK(gemm(n, kpad, kpad, D(G.Gam), kpad, 0, Pk, kpad, 0, Gt, kpad, nullptr, nullptr, 0.0, 1, 0));
+  HIPCHK(vif::launch_cross_deriv(a.G, P, n, k, kpad, p->sx, p->sy, p->t, ind->sx, ind->sy, ind->t,
+                                 Gt, D(G.cross), s));
+  // Psi = Gamma' U (split over the rows), and <Phi(L_k^-1 dSigma_k L_k^-T), Psi> per parameter
+  HIPCHK(gemm(kpad, kpad, n, D(G.Gam), kpad, 1, U, kpad, 0, D(G.part), kpad, nullptr, nullptr, 0.0,
+              G.splits, kk));
+  HIPCHK(vif::launch_splitk_reduce(kk, G.splits, kk, D(G.part), D(G.psi), s));
+  HIPCHK(vif::launch_kk_deriv(a.G, P, k, kpad, ind->sx, ind->sy, ind->t, D(G.dSk), s));
+  for (int pp = 0; pp < P; ++pp) {
+    HIPCHK(gemm(kpad, kpad, kpad, Pk, kpad, 0, D(G.dSk) + pp * kk, kpad, 0, D(G.T), kpad, nullptr,
+                nullptr, 0.0, 1, 0));
+    HIPCHK(gemm(kpad, kpad, kpad, D(G.T), kpad, 0, Pk, kpad, 1, D(G.X) + pp * kk, kpad, nullptr,
+                nullptr, 0.0, 1, 0));
+  }
+  const int nb = vif::phi_dot_blocks(kpad);
+  HIPCHK(vif::launch_phi_dot(kpad, P, D(G.X), D(G.psi), D(G.phi), s));
+  double* part = D(L.part);
+  double* sm = D(G.sums);
+  for (int pp = 0; pp < P; ++pp) {
+    HIPCHK(vif::launch_sum(n, D(G.blk) + pp * n, 0, part, sm + pp, s));
+    HIPCHK(vif::launch_sum(n, D(G.cross) + pp * n, 0, part, sm + P + pp, s));
+    HIPCHK(vif::launch_sum(nb, D(G.phi) + (int64_t)pp * nb, 0, part, sm + 2 * P + pp, s));
+  }
+  double h[3 * vif::kGradMaxParams];
+  HIPCHK(hipMemcpyAsync(h, sm, sizeof(double) * 3 * P, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int pp = 0; pp < P; ++pp) grad[pp] = h[pp] + h[P + pp] - h[2 * P + pp];
+  return ok();
+}
+
 size_t vif_residual_ws(int64_t n, int32_t k) {
   if (n < 1 || n >= (int64_t)INT32_MAX || k < 0 || k > VIF_MAX_K) return 0;
   return make_residual_layout(n, k).total;

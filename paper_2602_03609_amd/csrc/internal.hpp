@@ -22,6 +22,13 @@ struct NbrArgs {
   int mode;
   int nu_code;
   double ir_s, gamma, t0;
+  // Real-valued times (general = 1): slabs are time bins of width 1 / islab, the
+  // tables hold the bin-lag bounds, and each pair's lag factors are computed from
+  // its own lag l = t_i - t_j: psi = a l^(2 alpha) + 1, f1 = c1 log psi,
+  // f2 = c * psi^e2 (GNEITING: c1 = tau, e2 = -(beta gamma); GNEITING_MATERN:
+  // c1 = delta + gamma, e2 = -(gamma / 2)); MATERN_ANISO: f1 = (l ir_t)^2.
+  int general;
+  double islab, a, two_alpha, c1, c, e2, ir_t;
   const double *sx, *sy, *t;
   const double *tab1, *tab2, *bnd;
   int32_t* nbr;
@@ -34,6 +41,7 @@ struct NbrArgs {
 struct GridArgs {
   int gx, gy, ncell, nslab;
   int morton;                           // 1: cells numbered in Z order (gx = gy = 2^b)
+  double islab = 1.0;                   // slab of t: min((t - t0) * islab, nslab - 1)
   double xmin, ymin, cw, ch, icw, ich;  // cell sizes and their inverses
   double margin;                        // absolute slack on distance bounds
   const int32_t* off;                   // [nslab * ncell + 1]
@@ -120,6 +128,10 @@ struct FactorArgs {
   const void* lagtab;
   unsigned long long* fail;     // smallest point index with a non-positive-definite block
   unsigned long long* bad_nbr;  // smallest point index with an invalid neighbor row
+  // FP64 VIF NLL only, optional: the Cholesky factor of each point's residual block,
+  // [n, rows, rows] row-major (rows = 16 for m < 16, 32 for m < 32, else 64), zero above
+  // the diagonal, the identity past the point's block.
+  double* Lout;
 };
 
 // tab[2 l], tab[2 l + 1] = gneiting_lag(K, l) for l < nlag, in FP64 (prec 0) or FP32.
@@ -237,5 +249,60 @@ struct GradArgs {
 constexpr int kGradLagVals = 6;
 hipError_t launch_grad_lags(const GradKern& G, int nlag, double* tab, hipStream_t s);
 hipError_t launch_vecchia_grad(const GradArgs& a, hipStream_t s);
+
+// ---- VIF gradient (grad_vif.hip) ----------------------------------------------
+// C[M x N] = alpha op(A) op(B) (+ gamma eu[i] ev[j] when eu != NULL), FP64,
+// row-major; split K over blockIdx.y (kchunk per split, outputs cstride apart).
+struct GemmF64 {
+  int64_t M;
+  int N;
+  int64_t K;
+  const double* A;
+  int64_t lda;
+  int ta;
+  const double* B;
+  int64_t ldb;
+  int tb;
+  double* C;
+  int64_t ldc;
+  double alpha;
+  const double* eu;
+  const double* ev;
+  double gamma;
+  int64_t kchunk;
+  int64_t cstride;
+};
+hipError_t launch_gemm_f64(const GemmF64& g, int splits, hipStream_t s);
+hipError_t launch_splitk_reduce(int64_t count, int splits, int64_t stride, const double* part,
+                                double* out, hipStream_t s);
+hipError_t launch_fill_f64(double* p, int64_t cnt, double v, hipStream_t s);
+hipError_t launch_lead_block(int k, int kpad, const double* F, double* Lo, hipStream_t s);
+hipError_t launch_clip_kk(int k, int kpad, double* X, hipStream_t s);
+hipError_t launch_matvec(int kpad, const double* X, const double* x, double* y, hipStream_t s);
+hipError_t launch_resid_e(int64_t n, int k, int ldw, const double* W, const double* z,
+                          const double* v, double* e, hipStream_t s);
+hipError_t launch_kk_deriv(const GradKern& G, int P, int k, int kpad, const double* zx,
+                           const double* zy, const double* zt, double* dSk, hipStream_t s);
+int phi_dot_blocks(int kpad);
+hipError_t launch_phi_dot(int kpad, int P, const double* X, const double* Psi, double* out,
+                          hipStream_t s);
+hipError_t launch_cross_deriv(const GradKern& G, int P, int64_t n, int k, int ldg, const double* sx,
+                              const double* sy, const double* st, const double* zx, const double* zy,
+                              const double* zt, const double* Gt, double* crossd, hipStream_t s);
+struct VifGradArgs {
+  int64_t n;
+  int m, k, kpad, P;
+  int lrows;           // row stride of Lfac: 16, 32 or 64, the per-point kernel's block width
+  GradKern G;
+  const double *sx, *sy, *st, *y;
+  const int32_t* nbr;
+  const double* Lfac;  // [n, lrows, lrows] residual-block factors, lower triangle by rows
+  const double* U;     // [n, kpad]
+  const double* H;     // [n, kpad]: W M^-1 - e v'
+  const double* e;     // [n]: z - W v
+  double* Gam;         // [n, kpad], accumulated (zeroed by the caller)
+  double* blk;         // [P, n] per-point <Lambda_i, dC_S + dnugget I>
+};
+hipError_t launch_vif_grad_points(const VifGradArgs& a, hipStream_t s);
 
 }  // namespace vif

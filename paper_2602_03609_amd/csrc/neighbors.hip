@@ -94,7 +94,7 @@ __global__ void grid_count_kernel(int64_t n, const double* __restrict__ sx,
                                   int32_t* __restrict__ key) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int slab = G.nslab > 1 ? (int)(t[i] - t0) : 0;
+  const int slab = G.nslab > 1 ? min((int)((t[i] - t0) * G.islab), G.nslab - 1) : 0;
   const int cx = cell_of(sx[i], G.xmin, G.icw, G.gx);
   const int cy = cell_of(sy[i], G.ymin, G.ich, G.gy);
   int cell;
@@ -250,6 +250,21 @@ __device__ __forceinline__ double rank_key(double dx, double dy, double t1, doub
   return -(t1 + s);
 }
 
+// Lag-only factors of the key at the real lag l >= 0 (general times), in the
+// operation order of the per-lag tables the host computes for integer times.
+__device__ __forceinline__ void lag_factors(const NbrArgs& A, double l, double& f1, double& f2) {
+#pragma clang fp contract(off)
+  if (A.mode == 1) {
+    const double w = l * A.ir_t;
+    f1 = w * w;
+    f2 = 0.0;
+    return;
+  }
+  const double psi = A.a * pow(l, A.two_alpha) + 1.0;
+  f1 = A.c1 * log(psi);
+  f2 = A.c * pow(psi, A.e2);
+}
+
 // Upper bound of the key over candidates at distance >= d (d already reduced by
 // the slack): the same operation sequence as rank_key at that distance.
 template <int MODE>
@@ -357,11 +372,11 @@ __device__ __forceinline__ void offer(double key, int j, bool valid, double& K, 
 // after another, a chunk spanning several ranges, and the last chunk of the ring
 // is offered partly filled, so the ring's candidates take as few offers as their
 // count allows.
-template <int MODE>
+template <int MODE, bool GENERAL>
 __device__ __forceinline__ void scan_ring(const NbrArgs& A, const GridArgs& G, const int32_t* off,
-                                          int qcx, int qcy, int r, double qx, double qy, double t1,
-                                          double t2, int jmax, double& K, int& I, int& cnt,
-                                          double& thr, int& thr_i, int lane, int m) {
+                                          int qcx, int qcy, int r, double qx, double qy, double qt,
+                                          double t1, double t2, int jmax, double& K, int& I,
+                                          int& cnt, double& thr, int& thr_i, int lane, int m) {
   int p = -1;      // this lane's candidate position in the CSR arrays, -1 if none
   int filled = 0;  // lanes of the current chunk already assigned
   auto flush = [&]() {
@@ -369,7 +384,15 @@ __device__ __forceinline__ void scan_ring(const NbrArgs& A, const GridArgs& G, c
     const int j = inrun ? G.pidx[p] : INT_MAX;
     const bool valid = inrun && j < jmax;
     double key = -INFINITY;
-    if (valid) key = rank_key<MODE>(G.px[p] - qx, G.py[p] - qy, t1, t2, A);
+    if (valid) {
+      if constexpr (GENERAL) {
+        double f1, f2;
+        lag_factors(A, qt - A.t[j], f1, f2);
+        key = rank_key<MODE>(G.px[p] - qx, G.py[p] - qy, f1, f2, A);
+      } else {
+        key = rank_key<MODE>(G.px[p] - qx, G.py[p] - qy, t1, t2, A);
+      }
+    }
     offer(key, j, valid, K, I, cnt, thr, thr_i, lane, m);
     p = -1;
     filled = 0;
@@ -400,15 +423,21 @@ __device__ __forceinline__ void scan_ring(const NbrArgs& A, const GridArgs& G, c
 
 // One wavefront per query; the register budget is held to seven waves per SIMD
 // (measured faster than six, and eight spills).
-template <int MODE>
+// GENERAL (real-valued times): a slab is a time bin; the tables hold, per bin lag
+// L, the lag factors at the smallest and largest lag two bins L apart can have
+// (f1 nondecreasing, f2 nonincreasing in the lag), so both bounds hold for every
+// pair of those bins; since each pair's own factors come from the device math
+// library, the comparisons with the bounds keep a relative slack of 1e-12.
+template <int MODE, bool GENERAL>
 __global__ __launch_bounds__(256, 7) void neighbors_grid_kernel(NbrArgs A, GridArgs G) {
   const int lane = threadIdx.x & 63;
   const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (w >= A.n) return;  // uniform per wave
   const int64_t i = A.qlist ? (int64_t)A.qlist[w] : w;
   const int m = A.m;
-  const double qx = A.sx[i], qy = A.sy[i];
-  const int ti = (int)(A.t[i] - A.t0);
+  const double qx = A.sx[i], qy = A.sy[i], qt = A.t[i];
+  const int ti = GENERAL ? min((int)((qt - A.t0) * A.islab), G.nslab - 1) : (int)(qt - A.t0);
+  auto slack = [](double b) { return GENERAL ? b + 1e-12 * (1.0 + fabs(b)) : b; };
   const int qcx = cell_of(qx, G.xmin, G.icw, G.gx);
   const int qcy = cell_of(qy, G.ymin, G.ich, G.gy);
   double K = -INFINITY;
@@ -417,7 +446,7 @@ __global__ __launch_bounds__(256, 7) void neighbors_grid_kernel(NbrArgs A, GridA
   double thr = -INFINITY;
   int thr_i = INT_MAX;
   for (int lag = 0; lag <= ti; ++lag) {
-    if (cnt >= m && A.bnd[lag] < thr) break;
+    if (cnt >= m && slack(A.bnd[lag]) < thr) break;
     const int slab = ti - lag;
     const int32_t* off = G.off + (int64_t)slab * G.ncell;
     const int jmax = (lag == 0) ? (int)i : INT_MAX;
@@ -436,11 +465,11 @@ __global__ __launch_bounds__(256, 7) void neighbors_grid_kernel(NbrArgs A, GridA
         if (d == INFINITY) break;  // the grid is covered
         if (cnt >= m) {
           const double ds = fmax(0.0, d * (1.0 - 1e-9) - G.margin);
-          if (bound_key<MODE>(ds, t1, t2, A) < thr) break;
+          if (slack(bound_key<MODE>(ds, t1, t2, A)) < thr) break;
         }
       }
-      scan_ring<MODE>(A, G, off, qcx, qcy, r, qx, qy, t1, t2, jmax, K, I, cnt, thr, thr_i, lane,
-                      m);
+      scan_ring<MODE, GENERAL>(A, G, off, qcx, qcy, r, qx, qy, qt, t1, t2, jmax, K, I, cnt, thr,
+                               thr_i, lane, m);
     }
   }
   if (lane < m) A.nbr[i * m + lane] = lane < cnt ? I : -1;
@@ -710,11 +739,20 @@ __global__ void compact_kernel(int64_t n, const int32_t* __restrict__ flag,
 hipError_t launch_neighbors(const NbrArgs& a, const GridArgs& g, hipStream_t s) {
   if (a.n <= 0 || a.m <= 0) return hipSuccess;
   unsigned grid = (unsigned)((a.n + 3) / 4);
+  if (a.general) {
+    switch (a.mode) {
+      case 0: hipLaunchKernelGGL((neighbors_grid_kernel<0, true>), dim3(grid), dim3(256), 0, s, a, g); break;
+      case 1: hipLaunchKernelGGL((neighbors_grid_kernel<1, true>), dim3(grid), dim3(256), 0, s, a, g); break;
+      case 2: hipLaunchKernelGGL((neighbors_grid_kernel<2, true>), dim3(grid), dim3(256), 0, s, a, g); break;
+      default: hipLaunchKernelGGL((neighbors_grid_kernel<3, true>), dim3(grid), dim3(256), 0, s, a, g); break;
+    }
+    return hipGetLastError();
+  }
   switch (a.mode) {
-    case 0: hipLaunchKernelGGL(neighbors_grid_kernel<0>, dim3(grid), dim3(256), 0, s, a, g); break;
-    case 1: hipLaunchKernelGGL(neighbors_grid_kernel<1>, dim3(grid), dim3(256), 0, s, a, g); break;
-    case 2: hipLaunchKernelGGL(neighbors_grid_kernel<2>, dim3(grid), dim3(256), 0, s, a, g); break;
-    default: hipLaunchKernelGGL(neighbors_grid_kernel<3>, dim3(grid), dim3(256), 0, s, a, g); break;
+    case 0: hipLaunchKernelGGL((neighbors_grid_kernel<0, false>), dim3(grid), dim3(256), 0, s, a, g); break;
+    case 1: hipLaunchKernelGGL((neighbors_grid_kernel<1, false>), dim3(grid), dim3(256), 0, s, a, g); break;
+    case 2: hipLaunchKernelGGL((neighbors_grid_kernel<2, false>), dim3(grid), dim3(256), 0, s, a, g); break;
+    default: hipLaunchKernelGGL((neighbors_grid_kernel<3, false>), dim3(grid), dim3(256), 0, s, a, g); break;
   }
   return hipGetLastError();
 }

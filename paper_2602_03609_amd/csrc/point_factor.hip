@@ -784,6 +784,14 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
       A.logD[i] = 2.0 * log((double)Lpp_b);
       A.z[i] = (double)zi;
     }
+    if constexpr (PREC == 0) {
+      // the factor of the residual block, kept for the gradient (FP64 only)
+      if (A.Lout && active) {
+        double* lo = A.Lout + ((int64_t)i * ROWS + r) * ROWS;
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j) lo[j] = (j <= r) ? (double)a[j] : 0.0;
+      }
+    }
     // b_r = -x_r / L_pp (r < p), b_p = 1 / L_pp;  W_i = sum_r b_r U_{S_r}.
     const T inv = T(1) / Lpp_b;
     sBv[pl][r] = (r < p) ? -x * inv : (r == p ? inv : T(0));

@@ -249,3 +249,22 @@ def test_noalloc_neighbors_rejects_sizes_beyond_its_scratch():
     P.n = 100
     st = lib.vif_neighbors_noalloc(ctypes.byref(P), ctypes.byref(K), 64, ctypes.c_void_p(0x1000), None)
     assert st == L.VIF_E_UNSUPPORTED
+
+
+def test_library_binds_to_the_callers_hip_runtime():
+    """Loading the package before torch still leaves one HIP runtime in the
+    process, torch's: PyTorch ships its libamdhip64 under the system's soname, so
+    whichever is mapped first is the one libvif.so uses, and a second runtime
+    mapped later shares no devices or streams with the first."""
+    import subprocess
+    import sys
+    code = ("import paper_2602_03609_amd as v\n"
+            "v.load()\n"
+            "import torch, os\n"
+            "libs = sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l})\n"
+            "tdir = os.path.realpath(os.path.join(os.path.dirname(torch.__file__), 'lib'))\n"
+            "print(len(libs), all(os.path.realpath(p).startswith(tdir) for p in libs))\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                       cwd=ROOT)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.split() == ["1", "True"], r.stdout

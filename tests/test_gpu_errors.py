@@ -48,9 +48,10 @@ def test_bad_neighbor_rows_are_rejected():
         vif.vif_nll(*Xd, yd, d["kern"], d["m"], dev(bad, torch.int32))
 
 
-def test_unsorted_or_fractional_times_are_rejected():
+def test_unsorted_times_are_rejected_and_fractional_times_searched():
     vif = lib()
     torch = torch_cuda()
+    from oracle import neighbors as NB
     d = synth.config_small(seed=6, n_sites=40, n_times=3, k=0, m=4, kind=1)
     Xd, yd, _ = problem_on_device(d)
     t = d["t"].copy()
@@ -58,10 +59,17 @@ def test_unsorted_or_fractional_times_are_rejected():
     with pytest.raises(vif.VifError) as e:
         vif.vif_neighbors(Xd[0], Xd[1], dev(t, torch.float64), d["kern"], d["m"])
     assert e.value.status == 1
+    # one fractional time: the search takes real times (per-pair lag factors)
     t = d["t"] + 0.5 * (np.arange(d["n"]) == 7)
     t = np.maximum.accumulate(t)
+    got = vif.vif_neighbors(Xd[0], Xd[1], dev(t, torch.float64), d["kern"], d["m"]).cpu().numpy()
+    want = NB.brute_force(d["kern"], d["sx"], d["sy"], t, d["m"])
+    assert np.array_equal(got, want)
+    # the proposal search keeps to integer times
+    E = torch.zeros((d["n"], 16), dtype=torch.float32, device="cuda")
     with pytest.raises(vif.VifError) as e:
-        vif.vif_neighbors(Xd[0], Xd[1], dev(t, torch.float64), d["kern"], d["m"])
+        vif.vif_propose_neighbors(Xd[0], Xd[1], dev(t, torch.float64), d["kern"], d["m"], E, 8, 0.2, 1,
+                                  64, wmin=10, rmax=3)
     assert e.value.status == 5
 
 

@@ -64,12 +64,13 @@ def test_errors_on_either_stream_then_recovery():
     vif = lib()
     d = synth.config_small(seed=66, n_sites=40, n_times=3, k=6, m=4, kind=1)
     Xd, yd, Zd = problem_on_device(d)
-    # fractional times: refused by the search before anything is launched
+    # times out of order: refused by the search before anything is launched
     t = d["t"].copy()
     t[7] += 0.5
+    assert t[8] < t[7]
     with pytest.raises(vif.VifError) as e:
         vif.vif_neighbors_nll(Xd[0], Xd[1], dev(t, torch.float64), yd, d["kern"], d["m"], ind=Zd)
-    assert e.value.status == 5
+    assert e.value.status == 1 and "nondecreasing" in e.value.message
     # Sigma_k not positive definite: found on the NLL stream while the search runs
     zx, zy, zt = d["zx"].copy(), d["zy"].copy(), d["zt"].copy()
     zx[1], zy[1], zt[1] = zx[0], zy[0], zt[0]
