@@ -410,10 +410,23 @@ def kernel_name(stage, prec, m):
 def measured_traffic(stage, prec, m):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
     kernel's source has changed since the counters were taken."""
+    e = committed_counters("traffic", stage, prec, m)
+    return None if e is None else (e[0]["read_bytes"], e[0]["write_bytes"], e[1])
+
+
+def measured_mfma(stage, prec, m):
+    """Share of time the matrix pipes were busy in the kernel and the MFMA rate it executed
+    (all split products counted), from the committed rocprofv3 counter summary; None when the
+    kernel's source has changed since the counters were taken."""
+    e = committed_counters("mfma", stage, prec, m)
+    return None if e is None else (e[0]["mfma_busy"], e[0]["mfma_exec_TFLOP_per_s"], e[1])
+
+
+def committed_counters(kind, stage, prec, m):
     import glob
     import hashlib
     name = kernel_name(stage, prec, m)
-    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json"))):
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"{kind}_*.json"))):
         with open(path) as f:
             tab = json.load(f)
         e = tab.get(name)
@@ -423,7 +436,7 @@ def measured_traffic(stage, prec, m):
         with open(src, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
         if sha == e["source_sha256"]:
-            return e["read_bytes"], e["write_bytes"], os.path.relpath(path, ROOT)
+            return e, os.path.relpath(path, ROOT)
     return None
 
 
@@ -609,6 +622,9 @@ def main():
     if tr is not None:
         roof["traffic"] = tr[0] + tr[1]
         roof["traffic_read"], roof["traffic_write"], roof["traffic_source"] = tr
+    mf = measured_mfma(dom, args.prec, m)
+    if mf is not None:
+        roof["mfma_busy"], roof["mfma_exec_TFLOP_per_s"], roof["mfma_source"] = mf
     stages = {}
     for s, v in stage_ms.items():
         e = {"ms": v}
