@@ -1403,8 +1403,11 @@ int32_t vif_nll_grad_vif(const vif_points* p, const double* y, const vif_kernel*
   HIPCHK(vif::launch_trinv(kpad, D(G.T), D(G.LMi), D(L.dscr), s));
   auto gemm = [&](int64_t M_, int N_, int64_t K_, const double* A_, int64_t lda, int ta,
                   const double* B_, int64_t ldb, int tb, double* C_, int64_t ldc, const double* eu,
-                  const double* ev, double gam, int splits, int64_t cstride) {
+                  const double* ev, double gam, int splits, int64_t cstride, int b_lower = 0,
+                  int c_lower = 0) {
     vif::GemmF64 g{};
+    g.b_lower = b_lower;
+    g.c_lower = c_lower;
     g.M = M_; g.N = N_; g.K = K_;
     g.A = A_; g.lda = lda; g.ta = ta;
     g.B = B_; g.ldb = ldb; g.tb = tb;
@@ -1416,7 +1419,7 @@ int32_t vif_nll_grad_vif(const vif_points* p, const double* y, const vif_kernel*
     return vif::launch_gemm_f64(g, splits, s);
   };
   HIPCHK(gemm(kpad, kpad, kpad, D(G.LMi), kpad, 1, D(G.LMi), kpad, 0, D(G.Minv), kpad, nullptr,
-              nullptr, 0.0, 1, 0));
+              nullptr, 0.0, 1, 0, /*b_lower=*/1));
   HIPCHK(vif::launch_clip_kk(k, kpad, D(G.Minv), s));
   HIPCHK(vif::launch_fill_f64(q + k, kpad - k, 0.0, s));
   HIPCHK(vif::launch_matvec(kpad, D(G.Minv), q, D(G.v), s));          // v = M^-1 q
@@ -1444,12 +1447,14 @@ int32_t vif_nll_grad_vif(const vif_points* p, const double* y, const vif_kernel*
   HIPCHK(vif::launch_vif_grad_points(a, s));
   // <Gamma L_k^-1, dC_nk>: Gamma L_k^-1 into H's buffer
   double* Gt = D(G.H);
-  HIPCHK(gemm(n, kpad, kpad, D(G.Gam), kpad, 0, Pk, kpad, 0, Gt, kpad, nullptr, nullptr, 0.0, 1, 0));
+  HIPCHK(gemm(n, kpad, kpad, D(G.Gam), kpad, 0, Pk, kpad, 0, Gt, kpad, nullptr, nullptr, 0.0, 1, 0,
+              /*b_lower=*/1));
   HIPCHK(vif::launch_cross_deriv(a.G, P, n, k, kpad, p->sx, p->sy, p->t, ind->sx, ind->sy, ind->t,
                                  Gt, D(G.cross), s));
-  // Psi = Gamma' U (split over the rows), and <Phi(L_k^-1 dSigma_k L_k^-T), Psi> per parameter
+  // Psi = Gamma' U (split over the rows), and <Phi(L_k^-1 dSigma_k L_k^-T), Psi> per parameter;
+  // Phi is lower triangular, so only Psi's lower triangle is formed
   HIPCHK(gemm(kpad, kpad, n, D(G.Gam), kpad, 1, U, kpad, 0, D(G.part), kpad, nullptr, nullptr, 0.0,
-              G.splits, kk));
+              G.splits, kk, 0, /*c_lower=*/1));
   HIPCHK(vif::launch_splitk_reduce(kk, G.splits, kk, D(G.part), D(G.psi), s));
   HIPCHK(vif::launch_kk_deriv(a.G, P, k, kpad, ind->sx, ind->sy, ind->t, D(G.dSk), s));
   for (int pp = 0; pp < P; ++pp) {

@@ -40,18 +40,28 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 // Split K: blockIdx.y picks the K range [y kchunk, (y + 1) kchunk) and the output
 // C + y cstride (partials summed by gemm_splitk_reduce in a fixed order).
 // Tile 128 x 128 per workgroup (four wavefronts, 64 x 64 each as 4 x 4 MFMA
-// tiles of 16 x 16), K staged 16 at a time through LDS.
+// tiles of 16 x 16), K staged 16 at a time through LDS; the global loads of the
+// next stage are in flight (in registers) while the MFMAs consume the current one.
+// Workgroups are dealt round-robin to the 8 XCDs; each XCD takes a contiguous
+// range of tiles, so the tiles that share a block row of op(A) share an L2.
 constexpr int GBM = 128, GBN = 128, GBK = 16, GLD = GBM + 1;
+constexpr int GLA = (GBM * GBK) / 256, GLB = (GBN * GBK) / 256;  // loads per thread and stage
 
 __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmF64 g) {
   __shared__ double sA[GBK][GLD];
   __shared__ double sB[GBK][GLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ntn = (g.N + GBN - 1) / GBN;
-  const int64_t bm = (int64_t)(blockIdx.x / ntn) * GBM;
-  const int bn = (int)(blockIdx.x % ntn) * GBN;
-  const int64_t kb = (int64_t)blockIdx.y * g.kchunk;
+  const int64_t ntiles = ((g.M + GBM - 1) / GBM) * ntn;
+  const int64_t per = (ntiles + 7) / 8;
+  const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (t >= ntiles) return;  // whole workgroup, before any barrier
+  const int64_t bm = (t / ntn) * GBM;
+  const int bn = (int)(t % ntn) * GBN;
+  if (g.c_lower && bn >= bm + GBM) return;
+  int64_t kb = (int64_t)blockIdx.y * g.kchunk;
   const int64_t ke = kb + g.kchunk < g.K ? kb + g.kchunk : g.K;
+  if (g.b_lower && kb < bn) kb = bn;  // op(B)[l][j] = 0 for l < j <= bn + ...: start at bn
   double* C = g.C + (int64_t)blockIdx.y * g.cstride;
   const int wr = wave >> 1, wc = wave & 1;
   d4v acc[4][4];
@@ -60,30 +70,40 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmF64 g) {
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = d4v{0.0, 0.0, 0.0, 0.0};
   const int fr = lane & 15, fk = lane >> 4;
+  // this thread's staging coordinates (fixed over the K loop)
+  int amm[GLA], akk[GLA], bnn[GLB], bkk[GLB];
+#pragma unroll
+  for (int j = 0; j < GLA; ++j) {
+    const int e = tid + 256 * j;
+    if (g.ta) { akk[j] = e / GBM; amm[j] = e % GBM; } else { amm[j] = e / GBK; akk[j] = e % GBK; }
+  }
+#pragma unroll
+  for (int j = 0; j < GLB; ++j) {
+    const int e = tid + 256 * j;
+    if (g.tb) { bnn[j] = e / GBK; bkk[j] = e % GBK; } else { bkk[j] = e / GBN; bnn[j] = e % GBN; }
+  }
+  double ra[GLA], rb[GLB];
+  auto load = [&](int64_t k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int j = 0; j < GLA; ++j) {
+      const int64_t gi = bm + amm[j], gl = k0 + akk[j];
+      ra[j] = (gi < g.M && gl < ke) ? (g.ta ? g.A[gl * g.lda + gi] : g.A[gi * g.lda + gl]) : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < GLB; ++j) {
+      const int gj = bn + bnn[j];
+      const int64_t gl = k0 + bkk[j];
+      rb[j] = (gj < g.N && gl < ke) ? (g.tb ? g.B[(int64_t)gj * g.ldb + gl] : g.B[gl * g.ldb + gj]) : 0.0;
+    }
+  };
+  if (kb < ke) load(kb);
   for (int64_t k0 = kb; k0 < ke; k0 += GBK) {
-    // stage: 128 x 16 of op(A) and 16 x 128 of op(B), zero outside the matrices
 #pragma unroll
-    for (int j = 0; j < (GBM * GBK) / 256; ++j) {
-      const int e = tid + 256 * j;
-      int mm, kk;
-      if (g.ta) { kk = e / GBM; mm = e % GBM; } else { mm = e / GBK; kk = e % GBK; }
-      const int64_t gi = bm + mm, gl = k0 + kk;
-      double v = 0.0;
-      if (gi < g.M && gl < ke) v = g.ta ? g.A[gl * g.lda + gi] : g.A[gi * g.lda + gl];
-      sA[kk][mm] = v;
-    }
+    for (int j = 0; j < GLA; ++j) sA[akk[j]][amm[j]] = ra[j];
 #pragma unroll
-    for (int j = 0; j < (GBN * GBK) / 256; ++j) {
-      const int e = tid + 256 * j;
-      int nn, kk;
-      if (g.tb) { nn = e / GBK; kk = e % GBK; } else { kk = e / GBN; nn = e % GBN; }
-      const int gj = bn + nn;
-      const int64_t gl = k0 + kk;
-      double v = 0.0;
-      if (gj < g.N && gl < ke) v = g.tb ? g.B[(int64_t)gj * g.ldb + gl] : g.B[gl * g.ldb + gj];
-      sB[kk][nn] = v;
-    }
+    for (int j = 0; j < GLB; ++j) sB[bkk[j]][bnn[j]] = rb[j];
     __syncthreads();
+    if (k0 + GBK < ke) load(k0 + GBK);
 #pragma unroll
     for (int ks = 0; ks < GBK; ks += 4) {
       double af[4], bf[4];
@@ -191,7 +211,8 @@ __global__ __launch_bounds__(256) void kk_deriv_kernel(GradKern G, int P, int k,
 }
 
 // out[p * nb + block] = sum over the block's entries of Phi(X_p) .* Psi, Phi the
-// lower triangle of X_p with half its diagonal (entries past k are zero).
+// lower triangle of X_p with half its diagonal (entries past k are zero); Psi is
+// read on and below the diagonal only.
 __global__ __launch_bounds__(256) void phi_dot_kernel(int kpad, int P, const double* __restrict__ X,
                                                       const double* __restrict__ Psi,
                                                       double* __restrict__ out) {
@@ -204,8 +225,10 @@ __global__ __launch_bounds__(256) void phi_dot_kernel(int kpad, int P, const dou
   for (int p = 0; p < kGradMaxParams; ++p) t[p] = 0.0;
   if (e < kk) {
     const int a = (int)(e / kpad), b = (int)(e % kpad);
-    const double w = a > b ? 1.0 : (a == b ? 0.5 : 0.0);
-    for (int p = 0; p < P; ++p) t[p] = w * X[p * kk + e] * Psi[e];
+    if (a >= b) {
+      const double w = a > b ? 1.0 : 0.5;
+      for (int p = 0; p < P; ++p) t[p] = w * X[p * kk + e] * Psi[e];
+    }
   }
   for (int p = 0; p < P; ++p) {
     const double s = wave_sum(t[p]);
@@ -419,7 +442,8 @@ __global__ __launch_bounds__(64 * vg_waves<QMAX>()) void vif_grad_point_kernel(V
 hipError_t launch_gemm_f64(const GemmF64& g, int splits, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   const int64_t tiles = ((g.M + GBM - 1) / GBM) * ((g.N + GBN - 1) / GBN);
-  hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)tiles, (unsigned)splits), dim3(256), 0, s, g);
+  const int64_t grid = (tiles + 7) / 8 * 8;
+  hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)grid, (unsigned)splits), dim3(256), 0, s, g);
   return hipGetLastError();
 }
 

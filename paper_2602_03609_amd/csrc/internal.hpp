@@ -269,6 +269,11 @@ struct GemmF64 {
   const double* eu;
   const double* ev;
   double gamma;
+  // Structure that lets tiles or K steps be skipped: b_lower = op(B) is lower
+  // triangular (op(B)[l][j] = 0 for l < j), so column block j needs l >= j only;
+  // c_lower = only C[i][j] with i >= j is wanted (tiles wholly above the diagonal
+  // are not computed and their entries are left unwritten).
+  int b_lower, c_lower;
   int64_t kchunk;
   int64_t cstride;
 };

@@ -6,7 +6,7 @@ Bars: NLL within 1e-10 relative of the oracle's; every gradient entry within
 1e-8 of the largest entry's magnitude. Cases: the three kernel families,
 Gneiting-Matern at nu = 1/2, 3/2, 5/2, neighbor counts below and above 32
 (both per-point kernel widths), early points with fewer than m neighbors. At a
-size the dense oracle cannot reach (n = 20,000, k = 120) the gradient is
+size the dense oracle cannot reach (n = 20,000, k = 300) the gradient is
 checked against central differences of the GPU's own FP64 VIF NLL, and two
 calls agree to 1e-12 (Gamma is accumulated with atomics, so the last bits may
 differ).
@@ -66,7 +66,9 @@ def test_vif_gradient_matches_oracle(name):
 def test_vif_gradient_at_scale_against_finite_differences():
     torch = torch_cuda()
     vif = lib()
-    d = synth.config_small(seed=67, n_times=10, k=120, m=20, kind=1, n_stations=2200)
+    # k = 300 (kpad 320): the GEMMs span several 128-wide tiles, so the skipped
+    # triangular blocks of L_k^-1 and of Gamma'U are exercised
+    d = synth.config_small(seed=67, n_times=10, k=300, m=20, kind=1, n_stations=2200)
     kern = d["kern"]
     Xd, yd, Zd = problem_on_device(d)
     nb = vif.vif_neighbors(*Xd, kern, d["m"])
