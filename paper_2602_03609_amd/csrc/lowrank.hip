@@ -507,12 +507,13 @@ __global__ __launch_bounds__(256) void split_p_kernel(int64_t total, int kpad,
 constexpr int URB = 32;
 constexpr int UPAD = 8;
 
-// The URB rows' coordinates into LDS (one load per row, all in flight at once),
+// The ROWS rows' coordinates into LDS (one load per row, all in flight at once),
 // so that the row loop of fill_c_planes reads no global memory. Ends with a
 // barrier.
+template <int ROWS>
 __device__ __forceinline__ void stage_rows(const LowRankArgs& A, int64_t i0, double* sRow) {
   const int tid = threadIdx.x;
-  if (tid < 3 * URB) {
+  if (tid < 3 * ROWS) {
     const int row = tid / 3, c = tid - 3 * (tid / 3);
     const int64_t i = i0 + row;
     const double* src = c == 0 ? A.sx : (c == 1 ? A.sy : A.t);
@@ -521,18 +522,18 @@ __device__ __forceinline__ void stage_rows(const LowRankArgs& A, int64_t i0, dou
   __syncthreads();
 }
 
-// C(x_i, z_l) for the URB rows from i0 and the columns lbeg .. lbeg + ncol - 1
+// C(x_i, z_l) for the ROWS rows from i0 and the columns lbeg .. lbeg + ncol - 1
 // (ncol a multiple of 8) into NS bfloat16 planes of LDS (plane stride pst, row
 // stride ldc, column l at l - lbeg): the FP32 value split into NS terms, each
 // the bfloat16 rounding of what the previous ones leave. Rows past n and
 // columns past k hold zeros. One thread per 8 consecutive columns x 8 rows.
 // sRow: the rows' (x, y, t), staged in LDS by stage_rows.
-template <int NS>
+template <int NS, int ROWS>
 __device__ __forceinline__ void fill_c_planes(const LowRankArgs& A, int64_t i0, const double* sRow,
                                               int lbeg, int ncol, __bf16* C0, int pst, int ldc) {
   const int tid = threadIdx.x;
   const int ncg = ncol / 8;  // column groups
-  for (int task = tid; task < ncg * (URB / 8); task += (int)blockDim.x) {
+  for (int task = tid; task < ncg * (ROWS / 8); task += (int)blockDim.x) {
     const int cg = task % ncg, rg = task / ncg;
     double zx[8], zy[8], zt[8];
 #pragma unroll
@@ -901,6 +902,118 @@ __global__ __launch_bounds__(256, 2) void syrk_split_kernel(int64_t nrows, int k
       }
 }
 
+// Two-term (BF16X3) Gram in 256 x 256 tiles: one workgroup of eight wavefronts
+// per CU (each 64 x 128 of the tile, 4 x 8 MFMA tiles), so each staged 16-byte
+// piece of W feeds twice the products of a 128 x 128 tile and the CU asks its L2
+// for half the bytes per product. Same chunking, XCD mapping, piece layout and
+// product order as syrk_split_kernel<2>; a diagonal tile stages one block and
+// the two wavefronts whose part lies wholly above the diagonal stay idle.
+constexpr int TB2 = 256;
+
+__global__ __launch_bounds__(512, 1) void syrk_split256_kernel(int64_t nrows, int kpad,
+                                                              const __bf16* __restrict__ Wp,
+                                                              float* __restrict__ part, int nchunk,
+                                                              int ntile, int chunk_blocks) {
+  constexpr int NS = 2;
+  constexpr int PPS = NS * (SBK / 8) * TB2 / 512;  // 16-byte pieces per thread and block
+  __shared__ bf8v sP[2][NS][SBK / 8][TB2];
+  const int x = blockIdx.x & 7;
+  const int l = blockIdx.x >> 3;
+  const int c = (l / ntile) * 8 + x;
+  const int t = l - (l / ntile) * ntile;
+  if (c >= nchunk) return;  // whole block, before any barrier
+  int TI, TJ;
+  tile_of(t, TI, TJ);
+  const bool diag = TI == TJ;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;  // rows wr * 64 .. + 63, columns wc * 128 .. + 127
+  const bool skip = diag && wc * 128 >= wr * 64 + 64;
+  const int64_t wrb = nrows / 8;
+  const int64_t bbeg = (int64_t)c * chunk_blocks;
+  const int64_t bend = bbeg + chunk_blocks < wrb ? bbeg + chunk_blocks : wrb;
+  bf8v ra[PPS], rb[PPS];
+  auto load = [&](int64_t b0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < PPS; ++i) {
+      const int pc = tid + 512 * i;
+      const int col = pc & (TB2 - 1), gq = (pc / TB2) & 3, sp = pc / (TB2 * 4);
+      int64_t blk = b0 + gq;
+      blk = blk < bend ? blk : bend - 1;
+      const int ca = min(TI * TB2 + col, kpad - 1), cb = min(TJ * TB2 + col, kpad - 1);
+      ra[i] = *reinterpret_cast<const bf8v*>(Wp + ((sp * wrb + blk) * kpad + ca) * 8);
+      if (!diag) rb[i] = *reinterpret_cast<const bf8v*>(Wp + ((sp * wrb + blk) * kpad + cb) * 8);
+    }
+  };
+  auto store = [&](int64_t b0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < PPS; ++i) {
+      const int pc = tid + 512 * i;
+      const int col = pc & (TB2 - 1), gq = (pc / TB2) & 3, sp = pc / (TB2 * 4);
+      const bool okr = b0 + gq < bend;
+      sP[0][sp][gq][col] = (okr && TI * TB2 + col < kpad) ? ra[i] : bf8v{};
+      if (!diag) sP[1][sp][gq][col] = (okr && TJ * TB2 + col < kpad) ? rb[i] : bf8v{};
+    }
+  };
+  const int sb = diag ? 0 : 1;
+  f4v acc[4][8];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) acc[a][b] = f4v{0.f, 0.f, 0.f, 0.f};
+  const int g = lane >> 4, j = lane & 15;
+  const int nsteps = bend > bbeg ? (int)((bend - bbeg + 3) / 4) : 0;
+  if (nsteps > 0) {
+    load(bbeg);
+    store(bbeg);
+  }
+  __syncthreads();
+  for (int st = 0; st < nsteps; ++st) {
+    const bool more = st + 1 < nsteps;
+    const int64_t bnext = bbeg + (int64_t)(st + 1) * 4;
+    if (more) load(bnext);
+    if (!skip) {
+      bf8v bv[8][NS];
+#pragma unroll
+      for (int b = 0; b < 8; ++b)
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) bv[b][sp] = sP[sb][sp][g][wc * 128 + b * 16 + j];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        bf8v av[NS];
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) av[sp] = sP[0][sp][g][wr * 64 + a * 16 + j];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          if (diag) {
+            // the low-by-low product on the diagonal tiles (sums of squares there)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1], bv[b][1], acc[a][b], 0, 0, 0);
+          }
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1], bv[b][0], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], bv[b][1], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], bv[b][0], acc[a][b], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+    if (more) {
+      store(bnext);
+      __syncthreads();
+    }
+  }
+  if (skip) return;
+  float* out = part + ((int64_t)c * ntile + t) * (TB2 * TB2);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = wr * 64 + a * 16 + mfma16_row_f32acc(lane, e);
+        const int col = wc * 128 + b * 16 + j;
+        out[row * TB2 + col] = acc[a][b][e];
+      }
+}
+
 // M = I + sum over chunks (FP64, fixed order) of the lower tiles, q = row k, zz = (k, k).
 // Entry (r, c) of the matrix whose Cholesky factor gives both terms of the
 // Woodbury assembly: rows and columns 0 .. k-1 hold M = I + W'W, row k holds
@@ -917,29 +1030,30 @@ __device__ __forceinline__ double augmented_entry(int r, int c, int k, double s)
   return r == c ? 1.0 : 0.0;
 }
 
+template <int TT>
 __global__ __launch_bounds__(256) void syrk_split_reduce_kernel(int k, int kpad,
                                                                 const float* __restrict__ part,
                                                                 int nchunk, int ntile,
                                                                 double* __restrict__ M,
                                                                 double* __restrict__ q,
                                                                 double* __restrict__ zz) {
-  constexpr int PER = TB * TB / 256;  // blocks per tile
+  constexpr int PER = TT * TT / 256;  // blocks per tile
   const int t = blockIdx.x / PER;
   const int e = (blockIdx.x - t * PER) * 256 + threadIdx.x;
   int TI, TJ;
   tile_of(t, TI, TJ);
-  const int er = e / TB, ec = e - (e / TB) * TB;
-  // A diagonal tile's upper triangle (its upper-right quarter is not computed) is
+  const int er = e / TT, ec = e - (e / TT) * TT;
+  // A diagonal tile's upper triangle (parts of it are not computed) is
   // written by the thread of the mirrored lower entry, so every thread reads its
   // own entry's partials, contiguous across the block.
   const bool diag = TI == TJ;
   if (diag && er < ec) return;
-  const float* src = part + (int64_t)t * (TB * TB) + e;
-  const int64_t stride = (int64_t)ntile * (TB * TB);
+  const float* src = part + (int64_t)t * (TT * TT) + e;
+  const int64_t stride = (int64_t)ntile * (TT * TT);
   double s = 0.0;
 #pragma unroll 8
   for (int cc = 0; cc < nchunk; ++cc) s += (double)src[cc * stride];
-  const int r = TI * TB + er, col = TJ * TB + ec;
+  const int r = TI * TT + er, col = TJ * TT + ec;
   if (r < kpad && col < kpad) {
     M[(int64_t)r * kpad + col] = augmented_entry(r, col, k, s);
     if (diag && er > ec) M[(int64_t)col * kpad + r] = augmented_entry(col, r, k, s);
@@ -1024,19 +1138,22 @@ hipError_t launch_crosscov(const LowRankArgs& a, void* U, int prec, hipStream_t 
 // Output columns j < kpad / 2 need only the first half: they are finished and
 // written in the first phase. The upper columns keep their accumulators in
 // registers across the phases and are written after the second.
-constexpr int U6_MAXHI = 4;  // upper 32-column blocks per wave: kpad <= 2 * NWV * 32 * 4
-
-template <int NS, int NWV>
+// RT row tiles of 16 (ROWS = 16 RT rows per workgroup); MAXHI upper 32-column
+// blocks per wave (kpad <= 2 * NWV * 32 * MAXHI). More rows per workgroup feed
+// each P fragment read from L2 to more products (the L2 reads of P per row
+// halve from 32 to 64 rows).
+template <int NS, int NWV, int RT, int MAXHI>
 __global__ __launch_bounds__(64 * NWV) void lowrank_u_kernel(LowRankArgs A, const __bf16* __restrict__ Pb,
                                                         float* __restrict__ U) {
+  constexpr int ROWS = 16 * RT;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int kpad = A.kpad;
   const int kh = kpad / 2;  // kpad is a multiple of 64, so kh is one of 32
   const int ldc = kh + UPAD;
-  const int pst = URB * ldc;
+  const int pst = ROWS * ldc;
   __bf16* C0 = reinterpret_cast<__bf16*>(smem);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t i0 = (int64_t)blockIdx.x * URB;
+  const int64_t i0 = (int64_t)blockIdx.x * ROWS;
   const int64_t kk = (int64_t)kpad * kpad;
   const int nlo = kpad / 64;  // 32-column blocks below kh; as many above
   const int g = lane >> 4, j = lane & 15;
@@ -1060,7 +1177,7 @@ __global__ __launch_bounds__(64 * NWV) void lowrank_u_kernel(LowRankArgs A, cons
     auto step = [&](bf8v (*b)[NS], int k0) __attribute__((always_inline)) {
       const int ko = k0 - lbeg + 8 * g;
 #pragma unroll
-      for (int r = 0; r < 2; ++r) {
+      for (int r = 0; r < RT; ++r) {
         const __bf16* cp = C0 + (r * 16 + j) * ldc + ko;
         bf8v a[NS];
 #pragma unroll
@@ -1099,42 +1216,44 @@ __global__ __launch_bounds__(64 * NWV) void lowrank_u_kernel(LowRankArgs A, cons
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int r = mfma16_row_f32acc(lane, e);
-        const int64_t ia = i0 + r, ib = i0 + 16 + r;
-        if (ia < A.n) U[ia * kpad + jcol] = acc[0][c][e];
-        if (ib < A.n) U[ib * kpad + jcol] = acc[1][c][e];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+          const int64_t ia = i0 + rt * 16 + r;
+          if (ia < A.n) U[ia * kpad + jcol] = acc[rt][c][e];
+        }
       }
     }
   };
 
   // ---- first half of the columns of C ----
-  __shared__ double sRow[3 * URB];
-  stage_rows(A, i0, sRow);
-  fill_c_planes<NS>(A, i0, sRow, 0, kh, C0, pst, ldc);
+  __shared__ double sRow[3 * ROWS];
+  stage_rows<ROWS>(A, i0, sRow);
+  fill_c_planes<NS, ROWS>(A, i0, sRow, 0, kh, C0, pst, ldc);
   __syncthreads();
   for (int pass = 0; pass * NWV < nlo; ++pass) {  // lower blocks, snake order for balance
     const int pb = pass * NWV + ((pass & 1) ? NWV - 1 - wave : wave);
     if (pb >= nlo) continue;
-    f4v acc[2][2];
+    f4v acc[RT][2];
 #pragma unroll
-    for (int r = 0; r < 2; ++r) acc[r][0] = acc[r][1] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int r = 0; r < RT; ++r) acc[r][0] = acc[r][1] = f4v{0.f, 0.f, 0.f, 0.f};
     contract(pb, 0, 0, pb * 32 + 32, acc);
     store(pb, acc);
   }
-  f4v hi[U6_MAXHI][2][2];
+  f4v hi[MAXHI][RT][2];
 #pragma unroll
-  for (int q = 0; q < U6_MAXHI; ++q) {
+  for (int q = 0; q < MAXHI; ++q) {
 #pragma unroll
-    for (int r = 0; r < 2; ++r) hi[q][r][0] = hi[q][r][1] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int r = 0; r < RT; ++r) hi[q][r][0] = hi[q][r][1] = f4v{0.f, 0.f, 0.f, 0.f};
     const int hb = q * NWV + ((q & 1) ? NWV - 1 - wave : wave);
     if (hb < nlo) contract(nlo + hb, 0, 0, kh, hi[q]);
   }
   __syncthreads();  // every read of the first half is done
 
   // ---- second half ----
-  fill_c_planes<NS>(A, i0, sRow, kh, kh, C0, pst, ldc);
+  fill_c_planes<NS, ROWS>(A, i0, sRow, kh, kh, C0, pst, ldc);
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < U6_MAXHI; ++q) {
+  for (int q = 0; q < MAXHI; ++q) {
     const int hb = q * NWV + ((q & 1) ? NWV - 1 - wave : wave);
     if (hb >= nlo) continue;
     const int pb = nlo + hb;
@@ -1143,13 +1262,19 @@ __global__ __launch_bounds__(64 * NWV) void lowrank_u_kernel(LowRankArgs A, cons
   }
 }
 
+namespace {
+// Rows per workgroup: 64 for two terms up to kpad = 1024 (eight wavefronts, one
+// workgroup per CU, 133 KB of LDS at kpad = 1024), else 32.
+int lowrank_rows(int kpad, int prec) { return (prec == 2 && kpad <= 2 * 8 * 32 * 2) ? 64 : URB; }
+}  // namespace
+
 size_t lowrank_fused_lds(int kpad, int prec) {
-  return (size_t)(prec == 3 ? 3 : 2) * URB * (kpad / 2 + UPAD) * sizeof(__bf16);
+  return (size_t)(prec == 3 ? 3 : 2) * lowrank_rows(kpad, prec) * (kpad / 2 + UPAD) * sizeof(__bf16);
 }
 
 bool lowrank_fused_ok(int kpad, int prec) {
-  if (kpad > 2 * 8 * 32 * U6_MAXHI) return false;  // the eight-wavefront launch
-  return lowrank_fused_lds(kpad, prec) + 3 * URB * sizeof(double) <= 160 * 1024;
+  if (kpad > 2 * 8 * 32 * 4) return false;  // the eight-wavefront launch
+  return lowrank_fused_lds(kpad, prec) + 3 * lowrank_rows(kpad, prec) * sizeof(double) <= 160 * 1024;
 }
 
 hipError_t prepare_lowrank_fused() {
@@ -1159,15 +1284,18 @@ hipError_t prepare_lowrank_fused() {
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   if (dev >= 0 && dev < 64 && attr_dev[dev].load(std::memory_order_acquire)) return hipSuccess;
-  const int dyn = 160 * 1024 - 3 * URB * (int)sizeof(double);  // beside the static row stage
-  e = hipFuncSetAttribute((const void*)lowrank_u_kernel<2, 4>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+  // beside the static row stage of each variant
+  const int dyn32 = 160 * 1024 - 3 * 32 * (int)sizeof(double);
+  const int dyn64 = 160 * 1024 - 3 * 64 * (int)sizeof(double);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)lowrank_u_kernel<2, 8>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    e = hipFuncSetAttribute((const void*)lowrank_u_kernel<2, 8, 2, 4>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, dyn32);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)lowrank_u_kernel<3, 8>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    e = hipFuncSetAttribute((const void*)lowrank_u_kernel<3, 8, 2, 4>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, dyn32);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)lowrank_u_kernel<2, 8, 4, 2>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, dyn64);
   if (e == hipSuccess && dev >= 0 && dev < 64) attr_dev[dev].store(1, std::memory_order_release);
   return e;
 }
@@ -1180,18 +1308,17 @@ hipError_t launch_lowrank_fused(const LowRankArgs& a, const double* P, void* Pb,
   if (e != hipSuccess) return e;
   const dim3 gs((unsigned)((kk + 255) / 256));
   const size_t lds = lowrank_fused_lds(a.kpad, prec);
-  const unsigned grid = (unsigned)((a.n + URB - 1) / URB);
+  const int rows = lowrank_rows(a.kpad, prec);
+  const unsigned grid = (unsigned)((a.n + rows - 1) / rows);
   if (prec == 3) {
     hipLaunchKernelGGL(split_p_kernel<3>, gs, dim3(256), 0, s, kk, a.kpad, P, Ph);
-    hipLaunchKernelGGL((lowrank_u_kernel<3, 8>), dim3(grid), dim3(512), lds, s, a, (const __bf16*)Ph, U);
+    hipLaunchKernelGGL((lowrank_u_kernel<3, 8, 2, 4>), dim3(grid), dim3(512), lds, s, a, (const __bf16*)Ph, U);
   } else {
     hipLaunchKernelGGL(split_p_kernel<2>, gs, dim3(256), 0, s, kk, a.kpad, P, Ph);
-    // Two terms: 67 KB of LDS, so with four wavefronts per workgroup two
-    // workgroups share a CU (their evaluation and product phases overlap).
-    if (a.kpad <= 2 * 4 * 32 * U6_MAXHI)
-      hipLaunchKernelGGL((lowrank_u_kernel<2, 4>), dim3(grid), dim3(256), lds, s, a, (const __bf16*)Ph, U);
+    if (rows == 64)
+      hipLaunchKernelGGL((lowrank_u_kernel<2, 8, 4, 2>), dim3(grid), dim3(512), lds, s, a, (const __bf16*)Ph, U);
     else
-      hipLaunchKernelGGL((lowrank_u_kernel<2, 8>), dim3(grid), dim3(512), lds, s, a, (const __bf16*)Ph, U);
+      hipLaunchKernelGGL((lowrank_u_kernel<2, 8, 2, 4>), dim3(grid), dim3(512), lds, s, a, (const __bf16*)Ph, U);
   }
   return hipGetLastError();
 }
@@ -1216,6 +1343,10 @@ int syrk_ntile(int kpad, int tb) {
 }
 }  // namespace
 
+// Output tile of the split-BF16 Gram: 256 for two terms when the 256-wide tiles
+// are at least half real columns, else 128.
+int syrk_split_tb(int kpad, int prec) { return (prec == 2 && kpad >= 512) ? TB2 : TB; }
+
 int syrk_chunks(int64_t n, int, int prec, int chunk_rows) {
   if (prec <= 1) return 8;
   const int64_t c = (n + chunk_rows - 1) / chunk_rows;
@@ -1225,15 +1356,20 @@ int syrk_chunks(int64_t n, int, int prec, int chunk_rows) {
 size_t syrk_part_bytes(int64_t n, int kpad, int prec, int chunk_rows) {
   const size_t c = (size_t)syrk_chunks(n, kpad, prec, chunk_rows);
   if (prec <= 1) return sizeof(double) * c * syrk_ntile(kpad, NB) * NB * NB;
-  return sizeof(float) * c * syrk_ntile(kpad, TB) * TB * TB;
+  const int tb = syrk_split_tb(kpad, prec);
+  return sizeof(float) * c * syrk_ntile(kpad, tb) * tb * tb;
 }
 
 hipError_t launch_syrk(int64_t n, int kpad, const void* W, int prec, void* part, int nchunk,
                        hipStream_t s, int chunk_rows) {
   if (prec >= 2) {
-    const int ntile = syrk_ntile(kpad, TB);
+    const int tb = syrk_split_tb(kpad, prec);
+    const int ntile = syrk_ntile(kpad, tb);
     dim3 grid((unsigned)(ntile * nchunk));
-    if (prec == 2)
+    if (tb == TB2)
+      hipLaunchKernelGGL(syrk_split256_kernel, grid, dim3(512), 0, s, n, kpad, (const __bf16*)W,
+                         (float*)part, nchunk, ntile, chunk_rows / 8);
+    else if (prec == 2)
       hipLaunchKernelGGL(syrk_split_kernel<2>, grid, dim3(256), 0, s, n, kpad,
                          (const __bf16*)W, (float*)part, nchunk, ntile, chunk_rows / 8);
     else
@@ -1254,9 +1390,14 @@ hipError_t launch_syrk(int64_t n, int kpad, const void* W, int prec, void* part,
 hipError_t launch_syrk_reduce(int k, int kpad, const void* part, int prec, int nchunk, double* M,
                               double* q, double* zz, hipStream_t s) {
   if (prec >= 2) {
-    const int ntile = syrk_ntile(kpad, TB);
-    hipLaunchKernelGGL(syrk_split_reduce_kernel, dim3((unsigned)(ntile * (TB * TB / 256))),
-                       dim3(256), 0, s, k, kpad, (const float*)part, nchunk, ntile, M, q, zz);
+    const int tb = syrk_split_tb(kpad, prec);
+    const int ntile = syrk_ntile(kpad, tb);
+    if (tb == TB2)
+      hipLaunchKernelGGL(syrk_split_reduce_kernel<TB2>, dim3((unsigned)(ntile * (TB2 * TB2 / 256))),
+                         dim3(256), 0, s, k, kpad, (const float*)part, nchunk, ntile, M, q, zz);
+    else
+      hipLaunchKernelGGL(syrk_split_reduce_kernel<TB>, dim3((unsigned)(ntile * (TB * TB / 256))),
+                         dim3(256), 0, s, k, kpad, (const float*)part, nchunk, ntile, M, q, zz);
     return hipGetLastError();
   }
   const int ntile = syrk_ntile(kpad, NB);
