@@ -905,7 +905,7 @@ __global__ __launch_bounds__(256, 2) void syrk_split_kernel(int64_t nrows, int k
 // Two-term (BF16X3) Gram in 256 x 256 tiles: one workgroup of eight wavefronts
 // per CU (each 64 x 128 of the tile, 4 x 8 MFMA tiles), so each staged 16-byte
 // piece of W feeds twice the products of a 128 x 128 tile and the CU asks its L2
-// for half the bytes per product. Same chunking, XCD mapping, piece layout and
+// for half the bytes per product; two 64 KB stage buffers. Same chunking, XCD mapping, piece layout and
 // product order as syrk_split_kernel<2>; a diagonal tile stages one block and
 // the two wavefronts whose part lies wholly above the diagonal stay idle.
 constexpr int TB2 = 256;
@@ -916,7 +916,7 @@ __global__ __launch_bounds__(512, 1) void syrk_split256_kernel(int64_t nrows, in
                                                               int ntile, int chunk_blocks) {
   constexpr int NS = 2;
   constexpr int PPS = NS * (SBK / 8) * TB2 / 512;  // 16-byte pieces per thread and block
-  __shared__ bf8v sP[2][NS][SBK / 8][TB2];
+  __shared__ bf8v sP[2][2][NS][SBK / 8][TB2];  // [stage buffer][block][term][row group][column]
   const int x = blockIdx.x & 7;
   const int l = blockIdx.x >> 3;
   const int c = (l / ntile) * 8 + x;
@@ -944,14 +944,14 @@ __global__ __launch_bounds__(512, 1) void syrk_split256_kernel(int64_t nrows, in
       if (!diag) rb[i] = *reinterpret_cast<const bf8v*>(Wp + ((sp * wrb + blk) * kpad + cb) * 8);
     }
   };
-  auto store = [&](int64_t b0) __attribute__((always_inline)) {
+  auto store = [&](int buf, int64_t b0) __attribute__((always_inline)) {
 #pragma unroll
     for (int i = 0; i < PPS; ++i) {
       const int pc = tid + 512 * i;
       const int col = pc & (TB2 - 1), gq = (pc / TB2) & 3, sp = pc / (TB2 * 4);
       const bool okr = b0 + gq < bend;
-      sP[0][sp][gq][col] = (okr && TI * TB2 + col < kpad) ? ra[i] : bf8v{};
-      if (!diag) sP[1][sp][gq][col] = (okr && TJ * TB2 + col < kpad) ? rb[i] : bf8v{};
+      sP[buf][0][sp][gq][col] = (okr && TI * TB2 + col < kpad) ? ra[i] : bf8v{};
+      if (!diag) sP[buf][1][sp][gq][col] = (okr && TJ * TB2 + col < kpad) ? rb[i] : bf8v{};
     }
   };
   const int sb = diag ? 0 : 1;
@@ -964,10 +964,13 @@ __global__ __launch_bounds__(512, 1) void syrk_split256_kernel(int64_t nrows, in
   const int nsteps = bend > bbeg ? (int)((bend - bbeg + 3) / 4) : 0;
   if (nsteps > 0) {
     load(bbeg);
-    store(bbeg);
+    store(0, bbeg);
   }
   __syncthreads();
+  // Two stage buffers: step st computes from buffer st & 1 while the next step's
+  // pieces go to the other one, so each step needs one barrier.
   for (int st = 0; st < nsteps; ++st) {
+    const int buf = st & 1;
     const bool more = st + 1 < nsteps;
     const int64_t bnext = bbeg + (int64_t)(st + 1) * 4;
     if (more) load(bnext);
@@ -976,12 +979,12 @@ __global__ __launch_bounds__(512, 1) void syrk_split256_kernel(int64_t nrows, in
 #pragma unroll
       for (int b = 0; b < 8; ++b)
 #pragma unroll
-        for (int sp = 0; sp < NS; ++sp) bv[b][sp] = sP[sb][sp][g][wc * 128 + b * 16 + j];
+        for (int sp = 0; sp < NS; ++sp) bv[b][sp] = sP[buf][sb][sp][g][wc * 128 + b * 16 + j];
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         bf8v av[NS];
 #pragma unroll
-        for (int sp = 0; sp < NS; ++sp) av[sp] = sP[0][sp][g][wr * 64 + a * 16 + j];
+        for (int sp = 0; sp < NS; ++sp) av[sp] = sP[buf][0][sp][g][wr * 64 + a * 16 + j];
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
           if (diag) {
@@ -994,11 +997,8 @@ __global__ __launch_bounds__(512, 1) void syrk_split256_kernel(int64_t nrows, in
         }
       }
     }
+    if (more) store(buf ^ 1, bnext);
     __syncthreads();
-    if (more) {
-      store(bnext);
-      __syncthreads();
-    }
   }
   if (skip) return;
   float* out = part + ((int64_t)c * ntile + t) * (TB2 * TB2);

@@ -73,6 +73,54 @@ __device__ __forceinline__ bool seg_cholesky(T (&a)[ROWS], T& yv, T& diag, const
   return ok;
 }
 
+// Gauss-Jordan sweep over the first p columns of the segment's SPD matrix G
+// (lane r holding row r in a[]; the point's own row p last, q = p + 1), with y
+// carried as one more column. Step k eliminates column k from every other row
+// (not only the rows below), so the regression coefficients come out with no
+// back-substitution: afterwards lane r < p holds x_r = (G_NN^-1 G_Ni)_r in xo,
+// and lane p holds d = G_ii - G_iN G_NN^-1 G_Ni (D_i) in xo and
+// y_i - G_iN G_NN^-1 y_N in yv. The trailing block stays the symmetric Schur
+// complement of a Cholesky step, so row k's entries past k are column k's, and
+// each step is one LDS round trip: every lane writes its column-k entry (and
+// its y), then reads the pivot row. Rows past q are the identity. Returns false
+// on a nonpositive or non-finite pivot (p pivots and d).
+template <int ROWS, typename T>
+__device__ __forceinline__ bool seg_gauss_jordan(T (&a)[ROWS], T& yv, T& xo, const int r,
+                                                 const int p, const int kmax, T* col2) {
+  bool ok = true;
+  T pivr = T(1);
+#pragma unroll
+  for (int k = 0; k < ROWS - 1; ++k) {
+    if (k < kmax) {  // wave-uniform: the larger p of the wave's segments
+      T* col = col2 + (k & 1) * 2 * (ROWS + 1);
+      col[r] = a[k];
+      col[ROWS + 1 + r] = yv;
+      wave_lds_sync();
+      const bool act = k < p;
+      const T piv0 = col[k];
+      const bool good = !act || ((piv0 > T(0)) && (piv0 < T(INFINITY)));
+      ok = ok && good;
+      const T piv = (act && good) ? piv0 : T(1);
+      const T f = (act && r != k) ? a[k] / piv : T(0);
+      if (r == k) pivr = piv;
+      yv -= f * col[ROWS + 1 + k];
+#pragma unroll
+      for (int j = k + 1; j < ROWS; ++j) a[j] -= f * col[j];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  T ap = T(0);
+#pragma unroll
+  for (int j = 0; j < ROWS; ++j) ap = (j == p) ? a[j] : ap;
+  if (r == p) {
+    ok = ok && (ap > T(0)) && (ap < T(INFINITY));
+    xo = ap;
+  } else {
+    xo = (r < p) ? ap / pivr : T(0);
+  }
+  return ok;
+}
+
 // Wavefronts per block: keeps the per-block LDS (one ROWS x ROWS matrix per
 // point) at 32 KB in FP64.
 template <int ROWS> constexpr int wpb() { return ROWS == 16 ? 4 : (ROWS == 32 ? 2 : 1); }
@@ -751,13 +799,15 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
   T a[ROWS];
 #pragma unroll
   for (int j = 0; j < ROWS; ++j) a[j] = M[j * ROWS + r];
-  T Ldiag = T(1);
-  const bool ok = seg_cholesky<ROWS, T>(a, yv, Ldiag, r, sb, sCol[pl]);
-  if (active && r == 0 && !ok) flag_fail(A.fail, i);
-  const T Lpp_b = __shfl(Ldiag, sb + p);
-  const T zi = __shfl(yv, sb + p);
-  T x = T(0);
-  {
+  // x_r = (G_NN^-1 G_Ni)_r (r < p), L_pp = sqrt(D_i), z_i = (y_i - x' y_N) / L_pp.
+  T x = T(0), Lpp_b, zi;
+  if constexpr (PREC == 0) {
+    // FP64: Cholesky (its factor is kept for the gradient) and back-substitution.
+    T Ldiag = T(1);
+    const bool ok = seg_cholesky<ROWS, T>(a, yv, Ldiag, r, sb, sCol[pl]);
+    if (active && r == 0 && !ok) flag_fail(A.fail, i);
+    Lpp_b = __shfl(Ldiag, sb + p);
+    zi = __shfl(yv, sb + p);
     wave_lds_sync();
 #pragma unroll
     for (int j = 0; j < ROWS; ++j) M[r * ROWS + j] = (j <= r) ? a[j] : T(0);
@@ -772,6 +822,20 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
       if (r < rr) accb -= M[rr * ROWS + r] * xb;
     }
     if (r >= p) x = T(0);
+  } else {
+    // FP32: one Gauss-Jordan sweep (no back-substitution).
+    int kmax = p;
+#pragma unroll
+    for (int o = 32; o >= ROWS; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o));
+    T xo = T(0);
+    const bool ok = seg_gauss_jordan<ROWS, T>(a, yv, xo, r, p, kmax, sCol[pl]);
+    const T d = __shfl(xo, sb + p);
+    Lpp_b = dsqrt(d > T(0) ? d : T(1));
+    zi = __shfl(yv, sb + p) / Lpp_b;
+    x = (r < p) ? xo : T(0);
+    const unsigned long long bad = __ballot(!ok);
+    if (active && r == 0 && ((bad >> sb) & ((ROWS == 64) ? ~0ull : ((1ull << ROWS) - 1ull))) != 0ull)
+      flag_fail(A.fail, i);
   }
   if constexpr (WANT_B) {
     if (active) {
