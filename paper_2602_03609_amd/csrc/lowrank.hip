@@ -905,9 +905,10 @@ __global__ __launch_bounds__(256, 2) void syrk_split_kernel(int64_t nrows, int k
 // Two-term (BF16X3) Gram in 256 x 256 tiles: one workgroup of eight wavefronts
 // per CU (each 64 x 128 of the tile, 4 x 8 MFMA tiles), so each staged 16-byte
 // piece of W feeds twice the products of a 128 x 128 tile and the CU asks its L2
-// for half the bytes per product; two 64 KB stage buffers. Same chunking, XCD mapping, piece layout and
-// product order as syrk_split_kernel<2>; a diagonal tile stages one block and
-// the two wavefronts whose part lies wholly above the diagonal stay idle.
+// for half the bytes per product; two 64 KB stage buffers. Same chunking, XCD
+// mapping, piece layout and product order as syrk_split_kernel<2>; a diagonal
+// tile stages one block and the two wavefronts whose part lies wholly above the
+// diagonal stay idle.
 constexpr int TB2 = 256;
 
 __global__ __launch_bounds__(512, 1) void syrk_split256_kernel(int64_t nrows, int kpad,
