@@ -1201,8 +1201,9 @@ namespace {
 // Workspace of vif_nll_grad_vif: the FP64 VIF NLL's, then the gradient's buffers.
 struct VifGradLayout {
   size_t lfac = 0, e = 0, H = 0, Gam = 0, LMi = 0, Minv = 0, v = 0, psi = 0, part = 0, dSk = 0,
-         T = 0, X = 0, blk = 0, cross = 0, phi = 0, sums = 0, total = 0;
-  int Q = 16, splits = 1;
+         T = 0, X = 0, blk = 0, cross = 0, phi = 0, sums = 0, bw = 0, key = 0, cnt = 0, fill = 0,
+         list = 0, bsum = 0, total = 0;
+  int Q = 16, S = 32, splits = 1;  // Q: factor block width; S: gradient slots per point
   Layout fwd;
 };
 
@@ -1236,6 +1237,15 @@ VifGradLayout make_vif_grad_layout(int64_t n, int m, int k) {
   G.cross = take(sizeof(double) * (size_t)n * P);
   G.phi = take(sizeof(double) * (size_t)vif::phi_dot_blocks(G.fwd.kpad) * P);
   G.sums = take(sizeof(double) * 3 * P);
+  // the gradient's per-point kernel works in blocks of 32 (m < 32) or 64 lanes
+  G.S = m < 32 ? 32 : 64;
+  const size_t slots = (size_t)n * G.S;
+  G.bw = take(sizeof(double) * 2 * slots);
+  G.key = take(sizeof(int32_t) * slots);
+  G.cnt = take(sizeof(int32_t) * ((size_t)n + 1));
+  G.fill = take(sizeof(int32_t) * ((size_t)n + 1));
+  G.list = take(sizeof(int32_t) * slots);
+  G.bsum = take(sizeof(int32_t) * (((size_t)n + 1 + 1023) / 1024 + 1));
   G.total = off;
   return G;
 }
@@ -1426,8 +1436,10 @@ int32_t vif_nll_grad_vif(const vif_points* p, const double* y, const vif_kernel*
   HIPCHK(vif::launch_resid_e(n, k, kpad, W, z, D(G.v), D(G.e), s));  // e = z - W v
   // H = W M^-1 - e v'
   HIPCHK(gemm(n, kpad, kpad, W, kpad, 0, D(G.Minv), kpad, 0, D(G.H), kpad, D(G.e), D(G.v), -1.0, 1, 0));
-  // per-point terms and Gamma
-  HIPCHK(vif::launch_fill_f64(D(G.Gam), n * (int64_t)kpad, 0.0, s));
+  // per-point terms; Gamma's terms per conditioning slot
+  auto I32 = [&](size_t off) { return reinterpret_cast<int32_t*>(ws + off); };
+  HIPCHK(vif::launch_zero_i32(I32(G.cnt), n + 1, s));
+  HIPCHK(vif::launch_zero_i32(I32(G.fill), n + 1, s));
   vif::VifGradArgs a{};
   a.n = n;
   a.m = m;
@@ -1440,11 +1452,30 @@ int32_t vif_nll_grad_vif(const vif_points* p, const double* y, const vif_kernel*
   a.lrows = G.Q;
   a.Lfac = D(G.lfac);
   a.U = U;
+  a.W = W;
   a.H = D(G.H);
   a.e = D(G.e);
-  a.Gam = D(G.Gam);
   a.blk = D(G.blk);
+  a.bw = D(G.bw);
+  a.key = I32(G.key);
+  a.cnt = I32(G.cnt);
   HIPCHK(vif::launch_vif_grad_points(a, s));
+  // Gamma by rows: the slots of each row j listed (counts -> offsets -> fill), then
+  // summed in slot order
+  HIPCHK(vif::launch_exclusive_scan(I32(G.cnt), n + 1, I32(G.bsum), s));
+  HIPCHK(vif::launch_slot_fill(n * (int64_t)G.S, I32(G.key), I32(G.cnt), I32(G.fill), I32(G.list), s));
+  vif::GammaArgs ga{};
+  ga.n = n;
+  ga.k = k;
+  ga.kpad = kpad;
+  ga.qmax = G.S;
+  ga.phi = D(G.H);
+  ga.W = W;
+  ga.bw = D(G.bw);
+  ga.off = I32(G.cnt);
+  ga.list = I32(G.list);
+  ga.Gam = D(G.Gam);
+  HIPCHK(vif::launch_gamma_gather(ga, s));
   // <Gamma L_k^-1, dC_nk>: Gamma L_k^-1 into H's buffer
   double* Gt = D(G.H);
   HIPCHK(gemm(n, kpad, kpad, D(G.Gam), kpad, 0, Pk, kpad, 0, Gt, kpad, nullptr, nullptr, 0.0, 1, 0,

@@ -20,10 +20,17 @@
 //   dNLL = sum_i <Lambda_i, dC_S + dnugget I> + <Gamma L_k^-1, dC_nk>
 //          - <Phi(L_k^-1 dSigma_k L_k^-T), Gamma' U>.
 //
+// Lambda_i has rank two, so row r of b h_i' - 2 Lambda_i U_S is
+//   b_r phi_i + w_r W_i,   phi_i = h_i - (1 + b . g_i) W_i + U_S' w_i,
+// and Gamma_j sums these over the slots (i, r) with S_ir = j.
+//
 // gfx950 pieces: an FP64 MFMA GEMM (H, Gamma L_k^-1, Gamma' U by split K, and
 // the k x k products); one wavefront per point for Lambda_i, its contraction with
-// the block derivatives and, on MFMA, Lambda_i U_S, whose rows are added to Gamma
-// with FP64 atomics; a reduction over the n x k cross-covariance derivatives.
+// the block derivatives, and phi_i (written over h_i) with the slot weights
+// (b_r, w_r); Gamma by rows, each row gathering its slots (listed by a count,
+// scan and fill) in increasing slot order, so there are no floating-point
+// atomics and repeated runs agree bit for bit; a reduction over the n x k
+// cross-covariance derivatives.
 #include <math.h>
 
 #include "grad_common.hpp"
@@ -327,16 +334,28 @@ __global__ __launch_bounds__(64 * vg_waves<QMAX>()) void vif_grad_point_kernel(V
       if (r == kk) bv = vk / lkk;
     }
   }
-  // ---- g = e_i y_S + U_S h_i (row by row, lanes over the columns) ----
+  // ---- g = e_i y_S + U_S h_i (eight rows at a time, lanes over the columns; the
+  // eight wave sums are independent, so their shuffles overlap) ----
   const double ei = A.e[i];
   const double* hrow = A.H + i * (int64_t)kpad;
   double gv = r < q ? ei * yv : 0.0;
-  for (int rr = 0; rr < q; ++rr) {
-    const double* urow = A.U + (int64_t)L.sidx[rr] * kpad;
-    double part = 0.0;
-    for (int c = lane; c < k; c += 64) part += urow[c] * hrow[c];
-    part = wave_sum(part);
-    if (r == rr) gv += part;
+  for (int r0 = 0; r0 < q; r0 += 8) {
+    const double* urow[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) urow[e] = A.U + (int64_t)L.sidx[r0 + e < q ? r0 + e : r0] * kpad;
+    double part[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) part[e] = 0.0;
+    for (int c = lane; c < k; c += 64) {
+      const double hc = hrow[c];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) part[e] += urow[e][c] * hc;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const double t = wave_sum(part[e]);
+      if (r == r0 + e && r0 + e < q) gv += t;
+    }
   }
   // ---- w = R_S^-1 g: forward then backward solve ----
   double f = 0.0, accf = 0.0;
@@ -394,45 +413,85 @@ __global__ __launch_bounds__(64 * vg_waves<QMAX>()) void vif_grad_point_kernel(V
     const double s = wave_sum(tp[pp]);
     if (lane == 0) A.blk[(int64_t)pp * A.n + i] = s;
   }
-  // ---- Gamma rows: b_r h_i - 2 (Lambda U_S)_r, Lambda U_S on FP64 MFMA ----
-  constexpr int RT = QMAX / 16, KS = QMAX / 4;
-  const int fr = lane & 15, fk = lane >> 4;
-  double lf[RT][KS];
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-    for (int j = 0; j < KS; ++j) lf[rt][j] = L.lam[rt * 16 + fr][4 * j + fk];
-  int urows[KS];
-#pragma unroll
-  for (int j = 0; j < KS; ++j) urows[j] = L.sidx[4 * j + fk];
-  double brow[RT][4];
-  int grow[RT][4];
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int rr = rt * 16 + mfma16_row_f64(lane, e);
-      brow[rt][e] = L.b[rr];
-      grow[rt][e] = rr < q ? L.sidx[rr] : -1;
+  // ---- Gamma's terms: Lambda is rank two, so row r of b h_i' - 2 Lambda U_S is
+  // b_r phi_i + w_r W_i with phi_i = h_i - 2 c1 W_i + U_S' w (W_i = b' U_S) ----
+  double* hw = A.H + i * (int64_t)kpad;
+  const double* wrow = A.W + i * (int64_t)kpad;
+  for (int c = lane; c < k; c += 64) {
+    double v = 0.0;
+    for (int rr = 0; rr < q; ++rr) v += L.w[rr] * A.U[(int64_t)L.sidx[rr] * kpad + c];
+    hw[c] = hw[c] - 2.0 * c1 * wrow[c] + v;
+  }
+  if (r < QMAX) {
+    const int64_t sl = i * QMAX + r;
+    A.bw[2 * sl] = bv;
+    A.bw[2 * sl + 1] = wv;
+    A.key[sl] = r < q ? L.sidx[r] : -1;
+    if (r < q) atomicAdd(A.cnt + L.sidx[r], 1);
+  }
+}
+
+__global__ __launch_bounds__(256) void slot_fill_kernel(int64_t nslots, const int32_t* __restrict__ key,
+                                                        const int32_t* __restrict__ off,
+                                                        int32_t* __restrict__ fill,
+                                                        int32_t* __restrict__ list) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nslots) return;
+  const int j = key[e];
+  if (j < 0) return;
+  list[off[j] + atomicAdd(fill + j, 1)] = (int32_t)e;
+}
+
+// One wavefront per row j of Gamma. The row's slots are put in increasing order
+// (rank by counting, in LDS; lists longer than GMAX are summed in list order),
+// then summed term by term, lanes over the columns.
+constexpr int GMAX = 512;
+
+__global__ __launch_bounds__(256) void gamma_gather_kernel(GammaArgs A) {
+  __shared__ int32_t sraw[4][GMAX], ssort[4][GMAX];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 4 + wave;
+  if (j >= A.n) return;  // whole wavefront; no workgroup barriers below
+  const int beg = A.off[j], len = A.off[j + 1] - beg;
+  const bool sorted = len <= GMAX;
+  if (sorted) {
+    for (int t = lane; t < len; t += 64) sraw[wave][t] = A.list[beg + t];
+    wave_lds_sync();
+    for (int t = lane; t < len; t += 64) {
+      const int32_t me = sraw[wave][t];
+      int rank = 0;
+      for (int u = 0; u < len; ++u) rank += sraw[wave][u] < me ? 1 : 0;
+      ssort[wave][rank] = me;  // slots are distinct
     }
-  for (int c0 = 0; c0 < k; c0 += 16) {
-    const int col = c0 + fr;
-    const bool cok = col < k;
-    double bf[KS];
+    wave_lds_sync();
+  }
+  double* out = A.Gam + j * (int64_t)A.kpad;
+  constexpr int CW = 8;  // columns per lane and pass
+  for (int c0 = 0; c0 < A.kpad; c0 += 64 * CW) {
+    double acc[CW];
 #pragma unroll
-    for (int j = 0; j < KS; ++j)
-      bf[j] = (urows[j] >= 0 && cok) ? A.U[(int64_t)urows[j] * kpad + col] : 0.0;
-    const double hc = cok ? hrow[col] : 0.0;
+    for (int t = 0; t < CW; ++t) acc[t] = 0.0;
+    // two slots at a time: their row loads in flight together
+    for (int u = 0; u < len; u += 2) {
+      const bool two = u + 1 < len;
+      const int32_t e0 = sorted ? ssort[wave][u] : A.list[beg + u];
+      const int32_t e1 = two ? (sorted ? ssort[wave][u + 1] : A.list[beg + u + 1]) : e0;
+      const double b0 = A.bw[2 * (int64_t)e0], w0 = A.bw[2 * (int64_t)e0 + 1];
+      const double b1 = two ? A.bw[2 * (int64_t)e1] : 0.0, w1 = two ? A.bw[2 * (int64_t)e1 + 1] : 0.0;
+      const double* p0 = A.phi + (int64_t)(e0 / A.qmax) * A.kpad;
+      const double* q0 = A.W + (int64_t)(e0 / A.qmax) * A.kpad;
+      const double* p1 = A.phi + (int64_t)(e1 / A.qmax) * A.kpad;
+      const double* q1 = A.W + (int64_t)(e1 / A.qmax) * A.kpad;
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      d4v acc = d4v{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int j = 0; j < KS; ++j) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(lf[rt][j], bf[j], acc, 0, 0, 0);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gj = grow[rt][e];
-        if (gj >= 0 && cok) atomicAdd(A.Gam + (int64_t)gj * kpad + col, brow[rt][e] * hc - 2.0 * acc[e]);
+      for (int t = 0; t < CW; ++t) {
+        const int c = c0 + t * 64 + lane;
+        if (c < A.k) acc[t] += (b0 * p0[c] + w0 * q0[c]) + (b1 * p1[c] + w1 * q1[c]);
       }
+    }
+#pragma unroll
+    for (int t = 0; t < CW; ++t) {
+      const int c = c0 + t * 64 + lane;
+      if (c < A.kpad) out[c] = acc[t];
     }
   }
 }
@@ -508,8 +567,23 @@ hipError_t launch_cross_deriv(const GradKern& G, int P, int64_t n, int k, int ld
   return hipGetLastError();
 }
 
+hipError_t launch_slot_fill(int64_t nslots, const int32_t* key, const int32_t* off, int32_t* fill,
+                            int32_t* list, hipStream_t s) {
+  if (nslots <= 0) return hipSuccess;
+  hipLaunchKernelGGL(slot_fill_kernel, dim3((unsigned)((nslots + 255) / 256)), dim3(256), 0, s, nslots,
+                     key, off, fill, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_gamma_gather(const GammaArgs& a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gamma_gather_kernel, dim3((unsigned)((a.n + 3) / 4)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_vif_grad_points(const VifGradArgs& a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
+  // the slot arrays (bw, key) hold 32 slots per point for m < 32, else 64
   if (a.m < 32) {
     hipLaunchKernelGGL(vif_grad_point_kernel<32>, dim3((unsigned)((a.n + 3) / 4)), dim3(256), 0, s, a);
   } else {

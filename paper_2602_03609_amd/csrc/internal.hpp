@@ -98,6 +98,8 @@ hipError_t launch_validate_times(int64_t n, const double* t, uint32_t* flag, hip
 // out[0..3] = min sx, max sx, min sy, max sy (partial: 4 * 256 doubles of scratch).
 hipError_t launch_bbox(int64_t n, const double* sx, const double* sy, double* partial,
                        double* out, hipStream_t s);
+// In-place exclusive scan of a[0 .. len); bsum: (len + 1023) / 1024 entries of scratch.
+hipError_t launch_exclusive_scan(int32_t* a, int64_t len, int32_t* bsum, hipStream_t s);
 // Builds the CSR grid: counts/fill [nslab*ncell + 1], bsum [scan scratch], key [n].
 hipError_t launch_grid_build(int64_t n, const double* sx, const double* sy, const double* t,
                              double t0, const GridArgs& g, int32_t* counts, int32_t* fill,
@@ -303,11 +305,34 @@ struct VifGradArgs {
   const int32_t* nbr;
   const double* Lfac;  // [n, lrows, lrows] residual-block factors, lower triangle by rows
   const double* U;     // [n, kpad]
-  const double* H;     // [n, kpad]: W M^-1 - e v'
+  const double* W;     // [n, kpad]: the forward pass's W (FP64; column k holds z)
+  double* H;           // [n, kpad]: W M^-1 - e v' on entry; phi on return (below)
   const double* e;     // [n]: z - W v
-  double* Gam;         // [n, kpad], accumulated (zeroed by the caller)
   double* blk;         // [P, n] per-point <Lambda_i, dC_S + dnugget I>
+  // Gamma's terms per conditioning slot: row i of Gamma's sum over (i, r) is
+  // b_ir phi_i + w_ir W_i (phi_i = h_i - (1 + b.g) W_i + U_S' w_i, written over H);
+  // bw[(i * QMAX + r) * 2 + {0, 1}] = (b_ir, w_ir), key[i * QMAX + r] = S_ir (-1 past q),
+  // cnt[j] += the number of slots with S_ir = j (zeroed by the caller).
+  double* bw;
+  int32_t* key;
+  int32_t* cnt;
+};
+// Gamma_j = sum over slots (i, r) with S_ir = j of b_ir phi_i + w_ir W_i, from the
+// slots listed by j (CSR off/list, each list summed in increasing slot order).
+struct GammaArgs {
+  int64_t n;
+  int k, kpad, qmax;
+  const double* phi;   // [n, kpad]
+  const double* W;     // [n, kpad]
+  const double* bw;    // [n * qmax, 2]
+  const int32_t* off;  // [n + 1]
+  const int32_t* list; // slots
+  double* Gam;         // [n, kpad], written whole (zero past k)
 };
 hipError_t launch_vif_grad_points(const VifGradArgs& a, hipStream_t s);
+// list[off[j] + ..] = slots with key = j (fill zeroed by the caller; any order).
+hipError_t launch_slot_fill(int64_t nslots, const int32_t* key, const int32_t* off, int32_t* fill,
+                            int32_t* list, hipStream_t s);
+hipError_t launch_gamma_gather(const GammaArgs& a, hipStream_t s);
 
 }  // namespace vif

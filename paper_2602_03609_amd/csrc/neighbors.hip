@@ -491,6 +491,15 @@ hipError_t launch_bbox(int64_t n, const double* sx, const double* sy, double* pa
   return hipGetLastError();
 }
 
+hipError_t launch_exclusive_scan(int32_t* a, int64_t len, int32_t* bsum, hipStream_t s) {
+  if (len <= 0) return hipSuccess;
+  const int nb = (int)((len + 1023) / 1024);
+  hipLaunchKernelGGL(scan_tiles_kernel, dim3(nb), dim3(1024), 0, s, a, len, bsum);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, s, bsum, nb);
+  hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(1024), 0, s, a, len, (const int32_t*)bsum);
+  return hipGetLastError();
+}
+
 hipError_t launch_grid_build(int64_t n, const double* sx, const double* sy, const double* t,
                              double t0, const GridArgs& g, int32_t* counts, int32_t* fill,
                              int32_t* bsum, int32_t* key, double* px, double* py, int32_t* pidx,
