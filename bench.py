@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-prec", default="fp32", choices=list(PREC_ES))
     ap.add_argument("--batch-reps", type=int, default=10)
+    ap.add_argument("--batch-schedule", default=None,
+                    help="STREAMS,ROWS: a fixed batch schedule instead of the autotuned one")
     ap.add_argument("--residual", action="store_true",
                     help="time the residual-correlation neighbor search on the n=100k, k=500 "
                          "workload and print its own JSON line")
@@ -180,9 +182,14 @@ def batch_eval(args):
     points = sum(d["n"] for d in ds)
     prec = args.batch_prec
     b = vif.Batch(probs, prec=prec)
-    tune_ms = b.autotune(reps=2)
-    streams, rows = b.schedule()
-    log(f"batch: autotuned schedule streams={streams} rows={rows} ({tune_ms:.2f} ms)")
+    if args.batch_schedule:
+        streams, rows = (int(v) for v in args.batch_schedule.split(","))
+        b.set_schedule(streams, rows)
+        log(f"batch: fixed schedule streams={streams} rows={rows}")
+    else:
+        tune_ms = b.autotune(reps=2)
+        streams, rows = b.schedule()
+        log(f"batch: autotuned schedule streams={streams} rows={rows} ({tune_ms:.2f} ms)")
     b.graph_launch()
     torch.cuda.synchronize()
     st = b.status()

@@ -398,8 +398,8 @@ int32_t build_order(const vif_points* p, char* ws, const Layout& L, hipStream_t 
 }
 
 // Sigma_k, its Cholesky factor and inverse, then U = C(X,Z) L_k^-T.
-int32_t run_lowrank(const vif_points* p, const vif_points* ind, const vif_kernel* kern, int prec,
-                    char* ws, const Layout& L, hipStream_t s) {
+vif::LowRankArgs lowrank_args(const vif_points* p, const vif_points* ind, const vif_kernel* kern,
+                              const Layout& L) {
   vif::LowRankArgs a{};
   a.n = p->n;
   a.k = (int)ind->n;
@@ -408,14 +408,13 @@ int32_t run_lowrank(const vif_points* p, const vif_points* ind, const vif_kernel
   a.jitter = kern->jitter;
   a.sx = p->sx; a.sy = p->sy; a.t = p->t;
   a.zx = ind->sx; a.zy = ind->sy; a.zt = ind->t;
-  double* Sk = reinterpret_cast<double*>(ws + L.Sk);
-  double* P = reinterpret_cast<double*>(ws + L.P);
-  auto* fl = reinterpret_cast<unsigned long long*>(ws + L.flags);
-  PROF(VIF_STAGE_SIGMA_K, false);
-  HIPCHK(vif::launch_cov_kk(a, Sk, s));
-  HIPCHK(vif::launch_cholesky(L.kpad, Sk, reinterpret_cast<double*>(ws + L.dscr), fl + 1, s));
-  HIPCHK(vif::launch_trinv(L.kpad, Sk, P, reinterpret_cast<double*>(ws + L.dscr), s));
-  PROF(VIF_STAGE_SIGMA_K, true);
+  return a;
+}
+
+// U from L_k^-1 (in L.P): fused on chip in the split modes, else cross-covariance
+// then an in-place product.
+int32_t run_u(const vif::LowRankArgs& a, int prec, char* ws, const Layout& L, hipStream_t s) {
+  const double* P = reinterpret_cast<const double*>(ws + L.P);
   if (prec >= VIF_PREC_BF16X3 && vif::lowrank_fused_ok(L.kpad, prec)) {
     // Cross-covariance evaluated on chip inside the product.
     PROF(VIF_STAGE_TRMM, false);
@@ -430,6 +429,20 @@ int32_t run_lowrank(const vif_points* p, const vif_points* ind, const vif_kernel
   HIPCHK(vif::launch_trmm(a, P, ws + L.U, prec, s));
   PROF(VIF_STAGE_TRMM, true);
   return VIF_OK;
+}
+
+int32_t run_lowrank(const vif_points* p, const vif_points* ind, const vif_kernel* kern, int prec,
+                    char* ws, const Layout& L, hipStream_t s) {
+  const vif::LowRankArgs a = lowrank_args(p, ind, kern, L);
+  double* Sk = reinterpret_cast<double*>(ws + L.Sk);
+  double* P = reinterpret_cast<double*>(ws + L.P);
+  auto* fl = reinterpret_cast<unsigned long long*>(ws + L.flags);
+  PROF(VIF_STAGE_SIGMA_K, false);
+  HIPCHK(vif::launch_cov_kk(a, Sk, s));
+  HIPCHK(vif::launch_cholesky(L.kpad, Sk, reinterpret_cast<double*>(ws + L.dscr), fl + 1, s));
+  HIPCHK(vif::launch_trinv(L.kpad, Sk, P, reinterpret_cast<double*>(ws + L.dscr), s));
+  PROF(VIF_STAGE_SIGMA_K, true);
+  return run_u(a, prec, ws, L, s);
 }
 
 int32_t check_ind(const vif_points* ind, int* k) {
@@ -1625,16 +1638,20 @@ void drop_graph(vif_batch* b) {
 }
 
 // One problem's NLL, kernels only (capturable): the path of vif_nll with the
-// host-side quantities taken from the plan.
+// host-side quantities taken from the plan, in three stages so that the batch can
+// factor every problem's Sigma_k (after stage 0) and M (after stage 1) together:
+//   stage 0: flags; with inducing points, the processing order, the lag table and Sigma_k;
+//   stage 1: with inducing points, L_k^-1, U, the per-point factor, the Gram and M;
+//            without, the whole NLL;
+//   stage 2: with inducing points, the sums and the finalisation.
 int32_t enqueue_problem(const ProbPlan& P, int prec, int chunk_rows, char* wsb, double* nll_out,
-                        hipStream_t s) {
+                        int stage, hipStream_t s) {
   const Layout& L = P.L;
   char* ws = wsb + P.off;
   auto* fl = reinterpret_cast<unsigned long long*>(ws + L.flags);
   double* sums = reinterpret_cast<double*>(ws + L.sums);
   double* part = reinterpret_cast<double*>(ws + L.part);
   double* out = reinterpret_cast<double*>(ws + L.out);
-  HIPCHK(vif::launch_init_flags(ws + L.flags, s));
   vif::FactorArgs fa{};
   fa.n = P.p.n;
   fa.m = P.m;
@@ -1648,65 +1665,110 @@ int32_t enqueue_problem(const ProbPlan& P, int prec, int chunk_rows, char* wsb, 
   fa.fail = fl;
   fa.bad_nbr = fl + 3;
   if (P.k > 0) {
-    vif::GridArgs g = P.og;
-    HIPCHK(vif::launch_grid_build(P.p.n, P.p.sx, P.p.sy, P.p.t, P.t0, g,
-                                  reinterpret_cast<int32_t*>(ws + L.counts),
-                                  reinterpret_cast<int32_t*>(ws + L.fill),
-                                  reinterpret_cast<int32_t*>(ws + L.bsum),
-                                  reinterpret_cast<int32_t*>(ws + L.key), nullptr, nullptr,
-                                  reinterpret_cast<int32_t*>(ws + L.pidx), s));
-    fa.ord = reinterpret_cast<const int32_t*>(ws + L.pidx);
-    if (P.kern.kind == VIF_KERNEL_GNEITING && P.nlag > 0) {
-      HIPCHK(vif::launch_lag_table(to_dev(&P.kern), P.nlag, prec, ws + L.lag, s));
-      fa.lagtab = ws + L.lag;
+    const vif::LowRankArgs a = lowrank_args(&P.p, &P.ind, &P.kern, L);
+    if (stage == 0) {
+      HIPCHK(vif::launch_init_flags(ws + L.flags, s));
+      vif::GridArgs g = P.og;
+      HIPCHK(vif::launch_grid_build(P.p.n, P.p.sx, P.p.sy, P.p.t, P.t0, g,
+                                    reinterpret_cast<int32_t*>(ws + L.counts),
+                                    reinterpret_cast<int32_t*>(ws + L.fill),
+                                    reinterpret_cast<int32_t*>(ws + L.bsum),
+                                    reinterpret_cast<int32_t*>(ws + L.key), nullptr, nullptr,
+                                    reinterpret_cast<int32_t*>(ws + L.pidx), s));
+      if (P.kern.kind == VIF_KERNEL_GNEITING && P.nlag > 0)
+        HIPCHK(vif::launch_lag_table(to_dev(&P.kern), P.nlag, prec, ws + L.lag, s));
+      HIPCHK(vif::launch_cov_kk(a, reinterpret_cast<double*>(ws + L.Sk), s));
+      return VIF_OK;
     }
-    int32_t st = run_lowrank(&P.p, &P.ind, &P.kern, prec, ws, L, s);
-    if (st) return st;
-    fa.U = ws + L.U;
-    fa.W = ws + L.W;
-    fa.wrb = vif::w_plane_rows(P.p.n) / 8;
-    HIPCHK(vif::launch_point_factor(fa, 0, prec, s));
-    double* M = reinterpret_cast<double*>(ws + L.M);
-    double* q = reinterpret_cast<double*>(ws + L.q);
-    const int64_t wrows = prec >= VIF_PREC_BF16X3 ? vif::w_plane_rows(P.p.n) : P.p.n;
-    const int nchunk = vif::syrk_chunks(wrows, L.kpad, prec, chunk_rows);
-    HIPCHK(vif::launch_syrk(wrows, L.kpad, ws + L.W, prec, ws + L.syrk, nchunk, s, chunk_rows));
-    HIPCHK(vif::launch_syrk_reduce(P.k, L.kpad, ws + L.syrk, prec, nchunk, M, q, sums + 2, s));
-    HIPCHK(vif::launch_cholesky(L.kpad, M, reinterpret_cast<double*>(ws + L.dscr), fl + 2, s));
+    if (stage == 1) {
+      HIPCHK(vif::launch_trinv(L.kpad, reinterpret_cast<double*>(ws + L.Sk),
+                               reinterpret_cast<double*>(ws + L.P),
+                               reinterpret_cast<double*>(ws + L.dscr), s));
+      int32_t st = run_u(a, prec, ws, L, s);
+      if (st) return st;
+      fa.ord = reinterpret_cast<const int32_t*>(ws + L.pidx);
+      if (P.kern.kind == VIF_KERNEL_GNEITING && P.nlag > 0) fa.lagtab = ws + L.lag;
+      fa.U = ws + L.U;
+      fa.W = ws + L.W;
+      fa.wrb = vif::w_plane_rows(P.p.n) / 8;
+      HIPCHK(vif::launch_point_factor(fa, 0, prec, s));
+      double* M = reinterpret_cast<double*>(ws + L.M);
+      double* q = reinterpret_cast<double*>(ws + L.q);
+      const int64_t wrows = prec >= VIF_PREC_BF16X3 ? vif::w_plane_rows(P.p.n) : P.p.n;
+      const int nchunk = vif::syrk_chunks(wrows, L.kpad, prec, chunk_rows);
+      HIPCHK(vif::launch_syrk(wrows, L.kpad, ws + L.W, prec, ws + L.syrk, nchunk, s, chunk_rows));
+      HIPCHK(vif::launch_syrk_reduce(P.k, L.kpad, ws + L.syrk, prec, nchunk, M, q, sums + 2, s));
+      return VIF_OK;
+    }
     HIPCHK(vif::launch_sum(P.p.n, fa.logD, 0, part, sums + 0, s));
     HIPCHK(vif::launch_sum(P.p.n, fa.z, 1, part, sums + 1, s));
-    HIPCHK(vif::launch_finalize(P.p.n, P.k, L.kpad, M, sums + 0, sums + 1, out, s));
-  } else {
-    HIPCHK(vif::launch_point_factor(fa, 0, prec, s));
-    HIPCHK(vif::launch_sum(P.p.n, fa.logD, 0, part, sums + 0, s));
-    HIPCHK(vif::launch_sum(P.p.n, fa.z, 1, part, sums + 1, s));
-    HIPCHK(vif::launch_finalize(P.p.n, 0, 0, nullptr, sums + 0, sums + 1, out, s));
+    HIPCHK(vif::launch_finalize(P.p.n, P.k, L.kpad, reinterpret_cast<double*>(ws + L.M), sums + 0,
+                                sums + 1, out, s));
+    HIPCHK(vif::launch_copy_f64(out, nll_out, s));
+    return VIF_OK;
   }
+  if (stage == 0) {
+    HIPCHK(vif::launch_init_flags(ws + L.flags, s));
+    return VIF_OK;
+  }
+  if (stage == 2) return VIF_OK;
+  HIPCHK(vif::launch_point_factor(fa, 0, prec, s));
+  HIPCHK(vif::launch_sum(P.p.n, fa.logD, 0, part, sums + 0, s));
+  HIPCHK(vif::launch_sum(P.p.n, fa.z, 1, part, sums + 1, s));
+  HIPCHK(vif::launch_finalize(P.p.n, 0, 0, nullptr, sums + 0, sums + 1, out, s));
   HIPCHK(vif::launch_copy_f64(out, nll_out, s));
+  return VIF_OK;
+}
+
+// The factorisations of every problem's Sigma_k (which = 1) or M (which = 2) as
+// one set: one panel and one update launch per step for all of them.
+int32_t batch_cholesky(const vif_batch* b, char* wsb, int which, hipStream_t s) {
+  std::vector<double*> A, scr;
+  std::vector<int> N;
+  std::vector<unsigned long long*> fl;
+  for (const ProbPlan& P : b->probs) {
+    if (P.k == 0) continue;
+    char* ws = wsb + P.off;
+    A.push_back(reinterpret_cast<double*>(ws + (which == 1 ? P.L.Sk : P.L.M)));
+    N.push_back(P.L.kpad);
+    scr.push_back(reinterpret_cast<double*>(ws + P.L.dscr));
+    fl.push_back(reinterpret_cast<unsigned long long*>(ws + P.L.flags) + which);
+  }
+  if (A.empty()) return VIF_OK;
+  HIPCHK(vif::launch_cholesky_set((int)A.size(), A.data(), N.data(), scr.data(), fl.data(), s));
   return VIF_OK;
 }
 
 int32_t batch_enqueue(vif_batch* b, char* ws, double* nll, hipStream_t s) {
   const int ns = b->streams;
   const int np = (int)b->probs.size();
-  if (ns > 1) {
-    HIPCHK(hipEventRecord(b->ev_fork, s));
-    for (int j = 0; j < ns; ++j) HIPCHK(hipStreamWaitEvent(b->side[j], b->ev_fork, 0));
-  }
-  // largest problems first, round-robin over the streams
-  for (int r = 0; r < np; ++r) {
-    const int i = r;
-    hipStream_t ss = ns > 1 ? b->side[r % ns] : s;
-    int32_t st = enqueue_problem(b->probs[i], b->prec, b->chunk_rows, ws, nll + i, ss);
-    if (st) return st;
-  }
-  if (ns > 1) {
-    for (int j = 0; j < ns; ++j) {
-      HIPCHK(hipEventRecord(b->ev_join[j], b->side[j]));
-      HIPCHK(hipStreamWaitEvent(s, b->ev_join[j], 0));
+  auto fork = [&]() -> int32_t {
+    if (ns > 1) {
+      HIPCHK(hipEventRecord(b->ev_fork, s));
+      for (int j = 0; j < ns; ++j) HIPCHK(hipStreamWaitEvent(b->side[j], b->ev_fork, 0));
     }
+    return VIF_OK;
+  };
+  auto join = [&]() -> int32_t {
+    if (ns > 1) {
+      for (int j = 0; j < ns; ++j) {
+        HIPCHK(hipEventRecord(b->ev_join[j], b->side[j]));
+        HIPCHK(hipStreamWaitEvent(s, b->ev_join[j], 0));
+      }
+    }
+    return VIF_OK;
+  };
+  int32_t st = VIF_OK;
+  for (int stage = 0; stage < 3 && !st; ++stage) {
+    // problems round-robin over the streams, largest first
+    if ((st = fork())) break;
+    for (int i = 0; i < np && !st; ++i)
+      st = enqueue_problem(b->probs[i], b->prec, b->chunk_rows, ws, nll + i, stage,
+                           ns > 1 ? b->side[i % ns] : s);
+    if (st || (st = join())) break;
+    if (stage < 2) st = batch_cholesky(b, ws, stage + 1, s);
   }
-  return VIF_OK;
+  return st;
 }
 
 int32_t batch_check(const vif_batch* b, void* ws, size_t ws_bytes, const double* nll) {

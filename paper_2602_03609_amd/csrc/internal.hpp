@@ -161,6 +161,20 @@ hipError_t launch_cholesky(int N, double* A, double* scratch, unsigned long long
 // diagonal); T: scratch of trinv_scratch_bytes(N).
 size_t trinv_scratch_bytes(int N);
 hipError_t launch_trinv(int N, const double* L, double* P, double* T, hipStream_t s);
+// The blocked Cholesky of `count` matrices (each N[i] x N[i], N[i] a multiple of
+// 64, in place, scratch[i] and fail[i] as for launch_cholesky) with one panel and
+// one update launch per step for all of them (up to kCholSet per launch).
+constexpr int kCholSet = 32;
+struct CholSet {
+  int count, jb;
+  int pre[kCholSet + 1];
+  double* A[kCholSet];
+  double* dscr[kCholSet];
+  unsigned long long* fail[kCholSet];
+  int N[kCholSet];
+};
+hipError_t launch_cholesky_set(int count, double* const* A, const int* N, double* const* scratch,
+                               unsigned long long* const* fail, hipStream_t s);
 // U[i, l] = C(x_i, z_l) for l < k, 0 for k <= l < kpad; FP64 (prec 0) or FP32 (prec >= 1).
 hipError_t launch_crosscov(const LowRankArgs& a, void* U, int prec, hipStream_t s);
 // In place: U[i, :] <- U[i, :] P^T with P lower triangular (U = C(X,Z) L_k^-T).

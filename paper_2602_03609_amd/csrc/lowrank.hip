@@ -77,16 +77,15 @@ __device__ __forceinline__ double readlane_f64(double x, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// Panel kernel: block w factors the diagonal block jb (redundantly) and, for
+// Panel step: block w factors the diagonal block jb (redundantly) and, for
 // w > 0, solves row block jb + w of the panel against it.
-__global__ __launch_bounds__(256) void chol_panel_kernel(int N, double* __restrict__ A, int jb,
-                                                         unsigned long long* fail,
-                                                         double* __restrict__ dscr) {
+__device__ __forceinline__ void chol_panel_body(int N, double* __restrict__ A, int jb,
+                                                unsigned long long* fail,
+                                                double* __restrict__ dscr, const int w) {
   __shared__ double Ld[NB][NB + 1];
   __shared__ double rd[NB];
   __shared__ int bad;
   const int tid = threadIdx.x;
-  const int w = blockIdx.x;
   const int64_t d0 = (int64_t)jb * NB;
   const int lane = tid & 63, s = tid >> 2, g = tid & 3;
   // Right-looking factorisation of the diagonal block by wave 0 in registers:
@@ -147,19 +146,28 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(int N, double* __restri
   for (int i = 0; i < 16; ++i) A[(r0 + s) * N + d0 + g + 4 * i] = v[i];
 }
 
+__global__ __launch_bounds__(256) void chol_panel_kernel(int N, double* __restrict__ A, int jb,
+                                                         unsigned long long* fail,
+                                                         double* __restrict__ dscr) {
+  chol_panel_body(N, A, jb, fail, dscr, blockIdx.x);
+}
+
 // Trailing update of tile (IB, JB), jb < JB <= IB: A_IJ -= L_I,jb L_J,jb'.
 // The last block copies the factored diagonal block from scratch into A.
-__global__ __launch_bounds__(256) void chol_update_kernel(int N, double* __restrict__ A, int jb,
-                                                          const double* __restrict__ dscr) {
+// Update step: block b < nblk - 1 updates one lower trailing block; the last one
+// copies the factored diagonal block into place.
+__device__ __forceinline__ void chol_update_body(int N, double* __restrict__ A, int jb,
+                                                 const double* __restrict__ dscr, const int b,
+                                                 const int nblk) {
   __shared__ double La[NB][NB + 1];
   __shared__ double Lb[NB][NB + 1];
-  if (blockIdx.x == gridDim.x - 1) {
+  if (b == nblk - 1) {
     const int64_t d0 = (int64_t)jb * NB;
     for (int e = threadIdx.x; e < NB * NB; e += 256) A[(d0 + e / NB) * N + d0 + e % NB] = dscr[e];
     return;
   }
-  // Map blockIdx.x to (IB, JB) over the lower triangle of the trailing blocks.
-  int t = blockIdx.x, IB = jb + 1;
+  // Map b to (IB, JB) over the lower triangle of the trailing blocks.
+  int t = b, IB = jb + 1;
   while (t >= IB - jb) {
     t -= IB - jb;
     ++IB;
@@ -190,6 +198,31 @@ __global__ __launch_bounds__(256) void chol_update_kernel(int N, double* __restr
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) A[(ra + tr + 16 * i) * N + rb + tc + 16 * j] -= acc[i][j];
+}
+
+__global__ __launch_bounds__(256) void chol_update_kernel(int N, double* __restrict__ A, int jb,
+                                                          const double* __restrict__ dscr) {
+  chol_update_body(N, A, jb, dscr, blockIdx.x, gridDim.x);
+}
+
+// One panel or update step of the blocked Cholesky for a set of matrices at once:
+// the launch's blocks are dealt to the matrices by the prefix pre[] (matrix p
+// takes blocks pre[p] .. pre[p + 1] - 1), so independent factorisations share
+// the step's launch instead of queueing their own.
+__device__ __forceinline__ int cholset_member(const CholSet& S, int b) {
+  int p = 0;
+  while (p + 1 < S.count && b >= S.pre[p + 1]) ++p;
+  return p;
+}
+
+__global__ __launch_bounds__(256) void chol_panel_set_kernel(CholSet S) {
+  const int p = cholset_member(S, blockIdx.x);
+  chol_panel_body(S.N[p], S.A[p], S.jb, S.fail[p], S.dscr[p], blockIdx.x - S.pre[p]);
+}
+
+__global__ __launch_bounds__(256) void chol_update_set_kernel(CholSet S) {
+  const int p = cholset_member(S, blockIdx.x);
+  chol_update_body(S.N[p], S.A[p], S.jb, S.dscr[p], blockIdx.x - S.pre[p], S.pre[p + 1] - S.pre[p]);
 }
 
 // ----------------------------------------------------------- triangular inverse
@@ -1097,6 +1130,50 @@ hipError_t launch_cholesky(int N, double* A, double* scratch, unsigned long long
                        (const double*)scratch);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_cholesky_set(int count, double* const* A, const int* N, double* const* scratch,
+                               unsigned long long* const* fail, hipStream_t s) {
+  int maxnt = 0;
+  for (int i = 0; i < count; ++i) maxnt = N[i] / NB > maxnt ? N[i] / NB : maxnt;
+  for (int jb = 0; jb < maxnt; ++jb) {
+    for (int phase = 0; phase < 2; ++phase) {
+      // the matrices still factoring at this step, kCholSet per launch
+      CholSet S{};
+      S.jb = jb;
+      auto flush = [&]() {
+        if (S.count == 0) return hipSuccess;
+        if (phase == 0)
+          hipLaunchKernelGGL(chol_panel_set_kernel, dim3((unsigned)S.pre[S.count]), dim3(256), 0, s, S);
+        else
+          hipLaunchKernelGGL(chol_update_set_kernel, dim3((unsigned)S.pre[S.count]), dim3(256), 0, s, S);
+        const hipError_t e = hipGetLastError();
+        S.count = 0;
+        S.pre[0] = 0;
+        return e;
+      };
+      S.pre[0] = 0;
+      for (int i = 0; i < count; ++i) {
+        const int NT = N[i] / NB;
+        if (NT <= jb) continue;
+        const int nt = NT - jb - 1;
+        const int nblk = phase == 0 ? NT - jb : nt * (nt + 1) / 2 + 1;
+        S.A[S.count] = A[i];
+        S.N[S.count] = N[i];
+        S.dscr[S.count] = scratch[i];
+        S.fail[S.count] = fail[i];
+        S.pre[S.count + 1] = S.pre[S.count] + nblk;
+        ++S.count;
+        if (S.count == kCholSet) {
+          const hipError_t e = flush();
+          if (e != hipSuccess) return e;
+        }
+      }
+      const hipError_t e = flush();
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
 }
 
 size_t trinv_scratch_bytes(int N) {
