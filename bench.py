@@ -455,6 +455,17 @@ def mfma_peak(prec):
     return PEAK["bf16_TFs"]
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(d, m, n_query=6000, n_point=24000):
     """The FP64 oracle, timed on a bounded sample of the same workload (about 15 s)."""
     import numpy as np
@@ -498,6 +509,8 @@ def cpu_baseline(d, m, n_query=6000, n_point=24000):
         "value": 1.0 / t_step,
         "unit": "evals/s",
         "cores": int(blas_threads),
+        "host_cpus": os.cpu_count(),
+        "cpu_model": cpu_model(),
         "kind": "oracle",
         "sample": (f"FP64 NumPy/SciPy oracle: lag-pruned exact neighbor search on {n_query} "
                    f"sampled queries and the VIF per-point factor (U rows by triangular solve, "
@@ -583,8 +596,11 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     nll = None
+    step_ms = []  # each call returns after its stream has drained
     for _ in range(args.steps):
+        a = time.perf_counter()
         nll = step(args.prec)
+        step_ms.append((time.perf_counter() - a) * 1000.0)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = vif.vif_profile_read()
@@ -651,6 +667,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "step_ms": {"median": float(np.median(step_ms)), "p10": float(np.percentile(step_ms, 10)),
+                    "p90": float(np.percentile(step_ms, 90))},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
