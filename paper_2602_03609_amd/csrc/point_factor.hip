@@ -32,6 +32,21 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
 
+// One bfloat16 term of four values: returns bf16(rem) and leaves rem - that term
+// in rem (the term's float values taken from its bits, so that the packed
+// conversion is not repeated per value).
+__device__ __forceinline__ bf4v bf16_term(f4v& rem) {
+  bf4v hv;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) hv[c] = (__bf16)rem[c];
+  const uint2 u = __builtin_bit_cast(uint2, hv);
+  rem[0] -= __uint_as_float(u.x << 16);
+  rem[1] -= __uint_as_float(u.x & 0xffff0000u);
+  rem[2] -= __uint_as_float(u.y << 16);
+  rem[3] -= __uint_as_float(u.y & 0xffff0000u);
+  return hv;
+}
+
 template <int PREC> struct PrecT;
 template <> struct PrecT<0> { using T = double; using UT = double; };
 template <> struct PrecT<1> { using T = float; using UT = float; };
@@ -101,7 +116,10 @@ __device__ __forceinline__ bool seg_gauss_jordan(T (&a)[ROWS], T& yv, T& xo, con
       const bool good = !act || ((piv0 > T(0)) && (piv0 < T(INFINITY)));
       ok = ok && good;
       const T piv = (act && good) ? piv0 : T(1);
-      const T f = (act && r != k) ? a[k] / piv : T(0);
+      // the hardware reciprocal and one Newton step instead of a division
+      T inv = __builtin_amdgcn_rcpf(piv);
+      inv = inv * (T(2) - piv * inv);
+      const T f = (act && r != k) ? a[k] * inv : T(0);
       if (r == k) pivr = piv;
       yv -= f * col[ROWS + 1 + k];
 #pragma unroll
@@ -312,7 +330,8 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
   constexpr bool SPLIT = PREC >= 2;
   constexpr int NSP = PREC == 3 ? 3 : 2;
   constexpr int BPAD = 8;  // bf16 row padding (16 bytes)
-  constexpr size_t SPL_B = SPLIT ? (size_t)NSLOT * NSP * (KC + BPAD) * 2 : 0;
+  constexpr int ZROW = 4 * KC;
+  constexpr size_t SPL_B = SPLIT ? ((size_t)NSLOT * NSP * (KC + BPAD) + ZROW) * 2 : 0;
   constexpr size_t B1 = STAGE_B + SEL_B > MAT_B ? STAGE_B + SEL_B : MAT_B;
   constexpr size_t BIG_B = SPL_B > B1 ? SPL_B : B1;
   __shared__ __attribute__((aligned(16))) unsigned char sBig[BIG_B];
@@ -537,7 +556,7 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
   // gathers fall on different LDS banks unless their slots coincide modulo 16
   // (rows of interleaved planes, an even number of units apart, collided modulo 8).
   auto pick_width_split = [&]() {
-    const int capb = (int)(BIG_B / 2);
+    const int capb = (int)(BIG_B / 2) - ZROW;
     const int capp = MAXP * NTH * VPE;
     for (int w = 4 * KC; w > KC; w >>= 1)
       if (nu * NSP * (w + BPAD) <= capb && nu * w <= capp && A.ldu % (2 * w) == 0) return w;
@@ -572,16 +591,8 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
           // x = t_0 + t_1 (+ t_2), each term the bfloat16 rounding of the remainder.
           f4v rem = pre[j];
 #pragma unroll
-          for (int sp = 0; sp < NSP; ++sp) {
-            bf4v hv;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              const __bf16 h = (__bf16)rem[c];
-              hv[c] = h;
-              rem[c] -= (float)h;
-            }
-            *reinterpret_cast<bf4v*>(splane + (sp * nu + row) * sld + piece * 4) = hv;
-          }
+          for (int sp = 0; sp < NSP; ++sp)
+            *reinterpret_cast<bf4v*>(splane + (sp * nu + row) * sld + piece * 4) = bf16_term(rem);
         } else {
           *reinterpret_cast<f4v*>(stage + row * sld + piece * VPE) = pre[j];
         }
@@ -725,7 +736,67 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
     }
     }
   };
-  run_pass(gram_chunk, false);
+  if constexpr (SPLIT && PPW > 1 && NSP == 2) {
+    // BF16X3 with two or more points per wave: each (sub-step, point) pair's
+    // fragments load while the previous pair's products run, from offsets fixed
+    // for the pass; empty slots read the zero block (no masked loads).
+    const int zoff = (int)(BIG_B / 2) - ZROW;
+    for (int e = tid; e < ZROW; e += NTH) splane[zoff + e] = (__bf16)0.f;
+    int fo[PPW][NT][NSP];
+#pragma unroll
+    for (int s2 = 0; s2 < PPW; ++s2)
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti) {
+        const int sl = sSlot[wave * PPW + s2][ti * 16 + rr16];
+#pragma unroll
+        for (int sp = 0; sp < NSP; ++sp) fo[s2][ti][sp] = (sl >= 0 ? (sp * nu + sl) * sld : zoff) + kq * 8;
+      }
+    auto ld = [&](bf8v (&pt)[NT][NSP], const int (&o)[NT][NSP], int sub) __attribute__((always_inline)) {
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int sp = 0; sp < NSP; ++sp)
+          pt[ti][sp] = *reinterpret_cast<const bf8v*>(splane + o[ti][sp] + sub);
+    };
+    auto mm = [&](const bf8v (&part)[NT][NSP], AccT (&ac)[NTT]) __attribute__((always_inline)) {
+      int t = 0;
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int tj = 0; tj <= ti; ++tj) {
+          if constexpr (NSP == 3) {
+            ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][2], part[tj][0], ac[t], 0, 0, 0);
+            ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][1], part[tj][1], ac[t], 0, 0, 0);
+            ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][0], part[tj][2], ac[t], 0, 0, 0);
+          } else if (ti == tj) {
+            // low-by-low product on the diagonal tiles (a sum of squares there)
+            ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][1], part[tj][1], ac[t], 0, 0, 0);
+          }
+          ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][1], part[tj][0], ac[t], 0, 0, 0);
+          ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][0], part[tj][1], ac[t], 0, 0, 0);
+          ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part[ti][0], part[tj][0], ac[t], 0, 0, 0);
+          ++t;
+        }
+    };
+    auto gram_chunk_split = [&](int) __attribute__((always_inline)) {
+      bf8v buf[2][NT][NSP];
+      ld(buf[0], fo[0], 0);
+      for (int sub = 0; sub < cw; sub += KC) {
+        const int nx = sub + KC < cw ? sub + KC : sub;  // past the end: re-read (unused)
+#pragma unroll
+        for (int s2 = 0; s2 < PPW; ++s2) {
+          if (s2 + 1 < PPW)
+            ld(buf[(s2 + 1) & 1], fo[s2 + 1], sub);
+          else
+            ld(buf[0], fo[0], nx);
+          mm(buf[s2 & 1], acc[s2]);
+        }
+      }
+    };
+    run_pass(gram_chunk_split, false);
+  } else {
+    run_pass(gram_chunk, false);
+  }
   // Grams into LDS (the staging area is free now), full symmetric matrices.
 #pragma unroll
   for (int s2 = 0; s2 < PPW; ++s2) {
@@ -927,17 +998,9 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
           for (int q4 = 0; q4 < 4; ++q4)
             v[q4] = (kc + col == A.k) ? (float)sZ[4 * h + q4] : (float)wt[(4 * h + q4) * wst + col];
 #pragma unroll
-          for (int sp = 0; sp < NSP; ++sp) {
-            bf4v hv;
-#pragma unroll
-            for (int q4 = 0; q4 < 4; ++q4) {
-              const __bf16 hb = (__bf16)v[q4];
-              hv[q4] = hb;
-              v[q4] -= (float)hb;
-            }
+          for (int sp = 0; sp < NSP; ++sp)
             *reinterpret_cast<bf4v*>(
-                Wp + ((sp * A.wrb + (row0 >> 3)) * A.ldu + kc + col) * 8 + (row0 & 7)) = hv;
-          }
+                Wp + ((sp * A.wrb + (row0 >> 3)) * A.ldu + kc + col) * 8 + (row0 & 7)) = bf16_term(v);
         }
       }
     };
