@@ -28,6 +28,11 @@ COMMON = [
 ]
 # Packed FP32 instructions are disabled for device code.
 DEVICE_ONLY = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Per-source options. The per-point kernels keep each lane's matrix column in a
+# fully unrolled register array; promoting it to one vector register tuple makes
+# every guarded elimination step copy the whole tuple, so that promotion is off
+# there (the other sources index some private arrays at run time and keep it).
+PER_SOURCE = {"point_factor.hip": ["-mllvm", "-disable-promote-alloca-to-vector"]}
 
 
 def hipcc():
@@ -41,7 +46,7 @@ def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     path = os.path.join(CSRC, src)
     if src.endswith(".hip"):
-        cmd = [hipcc(), *COMMON, *DEVICE_ONLY, "-c", path, "-o", obj]
+        cmd = [hipcc(), *COMMON, *DEVICE_ONLY, *PER_SOURCE.get(src, []), "-c", path, "-o", obj]
     else:
         cmd = [hipcc(), *COMMON, "-ffp-contract=off", "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)

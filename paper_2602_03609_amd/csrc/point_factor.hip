@@ -47,6 +47,21 @@ __device__ __forceinline__ bf4v bf16_term(f4v& rem) {
   return hv;
 }
 
+// v from the lane whose index differs in bit 0 (CTRL 0xB1) or bit 1 (CTRL 0x4E) of
+// the quad, as a DPP move (no LDS traffic).
+template <int CTRL>
+__device__ __forceinline__ float quad_xor(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double quad_xor(double v) {
+  const int2 h = __builtin_bit_cast(int2, v);
+  int2 o;
+  o.x = __builtin_amdgcn_update_dpp(0, h.x, CTRL, 0xF, 0xF, false);
+  o.y = __builtin_amdgcn_update_dpp(0, h.y, CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, o);
+}
+
 template <int PREC> struct PrecT;
 template <> struct PrecT<0> { using T = double; using UT = double; };
 template <> struct PrecT<1> { using T = float; using UT = float; };
@@ -107,9 +122,10 @@ __device__ __forceinline__ bool seg_gauss_jordan(T (&a)[ROWS], T& yv, T& xo, con
 #pragma unroll
   for (int k = 0; k < ROWS - 1; ++k) {
     if (k < kmax) {  // wave-uniform: the larger p of the wave's segments
-      T* col = col2 + (k & 1) * 2 * (ROWS + 1);
+      // column k and y, in 16-byte aligned halves (col2 holds 4 (ROWS + 4) values)
+      T* col = col2 + (k & 1) * 2 * (ROWS + 4);
       col[r] = a[k];
-      col[ROWS + 1 + r] = yv;
+      col[ROWS + 4 + r] = yv;
       wave_lds_sync();
       const bool act = k < p;
       const T piv0 = col[k];
@@ -121,7 +137,7 @@ __device__ __forceinline__ bool seg_gauss_jordan(T (&a)[ROWS], T& yv, T& xo, con
       inv = inv * (T(2) - piv * inv);
       const T f = (act && r != k) ? a[k] * inv : T(0);
       if (r == k) pivr = piv;
-      yv -= f * col[ROWS + 1 + k];
+      yv -= f * col[ROWS + 4 + k];
 #pragma unroll
       for (int j = k + 1; j < ROWS; ++j) a[j] -= f * col[j];
       __builtin_amdgcn_sched_barrier(0);
@@ -342,7 +358,7 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
   __shared__ int sNU;
   __shared__ int sLoHi[2];
   __shared__ double sX[GP][ROWS], sY[GP][ROWS], sT[GP][ROWS];
-  __shared__ T sCol[GP][4 * (ROWS + 1)];
+  __shared__ __attribute__((aligned(16))) T sCol[GP][4 * (ROWS + 4)];
   __shared__ T sBv[GP][ROWS];
   __shared__ T sZ[GP];
   __shared__ int64_t sI[GP];
@@ -572,14 +588,21 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
   // periods before its data go to LDS.
   f4v preA[MAXP], preB[MAXP];
   // Loads are unconditional (surplus lanes re-read the last piece) so that the
-  // compiler can count them exactly and wait for one register set only.
-  auto load_into = [&](f4v (&pre)[MAXP], int kc) __attribute__((always_inline)) {
+  // compiler can count them exactly and wait for one register set only. The
+  // addresses of a thread's pieces at column 0 are set once per pass; a chunk's
+  // load then adds its column.
+  const UT* pptr[MAXP];
+  auto set_ptrs = [&]() __attribute__((always_inline)) {
 #pragma unroll
     for (int j = 0; j < MAXP; ++j) {
       const int e = min(tid + j * NTH, npieces - 1);
       const int row = e >> lppr, piece = e & ((1 << lppr) - 1);
-      pre[j] = *reinterpret_cast<const f4v*>(U + (int64_t)sUniq[row] * A.ldu + kc + piece * VPE);
+      pptr[j] = U + (int64_t)sUniq[row] * A.ldu + piece * VPE;
     }
+  };
+  auto load_into = [&](f4v (&pre)[MAXP], int kc) __attribute__((always_inline)) {
+#pragma unroll
+    for (int j = 0; j < MAXP; ++j) pre[j] = *reinterpret_cast<const f4v*>(pptr[j] + kc);
   };
   auto store_from = [&](f4v (&pre)[MAXP]) __attribute__((always_inline)) {
 #pragma unroll
@@ -793,8 +816,10 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
         }
       }
     };
+    set_ptrs();
     run_pass(gram_chunk_split, false);
   } else {
+    set_ptrs();
     run_pass(gram_chunk, false);
   }
   // Grams into LDS (the staging area is free now), full symmetric matrices.
@@ -828,6 +853,7 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
     sld = cw + VPE;
     lppr = __builtin_ctz(cw / VPE);
     npieces = nu << lppr;
+    set_ptrs();
     load_into(preA, 0);
   }
 
@@ -835,31 +861,73 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
   T* M = sM + pl * ROWS * ROWS;
   const T* lag_tab = reinterpret_cast<const T*>(A.lagtab);
   {
+    // Lane r takes the pairs (rp, e) for e < rp and (R, e - rp) otherwise, e = h + 2 tt:
+    // every lane gets ROWS / 2 pairs of the lower triangle.
     const int h = (r >= ROWS / 2) ? 1 : 0;
     const int rp = r - h * (ROWS / 2);
     const int R = ROWS - 1 - rp;
-#pragma unroll 1
-    for (int tt = 0; tt < ROWS / 2; ++tt) {
+    auto pair_of = [&](int tt, int& row, int& col) __attribute__((always_inline)) {
       const int e = h + 2 * tt;
-      if (e < ROWS - 1) {
-        const int row = (e < rp) ? rp : R;
-        const int col = (e < rp) ? e : e - rp;
-        T val = T(0);
-        if (row < q) {
-          const double dx = sX[pl][row] - sX[pl][col];
-          const double dy = sY[pl][row] - sY[pl][col];
-          const double dt = sT[pl][row] - sT[pl][col];
-          if (lag_tab) {
-            // the operations of cov_eval, the lag-only factors from the table
-            const int lg = (int)fabs(dt);
-            val = gneiting_pair<T>(A.K, (T)dx, (T)dy, lag_tab[2 * lg], lag_tab[2 * lg + 1]);
-          } else {
-            val = cov_eval<T>(A.K, (T)dx, (T)dy, (T)dt);
-          }
-          val -= M[row * ROWS + col];
+      row = (e < rp) ? rp : R;
+      col = (e < rp) ? e : e - rp;
+      return e < ROWS - 1;
+    };
+    auto put = [&](int row, int col, T val) __attribute__((always_inline)) {
+      M[row * ROWS + col] = val;
+      M[col * ROWS + row] = val;
+    };
+    if (sizeof(T) == 4 && lag_tab) {
+      // The lag factors of PB pairs are loaded together, then their covariances
+      // formed with the operations of cov_eval (the lag-only factors from the table).
+      constexpr int PB = ROWS / 2 < 8 ? ROWS / 2 : 8;
+#pragma unroll 1
+      for (int t0 = 0; t0 < ROWS / 2; t0 += PB) {
+        T la[PB], le[PB];
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+          int row, col;
+          const bool on = pair_of(t0 + b, row, col) && row < q;
+          const int lg = on ? (int)fabs(sT[pl][row] - sT[pl][col]) : 0;
+          la[b] = lag_tab[2 * lg];
+          le[b] = lag_tab[2 * lg + 1];
         }
-        M[row * ROWS + col] = val;
-        M[col * ROWS + row] = val;
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+          int row, col;
+          if (pair_of(t0 + b, row, col)) {
+            T val = T(0);
+            if (row < q) {
+              const double dx = sX[pl][row] - sX[pl][col];
+              const double dy = sY[pl][row] - sY[pl][col];
+              val = gneiting_pair<T>(A.K, (T)dx, (T)dy, la[b], le[b]) - M[row * ROWS + col];
+            }
+            put(row, col, val);
+          }
+        }
+      }
+    } else {
+#pragma unroll 1
+      for (int tt = 0; tt < ROWS / 2; ++tt) {
+        const int e = h + 2 * tt;
+        if (e < ROWS - 1) {
+          const int row = (e < rp) ? rp : R;
+          const int col = (e < rp) ? e : e - rp;
+          T val = T(0);
+          if (row < q) {
+            const double dx = sX[pl][row] - sX[pl][col];
+            const double dy = sY[pl][row] - sY[pl][col];
+            const double dt = sT[pl][row] - sT[pl][col];
+            if (lag_tab) {
+              const int lg = (int)fabs(dt);
+              val = gneiting_pair<T>(A.K, (T)dx, (T)dy, lag_tab[2 * lg], lag_tab[2 * lg + 1]);
+            } else {
+              val = cov_eval<T>(A.K, (T)dx, (T)dy, (T)dt);
+            }
+            val -= M[row * ROWS + col];
+          }
+          M[row * ROWS + col] = val;
+          M[col * ROWS + row] = val;
+        }
       }
     }
     T dg = T(1);
@@ -898,6 +966,8 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
     int kmax = p;
 #pragma unroll
     for (int o = 32; o >= ROWS; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o));
+    // uniform across the wave: a scalar, so the sweep's step guard is a scalar branch
+    kmax = __builtin_amdgcn_readfirstlane(kmax);
     T xo = T(0);
     const bool ok = seg_gauss_jordan<ROWS, T>(a, yv, xo, r, p, kmax, sCol[pl]);
     const T d = __shfl(xo, sb + p);
@@ -943,6 +1013,10 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
     typedef UT piece_t __attribute__((ext_vector_type(VPE)));
     const int nq = cw / VPE;
     const int items = GP * nq;
+    // With fewer items than threads, an item's rows are split over 2^hs adjacent
+    // lanes of a quad, whose partial sums are then added across the quad.
+    const int hs = (ROWS >= 32 && 4 * items <= NTH) ? 2 : ((ROWS >= 16 && 2 * items <= NTH) ? 1 : 0);
+    const int rpl = ROWS >> hs;  // rows per lane, a multiple of 8
     {
       const int sl = sSlot[pl][r];
       sSlot[pl][r] = sl >= 0 ? sl * sld : 0;
@@ -954,14 +1028,16 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
     auto w_chunk = [&](int kc) __attribute__((always_inline)) {
 #pragma unroll
       for (int j = 0; j < JI; ++j) {
-        const int it = tid + j * NTH;
+        const int t2 = tid + j * NTH;
+        const int it = t2 >> hs;
         if (it < items) {
           const int pp = it / nq, cq = it - pp * nq;
+          const int sub = t2 & ((1 << hs) - 1);
+          const int rb = sub * rpl;
           piece_t acc = piece_t{};
           const UT* src = stage + cq * VPE;
           // eight terms at a time: their reads in flight together
-#pragma unroll
-          for (int r0 = 0; r0 < ROWS; r0 += 8) {
+          for (int r0 = rb; r0 < rb + rpl; r0 += 8) {
             piece_t v[8];
             UT bb[8];
 #pragma unroll
@@ -972,6 +1048,15 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
 #pragma unroll
             for (int e = 0; e < 8; ++e) acc += bb[e] * v[e];
           }
+          if (hs >= 1) {
+#pragma unroll
+            for (int e = 0; e < VPE; ++e) acc[e] += quad_xor<0xB1>(acc[e]);
+          }
+          if (hs >= 2) {
+#pragma unroll
+            for (int e = 0; e < VPE; ++e) acc[e] += quad_xor<0x4E>(acc[e]);
+          }
+          if (sub != 0) continue;
           if constexpr (SPLIT) {
             *reinterpret_cast<piece_t*>(wt + pp * wst + cq * VPE) = acc;
           } else {
