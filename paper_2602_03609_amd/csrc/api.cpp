@@ -431,9 +431,8 @@ int32_t run_u(const vif::LowRankArgs& a, int prec, char* ws, const Layout& L, hi
   return VIF_OK;
 }
 
-int32_t run_lowrank(const vif_points* p, const vif_points* ind, const vif_kernel* kern, int prec,
-                    char* ws, const Layout& L, hipStream_t s) {
-  const vif::LowRankArgs a = lowrank_args(p, ind, kern, L);
+// Sigma_k, its Cholesky factor and L_k^-1 (in L.P).
+int32_t run_sigma_k(const vif::LowRankArgs& a, char* ws, const Layout& L, hipStream_t s) {
   double* Sk = reinterpret_cast<double*>(ws + L.Sk);
   double* P = reinterpret_cast<double*>(ws + L.P);
   auto* fl = reinterpret_cast<unsigned long long*>(ws + L.flags);
@@ -442,7 +441,14 @@ int32_t run_lowrank(const vif_points* p, const vif_points* ind, const vif_kernel
   HIPCHK(vif::launch_cholesky(L.kpad, Sk, reinterpret_cast<double*>(ws + L.dscr), fl + 1, s));
   HIPCHK(vif::launch_trinv(L.kpad, Sk, P, reinterpret_cast<double*>(ws + L.dscr), s));
   PROF(VIF_STAGE_SIGMA_K, true);
-  return run_u(a, prec, ws, L, s);
+  return VIF_OK;
+}
+
+int32_t run_lowrank(const vif_points* p, const vif_points* ind, const vif_kernel* kern, int prec,
+                    char* ws, const Layout& L, hipStream_t s) {
+  const vif::LowRankArgs a = lowrank_args(p, ind, kern, L);
+  const int32_t st = run_sigma_k(a, ws, L, s);
+  return st ? st : run_u(a, prec, ws, L, s);
 }
 
 int32_t check_ind(const vif_points* ind, int* k) {
@@ -505,8 +511,13 @@ int32_t nll_impl(const vif_points* p, const double* y, const vif_kernel* kern, i
       HIPCHK(vif::launch_lag_table(to_dev(kern), nlag, prec, ws + L.lag, s));
       fa.lagtab = ws + L.lag;
     }
+    // The side work (the neighbor search) starts after the chain of small Sigma_k
+    // kernels, whose launches would otherwise wait for its workgroups, and runs
+    // beside U.
+    const vif::LowRankArgs la = lowrank_args(p, ind, kern, L);
+    if ((st = run_sigma_k(la, ws, L, s))) return st;
     if (side && (st = side->start(s))) return st;
-    if ((st = run_lowrank(p, ind, kern, prec, ws, L, s))) return st;
+    if ((st = run_u(la, prec, ws, L, s))) return st;
     if (side) HIPCHK(hipStreamWaitEvent(s, side->done, 0));
     fa.U = ws + L.U;
     fa.W = ws + L.W;

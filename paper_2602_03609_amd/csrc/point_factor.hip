@@ -47,6 +47,26 @@ __device__ __forceinline__ bf4v bf16_term(f4v& rem) {
   return hv;
 }
 
+// LDS byte address of a pointer into a __shared__ array.
+__device__ __forceinline__ unsigned lds_addr(const void* p) {
+  return (unsigned)(size_t)(const __attribute__((address_space(3))) void*)p;
+}
+// LDS reads and writes for the direct-load staging loops, written out so that the
+// compiler does not order them behind the direct loads in flight (which fill the
+// other buffer); each block waits for its own LDS operations before it ends.
+__device__ __forceinline__ void lds_read4(f4v& a, f4v& b, f4v& c, f4v& d, unsigned oa, unsigned ob,
+                                          unsigned oc, unsigned od) {
+  asm volatile(
+      "ds_read_b128 %0, %4\n\tds_read_b128 %1, %5\n\tds_read_b128 %2, %6\n\tds_read_b128 %3, %7\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(a), "=&v"(b), "=&v"(c), "=&v"(d)
+      : "v"(oa), "v"(ob), "v"(oc), "v"(od)
+      : "memory");
+}
+__device__ __forceinline__ void lds_write16(unsigned o, f4v v) {
+  asm volatile("ds_write_b128 %0, %1\n\ts_waitcnt lgkmcnt(0)" : : "v"(o), "v"(v) : "memory");
+}
+
 // v from the lane whose index differs in bit 0 (CTRL 0xB1) or bit 1 (CTRL 0x4E) of
 // the quad, as a DPP move (no LDS traffic).
 template <int CTRL>
@@ -325,8 +345,14 @@ struct GroupShape {
   static constexpr int NSLOT = GP * ROWS;        // conditioning rows (union upper bound)
 };
 
-template <int ROWS, bool WANT_B, int PREC>
-__global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 : 1)) void vif_group_kernel(FactorArgs A) {
+// DMA (BF16X3 NLL, 32 rows): both passes stage the union's FP32 rows with direct
+// global-to-LDS loads into two alternating buffers (chunks of 64 columns, 32 for
+// unions of more than 96 rows), the loads of the next chunk in flight while the
+// current one is used; the Gram pass splits its fragments into bfloat16 terms as
+// it reads them.
+template <int ROWS, bool WANT_B, int PREC, bool DMA = false>
+__global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (DMA ? 3 : (ROWS == 32 ? 2 : 1))) void vif_group_kernel(FactorArgs A) {
+  static_assert(!DMA || (ROWS == 32 && PREC == 2 && !WANT_B), "direct-load staging: BF16X3 NLL, 32 rows");
   using Sh = GroupShape<ROWS, PREC>;
   using T = typename PrecT<PREC>::T;
   using UT = typename PrecT<PREC>::UT;
@@ -349,8 +375,18 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
   constexpr int ZROW = 4 * KC;
   constexpr size_t SPL_B = SPLIT ? ((size_t)NSLOT * NSP * (KC + BPAD) + ZROW) * 2 : 0;
   constexpr size_t B1 = STAGE_B + SEL_B > MAT_B ? STAGE_B + SEL_B : MAT_B;
-  constexpr size_t BIG_B = SPL_B > B1 ? SPL_B : B1;
-  __shared__ __attribute__((aligned(16))) unsigned char sBig[BIG_B];
+  // Direct-load staging: a 32 KB area (the union bitmap, then the chunk buffers, the
+  // per-point matrices between the passes) holding two 16 KB buffers, or one of
+  // 32 KB for the largest unions, then a zero segment read for empty slots; two W
+  // result tiles (GP rows of 64 + 4 floats). About 52 KB in all: three workgroups
+  // share a CU.
+  constexpr int PBUF0 = 32 * 1024, PBUF1 = 16 * 1024;
+  constexpr int PTILE = GP * (64 + 4) * 4;
+  static_assert(!DMA || (size_t)PBUF0 >= MAT_B, "direct-load layout");
+  constexpr size_t BIG_B = DMA ? (size_t)PBUF0 + 256 : (SPL_B > B1 ? SPL_B : B1);
+  __shared__ __attribute__((aligned(16))) unsigned char sBig[DMA ? 16 : BIG_B];
+  __shared__ __attribute__((aligned(16))) unsigned char sB0[DMA ? BIG_B : 16];
+  __shared__ __attribute__((aligned(16))) unsigned char sTile[DMA ? 2 * PTILE : 16];
   __shared__ int sIdx[GP][ROWS];
   __shared__ int sSlot[GP][ROWS];
   __shared__ int sSort[NSLOT];
@@ -362,8 +398,9 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
   __shared__ T sBv[GP][ROWS];
   __shared__ T sZ[GP];
   __shared__ int64_t sI[GP];
-  UT* stage = reinterpret_cast<UT*>(sBig);
-  T* sM = reinterpret_cast<T*>(sBig);
+  unsigned char* const sArea = DMA ? sB0 : sBig;  // the shared area (BIG_B bytes)
+  UT* stage = reinterpret_cast<UT*>(sArea);
+  T* sM = reinterpret_cast<T*>(sArea);
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
@@ -459,8 +496,8 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
   const int ulo = sLoHi[0], uhi = sLoHi[1];
   const bool use_bm = uhi < ulo || uhi - ulo < BMW * 32;
   if (use_bm) {
-    unsigned* bm = reinterpret_cast<unsigned*>(sBig);
-    int* pre = reinterpret_cast<int*>(sBig) + BMW;
+    unsigned* bm = reinterpret_cast<unsigned*>(sArea);
+    int* pre = reinterpret_cast<int*>(sArea) + BMW;
     for (int w = tid; w < BMW; w += NTH) bm[w] = 0u;
     __syncthreads();
     if (srow >= 0) {
@@ -583,7 +620,7 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
   int sld = SPLIT ? cw + BPAD : cw + VPE;  // row stride (bf16 per plane, or UT)
   int lppr = __builtin_ctz(cw / VPE);  // log2 of the 16-byte pieces per row and chunk
   int npieces = nu << lppr;
-  __bf16* splane = reinterpret_cast<__bf16*>(sBig);
+  __bf16* splane = reinterpret_cast<__bf16*>(sArea);
   // Two register sets of staged pieces: the loads of a chunk are issued two chunk
   // periods before its data go to LDS.
   f4v preA[MAXP], preB[MAXP];
@@ -649,6 +686,51 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
     store_from(preB);
     __syncthreads();
     compute(kc + cw);
+    __syncthreads();
+  };
+
+  // Direct-load geometry: a chunk is pcw columns of every union row, one segment of
+  // 4 pcw bytes per row, its 16-byte units XOR-swizzled by the slot (2^lpu units).
+  // A direct load moves 1 KB (64 lanes x 16 bytes) to consecutive LDS; pinst loads
+  // fill a chunk, taken by the wavefronts in turn.
+  [[maybe_unused]] int pcw = 64, lpu = 4, pinst = 0, pnbuf = 2;
+  [[maybe_unused]] const char* gp[8];
+  [[maybe_unused]] const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  if constexpr (DMA) {
+    pcw = nu <= 64 ? 64 : 32;
+    lpu = nu <= 64 ? 4 : 3;
+    pinst = (nu + (64 >> lpu) - 1) >> (6 - lpu);
+    pnbuf = pinst * 1024 <= PBUF1 ? 2 : 1;  // a single buffer (the whole area) holds 32 loads
+  }
+  // Each lane's source for its share of every load of a chunk, at column 0.
+  [[maybe_unused]] auto dma_ptrs = [&]() __attribute__((always_inline)) {
+    const int pu16 = 1 << lpu;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int inst = wave_u + i * NW;
+      const int sg = min((inst << (6 - lpu)) + (lane >> lpu), nu - 1);
+      const int u = (lane & (pu16 - 1)) ^ (sg & (pu16 - 1));
+      gp[i] = reinterpret_cast<const char*>(U + (int64_t)sUniq[sg] * A.ldu + u * 4);
+    }
+  };
+  // Loads of the chunk at column kc into buffer b (completion: vmcnt).
+  [[maybe_unused]] auto dma_issue = [&](int kc, int b) __attribute__((always_inline)) {
+    const int64_t koff = (int64_t)kc * 4;
+    auto into = [&](unsigned char* base) __attribute__((always_inline)) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int inst = wave_u + i * NW;
+        if (inst < pinst)
+          __builtin_amdgcn_global_load_lds(gp[i] + koff,
+                                           (__attribute__((address_space(3))) void*)(base + inst * 1024),
+                                           16, 0, 0);
+      }
+    };
+    into(sB0 + b * PBUF1);
+  };
+  // Start of a chunk: this wave's loads are in LDS, then every wave's.
+  [[maybe_unused]] auto dma_wait = [&]() __attribute__((always_inline)) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     __syncthreads();
   };
 
@@ -801,7 +883,7 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
           ++t;
         }
     };
-    auto gram_chunk_split = [&](int) __attribute__((always_inline)) {
+    [[maybe_unused]] auto gram_chunk_split = [&](int) __attribute__((always_inline)) {
       bf8v buf[2][NT][NSP];
       ld(buf[0], fo[0], 0);
       for (int sub = 0; sub < cw; sub += KC) {
@@ -816,8 +898,88 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
         }
       }
     };
-    set_ptrs();
-    run_pass(gram_chunk_split, false);
+    if constexpr (DMA) {
+      // Fragment addresses: lane (rr16, kq) of tile ti reads the two 16-byte units
+      // 2 kq and 2 kq + 1 (columns 8 kq .. 8 kq + 7 of a 32-column step) of its
+      // slot's segment, at (unit ^ (slot mod 2^lpu)); the second step of a
+      // 64-column chunk flips bit 7 of the offset. Empty slots read zeros.
+      if (tid < 16) reinterpret_cast<f4v*>(sB0 + PBUF0)[tid] = f4v{0.f, 0.f, 0.f, 0.f};
+      const int pu16 = 1 << lpu;
+      int fr[PPW][NT][2];  // byte offsets within a buffer; -1: empty slot
+#pragma unroll
+      for (int s2 = 0; s2 < PPW; ++s2)
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti) {
+          const int sl = sSlot[wave * PPW + s2][ti * 16 + rr16];
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            fr[s2][ti][h] = sl >= 0 ? sl * 4 * pcw + (((2 * kq + h) ^ (sl & (pu16 - 1))) << 4) : -1;
+        }
+      const unsigned ab0 = lds_addr(sB0), ab1 = ab0 + PBUF1, abz = ab0 + PBUF0;
+      // the bfloat16 terms of one pair's fragments, read from buffer base ab
+      auto frag = [&](bf8v (&pt)[NT][NSP], int s2, int sub, unsigned ab, unsigned az)
+                      __attribute__((always_inline)) {
+        const int sx = sub ? 128 : 0;
+        unsigned ad[NT][2];
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            ad[ti][h] = fr[s2][ti][h] >= 0 ? ab + (unsigned)(fr[s2][ti][h] ^ sx) : az + 16 * h;
+        f4v x[NT][2];
+        lds_read4(x[0][0], x[0][1], x[1][0], x[1][1], ad[0][0], ad[0][1], ad[1][0], ad[1][1]);
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti) {
+          const bf4v h0 = bf16_term(x[ti][0]), h1 = bf16_term(x[ti][1]);
+          bf4v l0, l1;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            l0[c] = (__bf16)x[ti][0][c];
+            l1[c] = (__bf16)x[ti][1][c];
+          }
+          pt[ti][0] = __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7);
+          pt[ti][1] = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);
+        }
+      };
+      // One chunk of NSUB 32-column steps: each pair's products are issued before
+      // the next pair's fragments are read.
+      auto gram_dma = [&](auto nsub_c, unsigned ab, unsigned az) __attribute__((always_inline)) {
+        constexpr int NSUB = decltype(nsub_c)::value;
+        constexpr int NP = NSUB * PPW;
+        bf8v pt[2][NT][NSP];
+        frag(pt[0], 0, 0, ab, az);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          mm(pt[q & 1], acc[q % PPW]);
+          __builtin_amdgcn_sched_barrier(0);
+          if (q + 1 < NP) frag(pt[(q + 1) & 1], (q + 1) % PPW, (q + 1) / PPW, ab, az);
+        }
+      };
+      auto gram_chunk = [&](int b) __attribute__((always_inline)) {
+        const unsigned ab = b ? ab1 : ab0, az = abz;
+        if (pcw == 64)
+          gram_dma(std::integral_constant<int, 2>{}, ab, az);
+        else
+          gram_dma(std::integral_constant<int, 1>{}, ab, az);
+      };
+      dma_ptrs();
+      dma_issue(0, 0);
+      const int nc = A.ldu / pcw;
+      for (int c = 0; c < nc; ++c) {
+        const int b = pnbuf == 2 ? (c & 1) : 0;
+        dma_wait();
+        if (pnbuf == 2 && c + 1 < nc) dma_issue((c + 1) * pcw, b ^ 1);
+        gram_chunk(b);
+        if (pnbuf == 1) {
+          __syncthreads();
+          if (c + 1 < nc) dma_issue((c + 1) * pcw, 0);
+        }
+      }
+      __syncthreads();
+    } else {
+      set_ptrs();
+      run_pass(gram_chunk_split, false);
+    }
   } else {
     set_ptrs();
     run_pass(gram_chunk, false);
@@ -845,8 +1007,8 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
 
   // W-pass geometry (FP32 staging after the result tile of the split modes) and
   // the loads of its first chunk, in flight during the per-point phase.
-  UT* wt = reinterpret_cast<UT*>(sBig);
-  if constexpr (!WANT_B) {
+  UT* wt = reinterpret_cast<UT*>(sArea);
+  if constexpr (!WANT_B && !DMA) {
     split_stage = false;
     stage = wt + ((GP * (4 * KC + VPE) + VPE - 1) / VPE) * VPE;
     cw = pick_width(CAPB - (int)(stage - wt), nu);
@@ -938,6 +1100,14 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
   T a[ROWS];
 #pragma unroll
   for (int j = 0; j < ROWS; ++j) a[j] = M[j * ROWS + r];
+  if constexpr (DMA) {
+    // Once every wave holds its blocks in registers, the first W chunk's loads go to
+    // buffer 1 during the per-point phase; a chunk too large for it waits for the
+    // whole area after that phase.
+    __syncthreads();
+    dma_ptrs();
+    if (pnbuf == 2) dma_issue(0, 1);
+  }
   // x_r = (G_NN^-1 G_Ni)_r (r < p), L_pp = sqrt(D_i), z_i = (y_i - x' y_N) / L_pp.
   T x = T(0), Lpp_b, zi;
   if constexpr (PREC == 0) {
@@ -1004,6 +1174,89 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (ROWS == 32 ? 2 
     __syncthreads();
 
     // ---- W rows: W_i = sum_r b_r U_{S_r}, gathered from the staged union rows ----
+    if constexpr (DMA) {
+      // An item is one point and one 16-byte piece of a chunk, its rows split over
+      // 2^hs adjacent lanes (partial sums added across the quad). Each lane keeps its
+      // rows' addresses within a buffer and their b_r in registers for the pass. The
+      // items' results go to a tile, written out as W terms at the start of the next
+      // chunk, before that chunk's loads are issued (two tiles alternate).
+      const int nqp = pcw / 4;
+      const int items = GP * nqp;  // 128 or 64: 2^hs lanes each fill the workgroup
+      const int hs = 4 * items <= NTH ? 2 : 1;
+      const int rpl = ROWS >> hs;  // 16 or 8
+      const int it = tid >> hs;
+      const int pp = it / nqp, cq = it - pp * nqp;
+      const int part = tid & ((1 << hs) - 1);
+      const int pu16 = 1 << lpu;
+      float wb[16];
+      unsigned wo[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int rr = part * rpl + e;
+        const int sl = (it < items && e < rpl) ? sSlot[pp][rr] : -1;
+        wb[e] = sl >= 0 ? (float)sBv[pp][rr] : 0.f;
+        wo[e] = sl >= 0 ? (unsigned)(sl * 4 * pcw + ((cq ^ (sl & (pu16 - 1))) << 4)) : 0u;
+      }
+      const int wst = pcw + 4;
+      const float* tiles = reinterpret_cast<const float*>(sTile);
+      const unsigned at0 = lds_addr(sTile) + (unsigned)((pp * wst + cq * 4) * 4);
+      const unsigned ab0 = lds_addr(sB0), ab1 = ab0 + PBUF1;
+      __bf16* Wp = reinterpret_cast<__bf16*>(A.W);
+      // Rows 4h .. 4h + 3 of one column from a tile: one 8-byte piece per term plane
+      // in the 8-row blocks of the W planes (rows in processing order).
+      auto planes = [&](int kc, int t) __attribute__((always_inline)) {
+        const float* wt = tiles + t * (PTILE / 4);
+        for (int e = tid; e < pcw * (GP / 4); e += NTH) {
+          const int col = e & (pcw - 1), h = e >> (lpu + 2);
+          const int64_t row0 = g * GP + 4 * h;
+          f4v v;
+#pragma unroll
+          for (int q4 = 0; q4 < 4; ++q4)
+            v[q4] = (kc + col == A.k) ? (float)sZ[4 * h + q4] : wt[(4 * h + q4) * wst + col];
+#pragma unroll
+          for (int sp = 0; sp < NSP; ++sp)
+            *reinterpret_cast<bf4v*>(
+                Wp + ((sp * A.wrb + (row0 >> 3)) * A.ldu + kc + col) * 8 + (row0 & 7)) = bf16_term(v);
+        }
+      };
+      auto gather = [&](unsigned ab, int t) __attribute__((always_inline)) {
+        if (it < items) {
+          f4v acc = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int r0 = 0; r0 < 16; r0 += 4) {
+            if (r0 < rpl) {
+              f4v v[4];
+              lds_read4(v[0], v[1], v[2], v[3], ab + wo[r0], ab + wo[r0 + 1], ab + wo[r0 + 2], ab + wo[r0 + 3]);
+#pragma unroll
+              for (int e = 0; e < 4; ++e) acc += wb[r0 + e] * v[e];
+            }
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[e] += quad_xor<0xB1>(acc[e]);
+          if (hs >= 2) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] += quad_xor<0x4E>(acc[e]);
+          }
+          if (part == 0) lds_write16(at0 + (unsigned)(t * PTILE), acc);
+        }
+      };
+      const int nc = A.ldu / pcw;  // chunk c in buffer (c + 1) mod 2, or all in buffer 0
+      if (pnbuf == 1) dma_issue(0, 0);
+      for (int c = 0; c < nc; ++c) {
+        const int b = pnbuf == 2 ? ((c + 1) & 1) : 0;
+        dma_wait();
+        if (c > 0) planes((c - 1) * pcw, (c - 1) & 1);
+        if (pnbuf == 2 && c + 1 < nc) dma_issue((c + 1) * pcw, b ^ 1);
+        gather(b ? ab1 : ab0, c & 1);
+        if (pnbuf == 1) {
+          __syncthreads();
+          if (c + 1 < nc) dma_issue((c + 1) * pcw, 0);
+        }
+      }
+      __syncthreads();
+      planes((nc - 1) * pcw, (nc - 1) & 1);
+      return;
+    }
     // An item is one point and one 16-byte piece of the staged chunk; each term is
     // one LDS read of a staged piece and VPE fused multiply-adds in the precision
     // of U (no products with the zeros of a dense selection matrix). The term's
@@ -1099,6 +1352,12 @@ hipError_t launch_group(const FactorArgs& a, int mode, hipStream_t s) {
   const int64_t ngrp =
       (PREC >= 2 && mode != 1) ? a.wrb * 8 / Sh::GP : (a.n + Sh::GP - 1) / Sh::GP;
   const unsigned grid = (unsigned)(((ngrp + 7) / 8) * 8);
+  if constexpr (ROWS == 32 && PREC == 2) {
+    if (mode != 1) {
+      hipLaunchKernelGGL((vif_group_kernel<32, false, 2, true>), dim3(grid), dim3(64 * Sh::NW), 0, s, a);
+      return hipGetLastError();
+    }
+  }
   if (mode == 1)
     hipLaunchKernelGGL((vif_group_kernel<ROWS, true, PREC>), dim3(grid), dim3(64 * Sh::NW), 0, s,
                        a);
