@@ -402,12 +402,15 @@ def kernel_name(stage, prec, m):
     c = PREC_CODE[prec]
     rows = 16 if m + 1 <= 16 else (32 if m + 1 <= 32 else 64)
     if stage == "point_factor":
-        return f"vif_group_kernel<{rows}, false, {c}>"
+        # BF16X3 at 32 rows stages its rows by direct loads (the fourth argument)
+        return f"vif_group_kernel<{rows}, false, {c}{', true' if (c == 2 and rows == 32) else ''}>"
     if stage == "syrk":
+        if c == 2:
+            return "syrk_split256_kernel"
         return f"syrk_split_kernel<{3 if c == 3 else 2}>" if c >= 2 else f"syrk_kernel<{c}>"
     if stage == "trmm":
         if c >= 2:
-            return "lowrank_u_kernel<3, 8>" if c == 3 else "lowrank_u_kernel<2, 4>"
+            return "lowrank_u_kernel<3, 8, 2, 4>" if c == 3 else "lowrank_u_kernel<2, 8, 4, 2>"
         return "trmm_f64_kernel" if c == 0 else "trmm_f32_kernel<false>"
     if stage == "crosscov":
         return f"crosscov_kernel<{'double' if c == 0 else 'float'}>"
