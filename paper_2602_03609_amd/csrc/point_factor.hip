@@ -347,7 +347,7 @@ struct GroupShape {
 
 // DMA (BF16X3 NLL, 32 rows): both passes stage the union's FP32 rows with direct
 // global-to-LDS loads into two alternating buffers (chunks of 64 columns, 32 for
-// unions of more than 96 rows), the loads of the next chunk in flight while the
+// unions of more than 64 rows), the loads of the next chunk in flight while the
 // current one is used; the Gram pass splits its fragments into bfloat16 terms as
 // it reads them.
 template <int ROWS, bool WANT_B, int PREC, bool DMA = false>
