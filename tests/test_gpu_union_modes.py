@@ -69,3 +69,26 @@ def test_nll_with_extreme_unions(mode, prec):
     err = rel(nll, o["nll"])
     log(f"[union] {mode} {prec} n={d['n']} gpu={nll:.12g} oracle={o['nll']:.12g} rel={err:.3e}")
     assert err <= NLL_TOL[prec]
+
+
+@functools.lru_cache(maxsize=None)
+def _case_m(m, mode):
+    d = synth.config_small(seed=9, n_times=6, k=60, m=m, kind=1, n_stations=200)
+    nb = _rows(d["n"], d["m"], mode, seed=13)
+    o = LK.vif(d["kern"], (d["sx"], d["sy"], d["t"]), d["y"], nb, (d["zx"], d["zy"], d["zt"]))
+    return d, nb, o
+
+
+@pytest.mark.parametrize("m", [16, 31])
+@pytest.mark.parametrize("mode", ["shared", "random"])
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_nll_at_the_row_bounds(m, mode, prec):
+    """m = 16 and m = 31: the smallest and largest neighbor counts of the 32-row blocks."""
+    vif = lib()
+    torch = torch_cuda()
+    d, nb, o = _case_m(m, mode)
+    Xd, yd, Zd = problem_on_device(d)
+    nll = vif.vif_nll(*Xd, yd, d["kern"], d["m"], dev(nb, torch.int32), ind=Zd, prec=prec)
+    err = rel(nll, o["nll"])
+    log(f"[union] m={m} {mode} {prec} n={d['n']} gpu={nll:.12g} oracle={o['nll']:.12g} rel={err:.3e}")
+    assert err <= NLL_TOL[prec]
