@@ -352,7 +352,8 @@ struct GroupShape {
 // it reads them.
 template <int ROWS, bool WANT_B, int PREC, bool DMA = false>
 __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (DMA ? 3 : (ROWS == 32 ? 2 : 1))) void vif_group_kernel(FactorArgs A) {
-  static_assert(!DMA || (ROWS == 32 && PREC == 2 && !WANT_B), "direct-load staging: BF16X3 NLL, 32 rows");
+  static_assert(!DMA || (ROWS == 32 && (PREC == 1 || PREC == 2) && !WANT_B),
+                "direct-load staging: FP32 and BF16X3 NLL, 32 rows");
   using Sh = GroupShape<ROWS, PREC>;
   using T = typename PrecT<PREC>::T;
   using UT = typename PrecT<PREC>::UT;
@@ -841,7 +842,118 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (DMA ? 3 : (ROWS
     }
     }
   };
-  if constexpr (SPLIT && PPW > 1 && NSP == 2) {
+  if constexpr (DMA) {
+    // Fragment addresses: lane (rr16, kq) of tile ti reads the two 16-byte units
+    // 2 kq and 2 kq + 1 (columns 8 kq .. 8 kq + 7 of a 32-column step) of its
+    // slot's segment, at (unit ^ (slot mod 2^lpu)); the second step of a
+    // 64-column chunk flips bit 7 of the offset. Empty slots read zeros.
+    if (tid < 16) reinterpret_cast<f4v*>(sB0 + PBUF0)[tid] = f4v{0.f, 0.f, 0.f, 0.f};
+    const int pu16 = 1 << lpu;
+    int fr[PPW][NT][2];  // byte offsets within a buffer; -1: empty slot
+#pragma unroll
+    for (int s2 = 0; s2 < PPW; ++s2)
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti) {
+        const int sl = sSlot[wave * PPW + s2][ti * 16 + rr16];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          fr[s2][ti][h] = sl >= 0 ? sl * 4 * pcw + (((2 * kq + h) ^ (sl & (pu16 - 1))) << 4) : -1;
+      }
+    const unsigned ab0 = lds_addr(sB0), ab1 = ab0 + PBUF1, abz = ab0 + PBUF0;
+    // one pair's fragments (eight FP32 values per tile and lane), from buffer base ab
+    auto frag = [&](f4v (&x)[NT][2], int s2, int sub, unsigned ab, unsigned az)
+                    __attribute__((always_inline)) {
+      const int sx = sub ? 128 : 0;
+      unsigned ad[NT][2];
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          ad[ti][h] = fr[s2][ti][h] >= 0 ? ab + (unsigned)(fr[s2][ti][h] ^ sx) : az + 16 * h;
+      lds_read4(x[0][0], x[0][1], x[1][0], x[1][1], ad[0][0], ad[0][1], ad[1][0], ad[1][1]);
+    };
+    // One pair's products. BF16X3: the fragments split into their two bfloat16
+    // terms, three products per tile and the low-by-low product on the diagonal
+    // tiles (as in the register-staged pass). FP32: eight K = 4 products per tile,
+    // lane group kq holding columns 8 kq .. 8 kq + 7.
+    auto pairmm = [&](f4v (&x)[NT][2], AccT (&ac)[NTT]) __attribute__((always_inline)) {
+      if constexpr (PREC == 2) {
+        bf8v pt[NT][2];
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti) {
+          const bf4v h0 = bf16_term(x[ti][0]), h1 = bf16_term(x[ti][1]);
+          bf4v l0, l1;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            l0[c] = (__bf16)x[ti][0][c];
+            l1[c] = (__bf16)x[ti][1][c];
+          }
+          pt[ti][0] = __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7);
+          pt[ti][1] = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);
+        }
+        int t = 0;
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+          for (int tj = 0; tj <= ti; ++tj) {
+            if (ti == tj)
+              ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pt[ti][1], pt[tj][1], ac[t], 0, 0, 0);
+            ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pt[ti][1], pt[tj][0], ac[t], 0, 0, 0);
+            ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pt[ti][0], pt[tj][1], ac[t], 0, 0, 0);
+            ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pt[ti][0], pt[tj][0], ac[t], 0, 0, 0);
+            ++t;
+          }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          int t = 0;
+#pragma unroll
+          for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+            for (int tj = 0; tj <= ti; ++tj) {
+              ac[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[ti][c >> 2][c & 3], x[tj][c >> 2][c & 3],
+                                                           ac[t], 0, 0, 0);
+              ++t;
+            }
+        }
+      }
+    };
+    // One chunk of NSUB 32-column steps: each pair's products are issued before
+    // the next pair's fragments are read.
+    auto gram_dma = [&](auto nsub_c, unsigned ab, unsigned az) __attribute__((always_inline)) {
+      constexpr int NSUB = decltype(nsub_c)::value;
+      constexpr int NP = NSUB * PPW;
+      f4v xs[2][NT][2];
+      frag(xs[0], 0, 0, ab, az);
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        pairmm(xs[q & 1], acc[q % PPW]);
+        __builtin_amdgcn_sched_barrier(0);
+        if (q + 1 < NP) frag(xs[(q + 1) & 1], (q + 1) % PPW, (q + 1) / PPW, ab, az);
+      }
+    };
+    auto gram_chunk = [&](int b) __attribute__((always_inline)) {
+      const unsigned ab = b ? ab1 : ab0, az = abz;
+      if (pcw == 64)
+        gram_dma(std::integral_constant<int, 2>{}, ab, az);
+      else
+        gram_dma(std::integral_constant<int, 1>{}, ab, az);
+    };
+    dma_ptrs();
+    dma_issue(0, 0);
+    const int nc = A.ldu / pcw;
+    for (int c = 0; c < nc; ++c) {
+      const int b = pnbuf == 2 ? (c & 1) : 0;
+      dma_wait();
+      if (pnbuf == 2 && c + 1 < nc) dma_issue((c + 1) * pcw, b ^ 1);
+      gram_chunk(b);
+      if (pnbuf == 1) {
+        __syncthreads();
+        if (c + 1 < nc) dma_issue((c + 1) * pcw, 0);
+      }
+    }
+    __syncthreads();
+  } else if constexpr (SPLIT && PPW > 1 && NSP == 2) {
     // BF16X3 with two or more points per wave: each (sub-step, point) pair's
     // fragments load while the previous pair's products run, from offsets fixed
     // for the pass; empty slots read the zero block (no masked loads).
@@ -898,88 +1010,8 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (DMA ? 3 : (ROWS
         }
       }
     };
-    if constexpr (DMA) {
-      // Fragment addresses: lane (rr16, kq) of tile ti reads the two 16-byte units
-      // 2 kq and 2 kq + 1 (columns 8 kq .. 8 kq + 7 of a 32-column step) of its
-      // slot's segment, at (unit ^ (slot mod 2^lpu)); the second step of a
-      // 64-column chunk flips bit 7 of the offset. Empty slots read zeros.
-      if (tid < 16) reinterpret_cast<f4v*>(sB0 + PBUF0)[tid] = f4v{0.f, 0.f, 0.f, 0.f};
-      const int pu16 = 1 << lpu;
-      int fr[PPW][NT][2];  // byte offsets within a buffer; -1: empty slot
-#pragma unroll
-      for (int s2 = 0; s2 < PPW; ++s2)
-#pragma unroll
-        for (int ti = 0; ti < NT; ++ti) {
-          const int sl = sSlot[wave * PPW + s2][ti * 16 + rr16];
-#pragma unroll
-          for (int h = 0; h < 2; ++h)
-            fr[s2][ti][h] = sl >= 0 ? sl * 4 * pcw + (((2 * kq + h) ^ (sl & (pu16 - 1))) << 4) : -1;
-        }
-      const unsigned ab0 = lds_addr(sB0), ab1 = ab0 + PBUF1, abz = ab0 + PBUF0;
-      // the bfloat16 terms of one pair's fragments, read from buffer base ab
-      auto frag = [&](bf8v (&pt)[NT][NSP], int s2, int sub, unsigned ab, unsigned az)
-                      __attribute__((always_inline)) {
-        const int sx = sub ? 128 : 0;
-        unsigned ad[NT][2];
-#pragma unroll
-        for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-          for (int h = 0; h < 2; ++h)
-            ad[ti][h] = fr[s2][ti][h] >= 0 ? ab + (unsigned)(fr[s2][ti][h] ^ sx) : az + 16 * h;
-        f4v x[NT][2];
-        lds_read4(x[0][0], x[0][1], x[1][0], x[1][1], ad[0][0], ad[0][1], ad[1][0], ad[1][1]);
-#pragma unroll
-        for (int ti = 0; ti < NT; ++ti) {
-          const bf4v h0 = bf16_term(x[ti][0]), h1 = bf16_term(x[ti][1]);
-          bf4v l0, l1;
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            l0[c] = (__bf16)x[ti][0][c];
-            l1[c] = (__bf16)x[ti][1][c];
-          }
-          pt[ti][0] = __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7);
-          pt[ti][1] = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);
-        }
-      };
-      // One chunk of NSUB 32-column steps: each pair's products are issued before
-      // the next pair's fragments are read.
-      auto gram_dma = [&](auto nsub_c, unsigned ab, unsigned az) __attribute__((always_inline)) {
-        constexpr int NSUB = decltype(nsub_c)::value;
-        constexpr int NP = NSUB * PPW;
-        bf8v pt[2][NT][NSP];
-        frag(pt[0], 0, 0, ab, az);
-#pragma unroll
-        for (int q = 0; q < NP; ++q) {
-          mm(pt[q & 1], acc[q % PPW]);
-          __builtin_amdgcn_sched_barrier(0);
-          if (q + 1 < NP) frag(pt[(q + 1) & 1], (q + 1) % PPW, (q + 1) / PPW, ab, az);
-        }
-      };
-      auto gram_chunk = [&](int b) __attribute__((always_inline)) {
-        const unsigned ab = b ? ab1 : ab0, az = abz;
-        if (pcw == 64)
-          gram_dma(std::integral_constant<int, 2>{}, ab, az);
-        else
-          gram_dma(std::integral_constant<int, 1>{}, ab, az);
-      };
-      dma_ptrs();
-      dma_issue(0, 0);
-      const int nc = A.ldu / pcw;
-      for (int c = 0; c < nc; ++c) {
-        const int b = pnbuf == 2 ? (c & 1) : 0;
-        dma_wait();
-        if (pnbuf == 2 && c + 1 < nc) dma_issue((c + 1) * pcw, b ^ 1);
-        gram_chunk(b);
-        if (pnbuf == 1) {
-          __syncthreads();
-          if (c + 1 < nc) dma_issue((c + 1) * pcw, 0);
-        }
-      }
-      __syncthreads();
-    } else {
-      set_ptrs();
-      run_pass(gram_chunk_split, false);
-    }
+    set_ptrs();
+    run_pass(gram_chunk_split, false);
   } else {
     set_ptrs();
     run_pass(gram_chunk, false);
@@ -1200,6 +1232,10 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (DMA ? 3 : (ROWS
       const int wst = pcw + 4;
       const float* tiles = reinterpret_cast<const float*>(sTile);
       const unsigned at0 = lds_addr(sTile) + (unsigned)((pp * wst + cq * 4) * 4);
+      // FP32: rows go to W directly (by point index), column k receiving z_i
+      [[maybe_unused]] const int64_t ipw = sI[pp];
+      [[maybe_unused]] const float zvw = (float)sZ[pp];
+      [[maybe_unused]] float* Wf = reinterpret_cast<float*>(A.W);
       const unsigned ab0 = lds_addr(sB0), ab1 = ab0 + PBUF1;
       __bf16* Wp = reinterpret_cast<__bf16*>(A.W);
       // Rows 4h .. 4h + 3 of one column from a tile: one 8-byte piece per term plane
@@ -1219,7 +1255,7 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (DMA ? 3 : (ROWS
                 Wp + ((sp * A.wrb + (row0 >> 3)) * A.ldu + kc + col) * 8 + (row0 & 7)) = bf16_term(v);
         }
       };
-      auto gather = [&](unsigned ab, int t) __attribute__((always_inline)) {
+      auto gather = [&](unsigned ab, int t, int kc) __attribute__((always_inline)) {
         if (it < items) {
           f4v acc = f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -1237,7 +1273,16 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (DMA ? 3 : (ROWS
 #pragma unroll
             for (int e = 0; e < 4; ++e) acc[e] += quad_xor<0x4E>(acc[e]);
           }
-          if (part == 0) lds_write16(at0 + (unsigned)(t * PTILE), acc);
+          if (part == 0) {
+            if constexpr (SPLIT) {
+              lds_write16(at0 + (unsigned)(t * PTILE), acc);
+            } else if (ipw >= 0) {
+#pragma unroll
+              for (int e = 0; e < 4; ++e)
+                if (kc + cq * 4 + e == A.k) acc[e] = zvw;
+              *reinterpret_cast<f4v*>(Wf + ipw * A.ldu + kc + cq * 4) = acc;
+            }
+          }
         }
       };
       const int nc = A.ldu / pcw;  // chunk c in buffer (c + 1) mod 2, or all in buffer 0
@@ -1245,16 +1290,20 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (DMA ? 3 : (ROWS
       for (int c = 0; c < nc; ++c) {
         const int b = pnbuf == 2 ? ((c + 1) & 1) : 0;
         dma_wait();
-        if (c > 0) planes((c - 1) * pcw, (c - 1) & 1);
+        if constexpr (SPLIT) {
+          if (c > 0) planes((c - 1) * pcw, (c - 1) & 1);
+        }
         if (pnbuf == 2 && c + 1 < nc) dma_issue((c + 1) * pcw, b ^ 1);
-        gather(b ? ab1 : ab0, c & 1);
+        gather(b ? ab1 : ab0, c & 1, c * pcw);
         if (pnbuf == 1) {
           __syncthreads();
           if (c + 1 < nc) dma_issue((c + 1) * pcw, 0);
         }
       }
-      __syncthreads();
-      planes((nc - 1) * pcw, (nc - 1) & 1);
+      if constexpr (SPLIT) {
+        __syncthreads();
+        planes((nc - 1) * pcw, (nc - 1) & 1);
+      }
       return;
     }
     // An item is one point and one 16-byte piece of the staged chunk; each term is
@@ -1352,9 +1401,9 @@ hipError_t launch_group(const FactorArgs& a, int mode, hipStream_t s) {
   const int64_t ngrp =
       (PREC >= 2 && mode != 1) ? a.wrb * 8 / Sh::GP : (a.n + Sh::GP - 1) / Sh::GP;
   const unsigned grid = (unsigned)(((ngrp + 7) / 8) * 8);
-  if constexpr (ROWS == 32 && PREC == 2) {
+  if constexpr (ROWS == 32 && (PREC == 1 || PREC == 2)) {
     if (mode != 1) {
-      hipLaunchKernelGGL((vif_group_kernel<32, false, 2, true>), dim3(grid), dim3(64 * Sh::NW), 0, s, a);
+      hipLaunchKernelGGL((vif_group_kernel<32, false, PREC, true>), dim3(grid), dim3(64 * Sh::NW), 0, s, a);
       return hipGetLastError();
     }
   }
