@@ -352,8 +352,8 @@ struct GroupShape {
 // it reads them.
 template <int ROWS, bool WANT_B, int PREC, bool DMA = false>
 __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (DMA ? 3 : (ROWS == 32 ? 2 : 1))) void vif_group_kernel(FactorArgs A) {
-  static_assert(!DMA || (ROWS == 32 && (PREC == 1 || PREC == 2) && !WANT_B),
-                "direct-load staging: FP32 and BF16X3 NLL, 32 rows");
+  static_assert(!DMA || (ROWS == 32 && PREC >= 1 && !WANT_B),
+                "direct-load staging: FP32 and split-BF16 NLL, 32 rows");
   using Sh = GroupShape<ROWS, PREC>;
   using T = typename PrecT<PREC>::T;
   using UT = typename PrecT<PREC>::UT;
@@ -874,7 +874,8 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (DMA ? 3 : (ROWS
     };
     // One pair's products. BF16X3: the fragments split into their two bfloat16
     // terms, three products per tile and the low-by-low product on the diagonal
-    // tiles (as in the register-staged pass). FP32: eight K = 4 products per tile,
+    // tiles (as in the register-staged pass). BF16X6: three terms, the six products
+    // whose term orders sum to at most two. FP32: eight K = 4 products per tile,
     // lane group kq holding columns 8 kq .. 8 kq + 7.
     auto pairmm = [&](f4v (&x)[NT][2], AccT (&ac)[NTT]) __attribute__((always_inline)) {
       if constexpr (PREC == 2) {
@@ -898,6 +899,35 @@ __global__ __launch_bounds__((64 * GroupShape<ROWS, PREC>::NW), (DMA ? 3 : (ROWS
           for (int tj = 0; tj <= ti; ++tj) {
             if (ti == tj)
               ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pt[ti][1], pt[tj][1], ac[t], 0, 0, 0);
+            ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pt[ti][1], pt[tj][0], ac[t], 0, 0, 0);
+            ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pt[ti][0], pt[tj][1], ac[t], 0, 0, 0);
+            ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pt[ti][0], pt[tj][0], ac[t], 0, 0, 0);
+            ++t;
+          }
+      } else if constexpr (PREC == 3) {
+        bf8v pt[NT][3];
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti) {
+          const bf4v a0 = bf16_term(x[ti][0]), b0 = bf16_term(x[ti][1]);
+          const bf4v a1 = bf16_term(x[ti][0]), b1 = bf16_term(x[ti][1]);
+          bf4v a2, b2;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            a2[c] = (__bf16)x[ti][0][c];
+            b2[c] = (__bf16)x[ti][1][c];
+          }
+          pt[ti][0] = __builtin_shufflevector(a0, b0, 0, 1, 2, 3, 4, 5, 6, 7);
+          pt[ti][1] = __builtin_shufflevector(a1, b1, 0, 1, 2, 3, 4, 5, 6, 7);
+          pt[ti][2] = __builtin_shufflevector(a2, b2, 0, 1, 2, 3, 4, 5, 6, 7);
+        }
+        int t = 0;
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+          for (int tj = 0; tj <= ti; ++tj) {
+            ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pt[ti][2], pt[tj][0], ac[t], 0, 0, 0);
+            ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pt[ti][1], pt[tj][1], ac[t], 0, 0, 0);
+            ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pt[ti][0], pt[tj][2], ac[t], 0, 0, 0);
             ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pt[ti][1], pt[tj][0], ac[t], 0, 0, 0);
             ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pt[ti][0], pt[tj][1], ac[t], 0, 0, 0);
             ac[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pt[ti][0], pt[tj][0], ac[t], 0, 0, 0);
@@ -1401,7 +1431,7 @@ hipError_t launch_group(const FactorArgs& a, int mode, hipStream_t s) {
   const int64_t ngrp =
       (PREC >= 2 && mode != 1) ? a.wrb * 8 / Sh::GP : (a.n + Sh::GP - 1) / Sh::GP;
   const unsigned grid = (unsigned)(((ngrp + 7) / 8) * 8);
-  if constexpr (ROWS == 32 && (PREC == 1 || PREC == 2)) {
+  if constexpr (ROWS == 32 && PREC >= 1) {
     if (mode != 1) {
       hipLaunchKernelGGL((vif_group_kernel<32, false, PREC, true>), dim3(grid), dim3(64 * Sh::NW), 0, s, a);
       return hipGetLastError();
