@@ -13,8 +13,8 @@ approximation"); the rows here are not the correlation-based ones, so that:
 * "random_wide": the same over more than 16384 points, so that a group's rows span
   an index range too wide for the union's bitmap (the sorting path).
 
-Bars as in test_gpu_parity: FP64 within 1e-8 relative, the split-BF16 modes within
-1e-5 relative.
+Bars as in test_gpu_parity: FP64 within 1e-8 relative, FP32 and the split-BF16 modes
+within 1e-5 relative.
 """
 import functools
 
@@ -27,7 +27,7 @@ from tests.gpu_util import dev, lib, log, problem_on_device, rel, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
-NLL_TOL = {"fp64": 1e-8, "bf16x3": 1e-5, "bf16x6": 1e-5}
+NLL_TOL = {"fp64": 1e-8, "fp32": 1e-5, "bf16x3": 1e-5, "bf16x6": 1e-5}
 
 
 def _rows(n, m, mode, seed):
@@ -59,7 +59,7 @@ def _case(mode):
 
 
 @pytest.mark.parametrize("mode", ["shared", "recent", "random", "random_wide"])
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
 def test_nll_with_extreme_unions(mode, prec):
     vif = lib()
     torch = torch_cuda()
@@ -91,4 +91,26 @@ def test_nll_at_the_row_bounds(m, mode, prec):
     nll = vif.vif_nll(*Xd, yd, d["kern"], d["m"], dev(nb, torch.int32), ind=Zd, prec=prec)
     err = rel(nll, o["nll"])
     log(f"[union] m={m} {mode} {prec} n={d['n']} gpu={nll:.12g} oracle={o['nll']:.12g} rel={err:.3e}")
+    assert err <= NLL_TOL[prec]
+
+
+@functools.lru_cache(maxsize=None)
+def _case_small_k(mode):
+    d = synth.config_small(seed=10, n_times=5, k=20, m=30, kind=1, n_stations=200)
+    nb = _rows(d["n"], d["m"], mode, seed=17)
+    o = LK.vif(d["kern"], (d["sx"], d["sy"], d["t"]), d["y"], nb, (d["zx"], d["zy"], d["zt"]))
+    return d, nb, o
+
+
+@pytest.mark.parametrize("mode", ["shared", "random"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
+def test_nll_with_one_chunk_rows(mode, prec):
+    """k = 20: rows of U padded to 64 columns, a single staged chunk (or two) per pass."""
+    vif = lib()
+    torch = torch_cuda()
+    d, nb, o = _case_small_k(mode)
+    Xd, yd, Zd = problem_on_device(d)
+    nll = vif.vif_nll(*Xd, yd, d["kern"], d["m"], dev(nb, torch.int32), ind=Zd, prec=prec)
+    err = rel(nll, o["nll"])
+    log(f"[union] k=20 {mode} {prec} n={d['n']} gpu={nll:.12g} oracle={o['nll']:.12g} rel={err:.3e}")
     assert err <= NLL_TOL[prec]
