@@ -48,19 +48,38 @@ __global__ void cov_kk_kernel(LowRankArgs A, double* __restrict__ S) {
 }
 
 // ---------------------------------------------------------------- Cholesky ---
+// Lane 4q + go's value to the four lanes 4q .. 4q + 3 (a DPP quad permutation;
+// go is a compile-time constant where it is called).
+__device__ __forceinline__ double quad_bcast(double x, int go) {
+  const long long b = __double_as_longlong(x);
+  int lo = (int)b, hi = (int)(b >> 32);
+  switch (go) {
+    case 0: lo = __builtin_amdgcn_update_dpp(lo, lo, 0x00, 0xF, 0xF, false);
+            hi = __builtin_amdgcn_update_dpp(hi, hi, 0x00, 0xF, 0xF, false); break;
+    case 1: lo = __builtin_amdgcn_update_dpp(lo, lo, 0x55, 0xF, 0xF, false);
+            hi = __builtin_amdgcn_update_dpp(hi, hi, 0x55, 0xF, 0xF, false); break;
+    case 2: lo = __builtin_amdgcn_update_dpp(lo, lo, 0xAA, 0xF, 0xF, false);
+            hi = __builtin_amdgcn_update_dpp(hi, hi, 0xAA, 0xF, 0xF, false); break;
+    default: lo = __builtin_amdgcn_update_dpp(lo, lo, 0xFF, 0xF, 0xF, false);
+             hi = __builtin_amdgcn_update_dpp(hi, hi, 0xFF, 0xF, 0xF, false); break;
+  }
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Solves T y = b (T lower triangular 64 x 64 in LDS, rd[r] = 1 / T[r][r] in LDS)
 // for 64 right-hand sides at once, all in registers: lanes 4s..4s+3 hold
 // right-hand side s, lane 4s + g holding entries g, g + 4, ..., g + 60 in v[].
-// Column r of the elimination is broadcast from its owner lane with a shuffle;
-// no barriers. Multiplying by the stored reciprocal keeps the division off the
-// serial chain of the 64 columns.
+// Column r of the elimination is broadcast from its owner lane within the quad
+// by a DPP move (no LDS round trip on the serial chain); no barriers.
+// Multiplying by the stored reciprocal keeps the division off the serial chain
+// of the 64 columns. Every lane of the wavefront takes part.
 __device__ __forceinline__ void tri_solve_regs(double v[16], const double (*T)[NB + 1],
-                                               const double* rd, int g, int lane) {
+                                               const double* rd, int g) {
 #pragma unroll
   for (int r = 0; r < NB; ++r) {
     const int go = r & 3, io = r >> 2;
     double y = v[io] * rd[r];
-    y = __shfl(y, (lane & ~3) | go);
+    y = quad_bcast(y, go);
     if (g == go) v[io] = y;
 #pragma unroll
     for (int i = io; i < 16; ++i) {
@@ -84,14 +103,15 @@ __device__ __forceinline__ void chol_panel_body(int N, double* __restrict__ A, i
                                                 double* __restrict__ dscr, const int w) {
   __shared__ double Ld[NB][NB + 1];
   __shared__ double rd[NB];
+  __shared__ __attribute__((aligned(16))) double sm[NB];
   __shared__ int bad;
   const int tid = threadIdx.x;
   const int64_t d0 = (int64_t)jb * NB;
-  const int lane = tid & 63, s = tid >> 2, g = tid & 3;
+  const int s = tid >> 2, g = tid & 3;
   // Right-looking factorisation of the diagonal block by wave 0 in registers:
-  // lane r holds row r; the pivot and each multiplier l_c are read from their
-  // owner lane with readlane (scalar registers), so there is no LDS traffic and
-  // no synchronisation until the factor is stored. Entries above the diagonal
+  // lane r holds row r; the pivot is read from its owner lane with readlane
+  // (scalar registers) and the multipliers l_c through LDS, with no
+  // synchronisation until the factor is stored. Entries above the diagonal
   // are never touched: the multiplier of rows r <= kk is zero. The multipliers
   // are a[kk] / sqrt(d) formed as a[kk] * rs with rs = 1 / sqrt(d) from the
   // hardware estimate and two Newton steps (rs += rs (1 - d rs^2) / 2), which
@@ -115,8 +135,16 @@ __device__ __forceinline__ void chol_panel_body(int N, double* __restrict__ A, i
       if (!okp && badl < 0) badl = kk;
       const double lm = r > kk ? a[kk] * rs : 0.0;
       if (r >= kk) a[kk] = r > kk ? lm : piv;
+      // The multipliers reach the other lanes through LDS, one broadcast read per
+      // two columns (a wavefront's LDS operations complete in issue order, so the
+      // reads see this step's writes and the next step's writes follow the reads).
+      sm[r] = lm;
 #pragma unroll
-      for (int c = kk + 1; c < NB; ++c) a[c] -= lm * readlane_f64(lm, c);
+      for (int c2 = (kk + 1) & ~1; c2 < NB; c2 += 2) {
+        const double2 p = *reinterpret_cast<const double2*>(&sm[c2]);
+        if (c2 >= kk + 1) a[c2] -= lm * p.x;
+        a[c2 + 1] -= lm * p.y;
+      }
       __builtin_amdgcn_sched_barrier(0);  // one column at a time (bounded scalar live ranges)
     }
 #pragma unroll
@@ -141,7 +169,7 @@ __device__ __forceinline__ void chol_panel_body(int N, double* __restrict__ A, i
   double v[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) v[i] = A[(r0 + s) * N + d0 + g + 4 * i];
-  tri_solve_regs(v, Ld, rd, g, lane);
+  tri_solve_regs(v, Ld, rd, g);
 #pragma unroll
   for (int i = 0; i < 16; ++i) A[(r0 + s) * N + d0 + g + 4 * i] = v[i];
 }
@@ -250,11 +278,11 @@ __global__ __launch_bounds__(256) void trinv_diag_kernel(int N, const double* __
   __syncthreads();
   if (tid < NB) rd[tid] = 1.0 / Ta[tid][tid];
   __syncthreads();
-  const int lane = tid & 63, sc = tid >> 2, g = tid & 3;
+  const int sc = tid >> 2, g = tid & 3;
   double v[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) v[i] = (g + 4 * i == sc) ? 1.0 : 0.0;
-  tri_solve_regs(v, Ta, rd, g, lane);
+  tri_solve_regs(v, Ta, rd, g);
 #pragma unroll
   for (int i = 0; i < 16; ++i) P[(r0 + g + 4 * i) * N + r0 + sc] = v[i];
 }
@@ -818,7 +846,6 @@ __global__ __launch_bounds__(256) void syrk_kernel(int64_t n, int kpad, const vo
 // runs the tiles of chunks x, x + 8, ... one chunk after the other, so that the
 // tiles sharing a chunk's rows run together and find them in that XCD's L2.
 constexpr int TB = 128;    // output tile
-constexpr int CHR = 4096;  // default rows per chunk (one FP32 accumulation)
 constexpr int SBK = 32;    // rows per step (the bf16 MFMA K)
 
 template <int NS>
