@@ -137,14 +137,17 @@ __device__ __forceinline__ void chol_panel_body(int N, double* __restrict__ A, i
       if (r >= kk) a[kk] = r > kk ? lm : piv;
       // The multipliers reach the other lanes through LDS, one broadcast read per
       // two columns (a wavefront's LDS operations complete in issue order, so the
-      // reads see this step's writes and the next step's writes follow the reads).
+      // reads see this step's writes and the next step's writes follow the reads;
+      // the wavefront-scope fences keep the compiler from reordering them).
       sm[r] = lm;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
       for (int c2 = (kk + 1) & ~1; c2 < NB; c2 += 2) {
         const double2 p = *reinterpret_cast<const double2*>(&sm[c2]);
         if (c2 >= kk + 1) a[c2] -= lm * p.x;
         a[c2 + 1] -= lm * p.y;
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_sched_barrier(0);  // one column at a time (bounded scalar live ranges)
     }
 #pragma unroll
