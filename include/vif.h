@@ -154,13 +154,16 @@ int32_t vif_nll_terms(const vif_points* p, const double* y, const vif_kernel* ke
                       double* terms, void* ws, size_t ws_bytes, void* hip_stream);
 
 /* vif_neighbors followed by vif_nll on its output, in one call: the neighbor
- * search (Alg. 2) runs on a library-owned non-blocking stream of hip_stream's
- * device (default priority) while hip_stream builds Sigma_k and U, and the
- * per-point stage waits for it. nbr (DEVICE int32 [n*m], written) and the NLL
- * are bit-identical to the two separate calls. Workspace:
- * vif_workspace_bytes(n, m, k, prec, VIF_OP_NEIGHBORS_NLL). Returns after both
- * streams have drained, also on error. Calls on one device from several host
- * threads run one at a time (they share that stream). */
+ * search (Alg. 2) runs on a library-owned stream of hip_stream's device (default
+ * priority, restricted to all but 32 of the device's compute units) while
+ * hip_stream builds Sigma_k, whose small launches take the CUs left free, and U;
+ * the per-point stage waits for the search. When hip_stream is the null stream,
+ * the NLL's work runs on a library-owned non-blocking stream ordered after the
+ * null stream's earlier work. nbr (DEVICE int32 [n*m], written) and the NLL are
+ * bit-identical to the two separate calls. Workspace:
+ * vif_workspace_bytes(n, m, k, prec, VIF_OP_NEIGHBORS_NLL). Returns after every
+ * stream it used has drained, also on error. Calls on one device from several
+ * host threads run one at a time (they share those streams). */
 int32_t vif_neighbors_nll(const vif_points* p, const double* y, const vif_kernel* kern, int32_t m,
                           int32_t* nbr, const vif_points* ind, int32_t prec, double* nll, void* ws,
                           size_t ws_bytes, void* hip_stream);

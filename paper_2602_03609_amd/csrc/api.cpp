@@ -511,12 +511,11 @@ int32_t nll_impl(const vif_points* p, const double* y, const vif_kernel* kern, i
       HIPCHK(vif::launch_lag_table(to_dev(kern), nlag, prec, ws + L.lag, s));
       fa.lagtab = ws + L.lag;
     }
-    // The side work (the neighbor search) starts after the chain of small Sigma_k
-    // kernels, whose launches would otherwise wait for its workgroups, and runs
-    // beside U.
+    // The side work (the neighbor search) starts first and runs beside the chain
+    // of small Sigma_k kernels, which use the CUs its stream leaves free, and U.
     const vif::LowRankArgs la = lowrank_args(p, ind, kern, L);
-    if ((st = run_sigma_k(la, ws, L, s))) return st;
     if (side && (st = side->start(s))) return st;
+    if ((st = run_sigma_k(la, ws, L, s))) return st;
     if ((st = run_u(la, prec, ws, L, s))) return st;
     if (side) HIPCHK(hipStreamWaitEvent(s, side->done, 0));
     fa.U = ws + L.U;
@@ -782,13 +781,18 @@ int32_t exact_grid(const vif_points* p, char* ws, const Layout& L, hipStream_t s
   return VIF_OK;
 }
 
-// One non-blocking stream at the default priority and two events per device, for
-// the neighbor search that vif_neighbors_nll runs beside the low-rank stages. The
-// lock serialises such calls on one device, which share the stream and events.
+// Per device, for vif_neighbors_nll: the stream of the neighbor search, which runs
+// beside the Sigma_k chain and U (default priority, restricted to all but
+// kSearchFreeCUs compute units, so that the chain's small launches find free CUs
+// while the search fills the rest); a non-blocking stream that takes the NLL's
+// work when the caller passes the null stream (a stream with a CU mask is a
+// blocking stream, which null-stream work would otherwise serialise with); and
+// three events. The lock serialises such calls on one device, which share them.
+constexpr int kSearchFreeCUs = 32;
 struct SideStream {
   std::mutex mu;
-  hipStream_t s = nullptr;
-  hipEvent_t fork = nullptr, done = nullptr;
+  hipStream_t s = nullptr, main = nullptr;
+  hipEvent_t fork = nullptr, done = nullptr, enter = nullptr;
 };
 
 constexpr int kMaxDevices = 64;
@@ -812,21 +816,39 @@ int32_t side_stream(hipStream_t main, SideStream** out) {
     int cur = 0;
     HIPCHK(hipGetDevice(&cur));
     if (cur != dev) HIPCHK(hipSetDevice(dev));
-    hipStream_t st = nullptr;
-    hipEvent_t a = nullptr, b = nullptr;
-    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    hipStream_t st = nullptr, sm = nullptr;
+    hipEvent_t a = nullptr, b = nullptr, c = nullptr;
+    int ncu = 0;
+    hipError_t e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess && ncu > 2 * kSearchFreeCUs) {
+      uint32_t mask[(4096 + 31) / 32] = {};
+      const int used = (ncu < 4096 ? ncu : 4096) - kSearchFreeCUs;
+      for (int cu = 0; cu < used; ++cu) mask[cu >> 5] |= 1u << (cu & 31);
+      if (hipExtStreamCreateWithCUMask(&st, (uint32_t)((used + kSearchFreeCUs + 31) / 32), mask) !=
+          hipSuccess) {
+        (void)hipGetLastError();  // fall back to a stream on every CU
+        st = nullptr;
+      }
+    }
+    if (e == hipSuccess && !st) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&sm, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&a, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c, hipEventDisableTiming);
     if (e != hipSuccess) {
+      if (c) (void)hipEventDestroy(c);
       if (b) (void)hipEventDestroy(b);
       if (a) (void)hipEventDestroy(a);
+      if (sm) (void)hipStreamDestroy(sm);
       if (st) (void)hipStreamDestroy(st);
     }
     if (cur != dev) HIPCHK(hipSetDevice(cur));
     if (e != hipSuccess) return fail(VIF_E_DEVICE, "side stream set-up: %s", hipGetErrorString(e));
     ss->s = st;
+    ss->main = sm;
     ss->fork = a;
     ss->done = b;
+    ss->enter = c;
   }
   *out = ss;
   return VIF_OK;
@@ -911,6 +933,13 @@ int32_t vif_neighbors_nll(const vif_points* p, const double* y, const vif_kernel
   SideStream* ss = nullptr;
   if ((st = side_stream(s, &ss))) return st;
   std::lock_guard<std::mutex> lock(ss->mu);
+  if (!s) {
+    // null stream: the work runs on the library's non-blocking stream, after what
+    // the caller enqueued before (the call returns with both streams drained)
+    HIPCHK(hipEventRecord(ss->enter, nullptr));
+    HIPCHK(hipStreamWaitEvent(ss->main, ss->enter, 0));
+    s = ss->main;
+  }
   SearchSetup S;
   if ((st = search_setup(p, kern, m, nbr, ws, Ln, s, &S))) return st;
   SideWork side;
@@ -927,8 +956,7 @@ int32_t vif_neighbors_nll(const vif_points* p, const double* y, const vif_kernel
     HIPCHK(hipEventRecord(ss->done, ss->s));
     return VIF_OK;
   };
-  st = nll_impl(p, y, kern, m, nbr, ind, prec, nll, nullptr, ws + off, ws_bytes - off, hip_stream,
-                &side);
+  st = nll_impl(p, y, kern, m, nbr, ind, prec, nll, nullptr, ws + off, ws_bytes - off, s, &side);
   // The search's host tables and the workspace are in use until both streams drain,
   // also when the NLL stopped early with an error.
   const hipError_t e_side = hipStreamSynchronize(ss->s);

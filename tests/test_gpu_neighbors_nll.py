@@ -84,7 +84,9 @@ def test_errors_on_either_stream_then_recovery():
 
 
 def test_on_a_side_torch_stream():
-    """Caller's stream other than the default one: results unchanged."""
+    """Caller's stream other than the default one (the library's streams fork from
+    and join it; on the null stream the NLL's work runs on a library stream):
+    results unchanged."""
     torch = torch_cuda()
     vif = lib()
     d = synth.config_small(**CASES["gneit_k40_m12"])
